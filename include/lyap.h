@@ -1,0 +1,180 @@
+/*
+ * lyap.h -- C ABI of the MI355X (gfx950) low-rank Lyapunov solver.
+ *
+ * Solves A X + X A^T + W = 0 with A Hurwitz and W = L L^T or W = L S L^T (S diagonal,
+ * possibly indefinite) by the factored, scaled sign-function Newton iteration
+ * (Section 3, eq (3.2)/(3.3), Alg 3.1/3.2) wrapped in mixed-precision iterative
+ * refinement (Section 2, Alg 2.1/2.2, Fragments 2.1-2.4), returning X ~ Z diag(D) Z^T.
+ *
+ * Conventions shared by every entry point
+ *  - Matrices are row-major (C order): element (i, j) of a matrix with leading dimension
+ *    ld lives at ptr[i * ld + j].
+ *  - Every matrix/vector pointer is a DEVICE pointer (hipMalloc'd or a torch CUDA tensor)
+ *    unless stated otherwise; info structs are HOST pointers.
+ *  - ``stream`` is a hipStream_t passed as void* (NULL = the default stream).  Every call
+ *    is stream-ordered and returns after its results are valid (host-synchronous), since
+ *    ranks and stopping decisions are taken on the host from a few device scalars.
+ *  - Ownership: the caller owns all input and output buffers; the library never frees or
+ *    keeps caller memory.  The handle owns a device workspace (grown on demand with
+ *    hipMalloc, released by lyap_destroy) and the cached sequence of inverses.
+ *  - Errors: every entry point returns an int status (LYAP_OK = 0 or one of the codes
+ *    below); nothing throws across the ABI.  On error the outputs are unspecified unless
+ *    the code's description says otherwise.
+ *  - Thread safety: a handle must not be used by two host threads at once.
+ */
+#ifndef LYAP_H
+#define LYAP_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+enum {
+  LYAP_OK = 0,
+  LYAP_NOT_CONVERGED = 1, /* i_max refinements done; outputs hold the last iterate       */
+  LYAP_STAGNATED = 2,     /* res_i/res_{i-1} > theta twice in a row (eq 4.2); outputs valid */
+  LYAP_NONFINITE = 3,     /* an inverse or iterate overflowed at the solver precision       */
+  LYAP_SINGULAR = 4,      /* an exact zero pivot in an inversion                            */
+  LYAP_NOT_STABLE = 5,    /* A-iteration did not converge to -I (A not Hurwitz) in k_max    */
+  LYAP_CAPACITY = 6,      /* the factor needs more than z_cap columns; *rank = needed       */
+  LYAP_BADARG = 7,        /* invalid size, pointer, precision order or option               */
+  LYAP_HIP_ERROR = 8,     /* a HIP runtime call failed                                      */
+  LYAP_NO_MEMORY = 9      /* workspace allocation failed                                    */
+};
+
+/* Arithmetic formats of Table 1.1.  Order of "precision" (larger unit roundoff first):
+ * BF16 > F16 > F32 > F64. */
+typedef enum { LYAP_F64 = 0, LYAP_F32 = 1, LYAP_F16 = 2, LYAP_BF16 = 3 } lyap_dtype;
+
+/* Precisions of Alg 2.1/2.2: solver u_s, working u, residual factorisation u_r and solution
+ * update u_c, with u_s >= u >= u_r, u_c.  This build supports u = u_r = u_c = F64 and any
+ * u_s (F64 gives the plain FP64 sign-function Newton solve). */
+typedef struct {
+  int u_s, u, u_r, u_c; /* lyap_dtype values */
+} lyap_precisions;
+
+/* Options; lyap_default_options fills in the paper's Section 4.1 values. */
+typedef struct {
+  double tol;        /* tau_I on the relative residual of eq (4.1); default 1e-13        */
+  int i_max;         /* refinement steps; default 50                                      */
+  int k_max;         /* Newton steps per solver call; default 50                          */
+  double rho;        /* in-solver truncation when columns exceed floor(rho n); 0.1        */
+  double eta_r;      /* residual truncation, relative to max|lambda|; 1e-4               */
+  double eta_s;      /* solution truncation, relative to max|sigma|; <= 0 means 10 u     */
+  double delta_off;  /* Frobenius scaling switched off once delta_k < delta_off; 1e-2     */
+  double theta;      /* stagnation ratio of eq (4.2); 0.9                                 */
+  int refine;        /* 1: iterative refinement (Alg 2.2); 0: one solve + residual check  */
+  int psd;           /* -1 auto (S == NULL or S >= 0), 0 off, 1 on: PSD projection        */
+} lyap_options;
+
+/* Per-solve diagnostics (Table 4.1 columns plus timings). */
+typedef struct {
+  int status;             /* same as the return code                                     */
+  double res;             /* relative residual (eq 4.1) of the returned factors          */
+  int n_res;              /* entries used in res_hist                                    */
+  double res_hist[64];    /* res_i per refinement step                                   */
+  int newton_total;       /* varsigma: Newton steps over all solver calls                */
+  int newton_max;         /* alpha: largest number of Newton steps in one call           */
+  int inversions;         /* inverses actually computed (the cached sequence length K)   */
+  int refinements;        /* correction solves performed                                 */
+  int rank;               /* columns of the returned Z                                   */
+  int n_mu;               /* entries used in mus                                         */
+  double mus[64];         /* Frobenius scalings mu_0 .. mu_{K-1}                         */
+  double onenorm[64];     /* ||A_k + I||_1 after each Newton step                        */
+  double phase_ms[8];     /* 0 inversions, 1 Newton update+norms, 2 factor products,
+                             3 in-solver truncation, 4 residual factorisation,
+                             5 solution update, 6 other, 7 total                          */
+} lyap_info;
+
+typedef struct lyap_handle_s* lyap_handle;
+
+/* Create a handle bound to HIP device ``device`` (the device must be current in the
+ * calling thread for every later call).  *h receives the handle. */
+int lyap_create(lyap_handle* h, int device);
+/* Destroy a handle and free its workspace.  NULL is accepted. */
+int lyap_destroy(lyap_handle h);
+/* Section 4.1 defaults: tol 1e-13, i_max 50, k_max 50, rho 0.1, eta_r 1e-4, eta_s 10u,
+ * delta_off 1e-2, theta 0.9, refine 1, psd -1. */
+void lyap_default_options(lyap_options* opt);
+/* Human-readable text of a status code (static string). */
+const char* lyap_strerror(int code);
+/* Library version string and the GPU architecture it was built for. */
+const char* lyap_version(void);
+
+/*
+ * lyap_solve -- Alg 2.2 (LDL^T-type mixed-precision IR) with Alg 3.2 as the solver.
+ *
+ *  n, m      order of A and number of columns of L (1 <= m <= n).
+ *  A         n x n FP64, row-major, leading dimension lda >= n; A must be Hurwitz.
+ *  L         n x m FP64, row-major, ldl >= m.
+ *  S         m FP64 values: the diagonal of S (W = L diag(S) L^T), or NULL for W = L L^T.
+ *  prec      precisions {u_s, u, u_r, u_c}; u, u_r, u_c must be LYAP_F64.
+ *  opt       options or NULL for the defaults.
+ *  Z         n x z_cap FP64 output, row-major, ldz >= z_cap; columns 0..rank-1 receive
+ *            orthonormal factor columns.
+ *  D         z_cap FP64 output: the diagonal of D (X ~ Z diag(D) Z^T).  For a Cholesky-type
+ *            equation (S == NULL) D > 0 and Z diag(sqrt D) is a Cholesky-type factor.
+ *  rank      host int: the number of columns written.
+ *  info      host lyap_info or NULL.
+ * Returns LYAP_OK when res <= tol.  LYAP_NOT_CONVERGED / LYAP_STAGNATED still write the
+ * last iterate.  With opt->refine == 0 the call runs the plain sign-function Newton solve
+ * at u_s and one residual evaluation (the FP64 baseline when u_s = LYAP_F64).
+ */
+int lyap_solve(lyap_handle h, void* stream, int n, int m, const double* A, int lda,
+               const double* L, int ldl, const double* S, lyap_precisions prec,
+               const lyap_options* opt, double* Z, int ldz, int z_cap, double* D, int* rank,
+               lyap_info* info);
+
+/* ---------------------------------------------------------------------------------
+ * Component entry points.  Each runs one hot-path kernel family on the handle's stream
+ * ordering; they exist so that each step of the path can be checked on its own.
+ * ------------------------------------------------------------------------------ */
+
+/*
+ * lyap_inverse -- inverse of the n x n FP64 matrix A (row-major, lda) at solver precision
+ * ``dtype`` (the inversion of Alg 3.1/3.2, first line of the loop): Gauss-Jordan
+ * elimination with partial pivoting (ties to the lowest row index).  For F32/F16/BF16 the
+ * matrix is held in binary32, scaled by a power of two, and every block-update product
+ * takes its operands rounded to ``dtype`` with binary32 accumulation.  The result is
+ * written in FP64 to Ainv (row-major, ldi).  Returns LYAP_SINGULAR on an exact zero pivot.
+ */
+int lyap_inverse(lyap_handle h, void* stream, int dtype, int n, const double* A, int lda,
+                 double* Ainv, int ldi);
+
+/*
+ * lyap_gemm -- C = alpha * op(A) * op(B) + beta * C in FP64 on the FP64 matrix cores, or
+ * with operands rounded to ``dtype`` (F32/F16/BF16) and binary32 accumulation.  op(X) is
+ * X or X^T (transa/transb = 0/1).  All matrices FP64 row-major.  op(A) is M x K, op(B) is
+ * K x N, C is M x N.
+ */
+int lyap_gemm(lyap_handle h, void* stream, int dtype, int transa, int transb, int M, int N,
+              int K, double alpha, const double* A, int lda, const double* B, int ldb,
+              double beta, double* C, int ldc);
+
+/*
+ * lyap_qr -- thin QR F = U T of the n x p FP64 matrix F (n >= p), as used by the residual
+ * factorisation and solution update (Fragments 2.1-2.4) and RankTruncLdlt (Alg 3.2):
+ * block Gram-Schmidt with re-orthogonalisation over panels factored by a Householder
+ * tall-skinny QR.  U is n x p (row-major, ldu), T is p x p upper triangular (row-major,
+ * ldt).  F is not modified.
+ */
+int lyap_qr(lyap_handle h, void* stream, int n, int p, const double* F, int ldf, double* U,
+            int ldu, double* T, int ldt);
+
+/*
+ * lyap_syev -- spectral decomposition H = V diag(w) V^T of the symmetric p x p FP64 matrix
+ * H (row-major, ldh; only its symmetric part is used), as needed by Fragments 2.1-2.4 and
+ * the in-solver truncation: cyclic block Jacobi.  w (p) receives the eigenvalues in
+ * descending order of magnitude; V (p x p, row-major, ldv) the orthonormal eigenvectors as
+ * columns.  H is not modified.
+ */
+int lyap_syev(lyap_handle h, void* stream, int p, const double* H, int ldh, double* w,
+              double* V, int ldv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LYAP_H */
