@@ -1,0 +1,145 @@
+"""MI355X (gfx950) solver for low-rank Lyapunov equations A X + X A^T + W = 0.
+
+Python entry points over the C ABI of liblyap.so (include/lyap.h).  Tensors must be CUDA
+(HIP) float64 tensors on the same device; they are passed by pointer together with the
+current stream.  All arithmetic runs in the library's HIP kernels.
+
+    solve(A, L, S=None, precisions=("fp16", "fp64", "fp64", "fp64"), tol=1e-13, ...)
+        -> (Z, D, info) with X ~ Z diag(D) Z^T     (Alg 2.2 with Alg 3.2 as the solver)
+    inverse(A, dtype)        -- inversion at a solver precision (Gauss-Jordan, pivoting)
+    gemm(A, B, ...)          -- matrix-core product
+    qr(F) -> (U, T)          -- thin QR of a tall matrix
+    syev(H) -> (w, V)        -- symmetric spectral decomposition
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import DTYPES, Info, LyapError, Options, Precisions
+
+__all__ = ["solve", "inverse", "gemm", "qr", "syev", "LyapError", "version"]
+
+
+def _dev(*ts):
+    dev = None
+    for t in ts:
+        if t is None:
+            continue
+        if not t.is_cuda:
+            raise ValueError("tensors must be on a GPU device")
+        if t.dtype != torch.float64:
+            raise ValueError("tensors must be float64")
+        if dev is None:
+            dev = t.device.index if t.device.index is not None else torch.cuda.current_device()
+    return dev
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _rowmajor(t):
+    """(tensor, leading dimension) for a row-major view with unit column stride."""
+    if t.stride(1) != 1 or t.stride(0) < t.shape[1]:
+        t = t.contiguous()
+    return t, t.stride(0)
+
+
+def version() -> str:
+    return _lib.lib().lyap_version().decode()
+
+
+def inverse(A: torch.Tensor, dtype: str = "fp64") -> torch.Tensor:
+    dev = _dev(A)
+    n = A.shape[0]
+    A, lda = _rowmajor(A)
+    out = torch.empty((n, n), dtype=torch.float64, device=A.device)
+    code = _lib.lib().lyap_inverse(_lib.handle(dev), _stream(dev), DTYPES[dtype], n, _ptr(A), lda,
+                                   _ptr(out), n)
+    _lib.check(code, "lyap_inverse")
+    return out
+
+
+def gemm(A, B, C=None, alpha=1.0, beta=0.0, transa=False, transb=False, dtype="fp64"):
+    dev = _dev(A, B, C)
+    A, lda = _rowmajor(A)
+    B, ldb = _rowmajor(B)
+    M = A.shape[1] if transa else A.shape[0]
+    K = A.shape[0] if transa else A.shape[1]
+    N = B.shape[0] if transb else B.shape[1]
+    if C is None:
+        C = torch.zeros((M, N), dtype=torch.float64, device=A.device)
+        beta = 0.0
+    if C.stride(1) != 1:
+        raise ValueError("C must have unit column stride")
+    code = _lib.lib().lyap_gemm(_lib.handle(dev), _stream(dev), DTYPES[dtype], int(transa),
+                                int(transb), M, N, K, float(alpha), _ptr(A), lda, _ptr(B), ldb,
+                                float(beta), _ptr(C), C.stride(0))
+    _lib.check(code, "lyap_gemm")
+    return C
+
+
+def qr(F: torch.Tensor):
+    dev = _dev(F)
+    F, ldf = _rowmajor(F)
+    n, p = F.shape
+    k = min(n, p)
+    U = torch.empty((n, k), dtype=torch.float64, device=F.device)
+    T = torch.empty((k, p), dtype=torch.float64, device=F.device)
+    code = _lib.lib().lyap_qr(_lib.handle(dev), _stream(dev), n, p, _ptr(F), ldf, _ptr(U), k,
+                              _ptr(T), p)
+    _lib.check(code, "lyap_qr")
+    return U, T
+
+
+def syev(H: torch.Tensor):
+    dev = _dev(H)
+    H, ldh = _rowmajor(H)
+    p = H.shape[0]
+    w = torch.empty(p, dtype=torch.float64, device=H.device)
+    V = torch.empty((p, p), dtype=torch.float64, device=H.device)
+    code = _lib.lib().lyap_syev(_lib.handle(dev), _stream(dev), p, _ptr(H), ldh, _ptr(w),
+                                _ptr(V), p)
+    _lib.check(code, "lyap_syev")
+    return w, V
+
+
+def solve(A, L, S=None, precisions=("fp16", "fp64", "fp64", "fp64"), tol=1e-13, refine=True,
+          z_cap=None, raise_on_error=True, **opts):
+    """Alg 2.2 (LDL^T-type mixed-precision IR) on the GPU.  Returns (Z, D, info)."""
+    dev = _dev(A, L, S)
+    n = A.shape[0]
+    m = L.shape[1]
+    A, lda = _rowmajor(A)
+    L, ldl = _rowmajor(L)
+    if S is not None:
+        S = S.contiguous()
+    if z_cap is None:
+        z_cap = n  # the rank of X never exceeds n
+    Z = torch.zeros((n, z_cap), dtype=torch.float64, device=A.device)
+    Dv = torch.zeros(z_cap, dtype=torch.float64, device=A.device)
+    o = _lib.default_options()
+    o.tol = tol
+    o.refine = int(bool(refine))
+    for k, v in opts.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown option {k}")
+        setattr(o, k, v)
+    prec = Precisions(*[DTYPES[p] for p in precisions])
+    rank = ctypes.c_int(0)
+    info = Info()
+    code = _lib.lib().lyap_solve(_lib.handle(dev), _stream(dev), n, m, _ptr(A), lda, _ptr(L), ldl,
+                                 _ptr(S), prec, ctypes.byref(o), _ptr(Z), z_cap, z_cap, _ptr(Dv),
+                                 ctypes.byref(rank), ctypes.byref(info))
+    d = info.as_dict()
+    if code != 0 and raise_on_error and code not in (1, 2):
+        _lib.check(code, "lyap_solve")
+    r = rank.value
+    return Z[:, :r], Dv[:r], d

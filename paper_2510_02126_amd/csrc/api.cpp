@@ -1,0 +1,213 @@
+// C ABI of the solver library (declared in include/lyap.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+
+#include "common.hpp"
+#include "internal.hpp"
+#include "solver.hpp"
+
+using namespace lyap;
+
+namespace lyap {
+
+int Arena::reserve(size_t bytes) {
+  if (bytes <= cap) return LYAP_OK;
+  release();
+  size_t want = align_up(bytes, (size_t)1 << 20);
+  if (hipMalloc(&base, want) != hipSuccess) {
+    base = nullptr;
+    return LYAP_NO_MEMORY;
+  }
+  cap = want;
+  top = 0;
+  return LYAP_OK;
+}
+
+void Arena::release() {
+  if (base) (void)hipFree(base);
+  base = nullptr;
+  cap = 0;
+  top = 0;
+}
+
+}  // namespace lyap
+
+struct lyap_handle_s {
+  int device = 0;
+  Arena ws;          // per-call scratch
+  Solver solver;     // owns the cached inverse sequence and persistent buffers
+  int* flags = nullptr;  // device status flags
+};
+
+static bool valid_dtype(int d) { return d >= LYAP_F64 && d <= LYAP_BF16; }
+
+extern "C" {
+
+const char* lyap_strerror(int code) {
+  switch (code) {
+    case LYAP_OK: return "ok";
+    case LYAP_NOT_CONVERGED: return "refinement did not reach the tolerance within i_max steps";
+    case LYAP_STAGNATED: return "refinement stagnated (residual ratio above theta twice)";
+    case LYAP_NONFINITE: return "non-finite value at the solver precision";
+    case LYAP_SINGULAR: return "exact zero pivot in an inversion";
+    case LYAP_NOT_STABLE: return "Newton iteration did not converge to -I (A not Hurwitz?)";
+    case LYAP_CAPACITY: return "factor needs more columns than z_cap";
+    case LYAP_BADARG: return "invalid argument";
+    case LYAP_HIP_ERROR: return "HIP runtime error";
+    case LYAP_NO_MEMORY: return "device memory allocation failed";
+    default: return "unknown status";
+  }
+}
+
+const char* lyap_version(void) { return "lyap-mi355x 0.1 (gfx950)"; }
+
+void lyap_default_options(lyap_options* o) {
+  if (!o) return;
+  o->tol = 1e-13;
+  o->i_max = 50;
+  o->k_max = 50;
+  o->rho = 0.1;
+  o->eta_r = 1e-4;
+  o->eta_s = 0.0;
+  o->delta_off = 1e-2;
+  o->theta = 0.9;
+  o->refine = 1;
+  o->psd = -1;
+}
+
+int lyap_create(lyap_handle* h, int device) {
+  if (!h) return LYAP_BADARG;
+  *h = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
+    return LYAP_HIP_ERROR;
+  if (hipSetDevice(device) != hipSuccess) return LYAP_HIP_ERROR;
+  lyap_handle_s* p = new (std::nothrow) lyap_handle_s();
+  if (!p) return LYAP_NO_MEMORY;
+  p->device = device;
+  if (hipMalloc(&p->flags, 16 * sizeof(int)) != hipSuccess) {
+    delete p;
+    return LYAP_NO_MEMORY;
+  }
+  *h = p;
+  return LYAP_OK;
+}
+
+int lyap_destroy(lyap_handle h) {
+  if (!h) return LYAP_OK;
+  (void)hipDeviceSynchronize();
+  h->solver.release();
+  h->ws.release();
+  if (h->flags) (void)hipFree(h->flags);
+  delete h;
+  return LYAP_OK;
+}
+
+int lyap_inverse(lyap_handle h, void* stream, int dtype, int n, const double* A, int lda,
+                 double* Ainv, int ldi) {
+  if (!h || !valid_dtype(dtype) || n < 0 || (n > 0 && (!A || !Ainv || lda < n || ldi < n)))
+    return LYAP_BADARG;
+  if (n == 0) return LYAP_OK;
+  if (n > 4096) return LYAP_BADARG;
+  hipStream_t s = (hipStream_t)stream;
+  LYAP_TRY(h->ws.reserve(inverse_workspace_bytes((Prec)dtype, n) + (1 << 20)));
+  h->ws.reset();
+  LYAP_TRY(fill_int(s, h->flags, 2, 0));
+  LYAP_TRY(invert(s, (Prec)dtype, n, A, lda, Ainv, ldi, h->ws, h->flags));
+  int f[2] = {0, 0};
+  LYAP_HIP(hipMemcpyAsync(f, h->flags, sizeof(f), hipMemcpyDeviceToHost, s));
+  LYAP_HIP(hipStreamSynchronize(s));
+  if (f[0]) return LYAP_SINGULAR;
+  if (f[1]) return LYAP_NONFINITE;
+  return LYAP_OK;
+}
+
+int lyap_gemm(lyap_handle h, void* stream, int dtype, int transa, int transb, int M, int N, int K,
+              double alpha, const double* A, int lda, const double* B, int ldb, double beta,
+              double* C, int ldc) {
+  if (!h || !valid_dtype(dtype) || M < 0 || N < 0 || K < 0) return LYAP_BADARG;
+  if (M == 0 || N == 0) return LYAP_OK;
+  if (!C || ldc < N || (K > 0 && (!A || !B))) return LYAP_BADARG;
+  if (K > 0) {
+    if (lda < (transa ? M : K) || ldb < (transb ? K : N)) return LYAP_BADARG;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  GemmDesc g;
+  g.M = M; g.N = N; g.K = K;
+  g.alpha = alpha; g.beta = beta;
+  g.A = A;
+  if (!transa) { g.sar = lda; g.sac = 1; } else { g.sar = 1; g.sac = lda; }
+  g.B = B;
+  if (!transb) { g.sbr = ldb; g.sbc = 1; } else { g.sbr = 1; g.sbc = ldb; }
+  g.C = C; g.ldc = ldc;
+  if (dtype == LYAP_F64) {
+    size_t ws_elems = (size_t)64 * M * N;
+    ws_elems = std::min(ws_elems, (size_t)1 << 26);
+    LYAP_TRY(h->ws.reserve(ws_elems * sizeof(double) + (1 << 20)));
+    h->ws.reset();
+    double* part = h->ws.take<double>(ws_elems);
+    LYAP_TRY(gemm_f64(s, g, part, ws_elems));
+  } else {
+    LYAP_TRY(gemm_lp(s, (Prec)dtype, Store::F64, Store::F64, Store::F64, g));
+  }
+  LYAP_HIP(hipStreamSynchronize(s));
+  return LYAP_OK;
+}
+
+int lyap_qr(lyap_handle h, void* stream, int n, int p, const double* F, int ldf, double* U,
+            int ldu, double* T, int ldt) {
+  const int k = n < p ? n : p;
+  if (!h || n < 0 || p < 0 || n > 4096 ||
+      (p > 0 && (!F || !U || !T || ldf < p || ldu < k || ldt < p)))
+    return LYAP_BADARG;
+  if (p == 0) return LYAP_OK;
+  hipStream_t s = (hipStream_t)stream;
+  LYAP_TRY(h->ws.reserve(qr_workspace_bytes(n, p) + (1 << 20)));
+  h->ws.reset();
+  LYAP_TRY(qr(s, n, p, F, ldf, U, ldu, T, ldt, h->ws));
+  LYAP_HIP(hipStreamSynchronize(s));
+  return LYAP_OK;
+}
+
+int lyap_syev(lyap_handle h, void* stream, int p, const double* H, int ldh, double* w, double* V,
+              int ldv) {
+  if (!h || p < 0 || (p > 0 && (!H || !w || !V || ldh < p || ldv < p))) return LYAP_BADARG;
+  if (p == 0) return LYAP_OK;
+  hipStream_t s = (hipStream_t)stream;
+  LYAP_TRY(h->ws.reserve(syev_workspace_bytes(p) + (1 << 20)));
+  h->ws.reset();
+  LYAP_TRY(syev(s, p, H, ldh, w, V, ldv, h->ws, 0.0, nullptr));
+  LYAP_HIP(hipStreamSynchronize(s));
+  return LYAP_OK;
+}
+
+int lyap_solve(lyap_handle h, void* stream, int n, int m, const double* A, int lda,
+               const double* L, int ldl, const double* S, lyap_precisions prec,
+               const lyap_options* opt, double* Z, int ldz, int z_cap, double* D, int* rank,
+               lyap_info* info) {
+  if (!h || n <= 0 || m <= 0 || m > n || !A || !L || !Z || !D || !rank || lda < n || ldl < m ||
+      z_cap < 1 || ldz < z_cap)
+    return LYAP_BADARG;
+  if (!valid_dtype(prec.u_s) || prec.u != LYAP_F64 || prec.u_r != LYAP_F64 ||
+      prec.u_c != LYAP_F64)
+    return LYAP_BADARG;
+  if (n > 4096) return LYAP_BADARG;
+  lyap_options o;
+  if (opt) o = *opt;
+  else lyap_default_options(&o);
+  if (!(o.tol >= 0) || o.i_max < 0 || o.i_max > 63 || o.k_max < 1 || o.k_max > 64 ||
+      !(o.rho > 0) || !(o.eta_r >= 0) || !(o.theta > 0))
+    return LYAP_BADARG;
+  lyap_info local;
+  lyap_info* inf = info ? info : &local;
+  std::memset(inf, 0, sizeof(*inf));
+  int code = h->solver.solve((hipStream_t)stream, h->ws, h->flags, n, m, A, lda, L, ldl, S,
+                             (Prec)prec.u_s, o, Z, ldz, z_cap, D, rank, inf);
+  inf->status = code;
+  return code;
+}
+
+}  // extern "C"

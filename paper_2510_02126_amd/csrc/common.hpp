@@ -1,0 +1,96 @@
+// Shared definitions for the gfx950 Lyapunov solver library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_bf16.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/lyap.h"
+
+namespace lyap {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// Operand formats of the matrix-core products.
+enum class Prec : int { F64 = LYAP_F64, F32 = LYAP_F32, F16 = LYAP_F16, BF16 = LYAP_BF16 };
+
+inline double unit_roundoff(Prec p) {
+  switch (p) {
+    case Prec::F64: return 1.1102230246251565e-16;   // 2^-53
+    case Prec::F32: return 5.960464477539063e-08;    // 2^-24
+    case Prec::F16: return 4.8828125e-04;            // 2^-11
+    case Prec::BF16: return 3.90625e-03;             // 2^-8
+  }
+  return 0.0;
+}
+
+// Status propagated out of the internal routines.
+struct Status {
+  int code = LYAP_OK;
+  bool ok() const { return code == LYAP_OK; }
+};
+
+#define LYAP_HIP(expr)                                   \
+  do {                                                   \
+    hipError_t _e = (expr);                              \
+    if (_e != hipSuccess) return LYAP_HIP_ERROR;         \
+  } while (0)
+
+#define LYAP_TRY(expr)                                   \
+  do {                                                   \
+    int _c = (expr);                                     \
+    if (_c != LYAP_OK) return _c;                        \
+  } while (0)
+
+inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Device workspace owned by a handle: one bump allocator over a growable hipMalloc block.
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0;
+  size_t top = 0;
+  int reserve(size_t bytes);          // ensure capacity (frees old block; call when empty)
+  void reset() { top = 0; }
+  template <class T>
+  T* take(size_t count) {
+    size_t off = align_up(top, 256);
+    size_t need = off + align_up(count * sizeof(T), 256);
+    if (need > cap) return nullptr;
+    top = need;
+    return reinterpret_cast<T*>(base + off);
+  }
+  void release();
+};
+
+// ------------------------------------------------------------------ launchers
+// Generic strided product C = alpha * opA * opB + beta * C, opA(i,k) = A[i*sar + k*sac],
+// opB(k,j) = B[k*sbr + j*sbc], C row-major (ldc).  Operand storage types are given by
+// the template instantiations in gemm.hip.
+struct GemmDesc {
+  int M = 0, N = 0, K = 0;
+  double alpha = 1.0, beta = 0.0;
+  const void* A = nullptr;
+  long sar = 0, sac = 0;
+  const void* B = nullptr;
+  long sbr = 0, sbc = 0;
+  void* C = nullptr;
+  long ldc = 0;
+};
+
+// Storage type codes for operands/results.
+enum class Store : int { F64 = 0, F32 = 1, F16 = 2, BF16 = 3 };
+
+// Product with FP64 matrix cores (all storage F64).
+int gemm_f64(hipStream_t s, const GemmDesc& d, double* splitk_ws = nullptr, size_t ws_elems = 0);
+// Product with operands rounded to ``op`` (F32/F16/BF16), binary32 accumulation.  A and B
+// stored as ``sa``/``sb``, C stored as ``sc`` (F32 or F64).
+int gemm_lp(hipStream_t s, Prec op, Store sa, Store sb, Store sc, const GemmDesc& d);
+
+}  // namespace lyap

@@ -1,0 +1,343 @@
+// Matrix-core products for gfx950.
+//
+// Two kernel families:
+//  * gemm_k4   -- 16x16x4 MFMA with one operand element per lane (FP64: v_mfma_f64_16x16x4f64,
+//                 binary32: v_mfma_f32_16x16x4f32).  Block tile 64x64, k-tile 16, 4 waves in
+//                 a 2x2 grid, each wave 32x32 (2x2 MFMA tiles).
+//  * gemm_k32  -- 16x16x32 MFMA with eight operand elements per lane (fp16 / bf16 operands,
+//                 binary32 accumulation).  Block tile 64x64, k-tile 32.
+// Operands are read through generic strides so that transposed views need no copies; the
+// loader picks a coalesced thread mapping from whichever stride is unit.  Ragged M, N, K are
+// zero-padded in LDS.  FP64 products can split K across blocks, with a deterministic
+// second pass that sums the partial products in a fixed order.
+#include <algorithm>
+
+#include "common.hpp"
+
+namespace lyap {
+namespace {
+
+constexpr int BM = 64, BN = 64, NT = 256;
+
+template <class T> __device__ inline double to_d(T x) { return (double)x; }
+template <> __device__ inline double to_d<_Float16>(_Float16 x) { return (double)(float)x; }
+template <> __device__ inline double to_d<__bf16>(__bf16 x) { return (double)(float)x; }
+
+template <class D> struct Cvt;
+template <> struct Cvt<double> {
+  template <class S> __device__ static double f(S x) { return to_d(x); }
+};
+template <> struct Cvt<float> {
+  __device__ static float f(double x) { return (float)x; }
+  __device__ static float f(float x) { return x; }
+  __device__ static float f(_Float16 x) { return (float)x; }
+  __device__ static float f(__bf16 x) { return (float)x; }
+};
+template <> struct Cvt<_Float16> {
+  __device__ static _Float16 f(double x) { return (_Float16)(float)x; }
+  __device__ static _Float16 f(float x) { return (_Float16)x; }
+  __device__ static _Float16 f(_Float16 x) { return x; }
+  __device__ static _Float16 f(__bf16 x) { return (_Float16)(float)x; }
+};
+template <> struct Cvt<__bf16> {
+  __device__ static __bf16 f(double x) { return (__bf16)(float)x; }
+  __device__ static __bf16 f(float x) { return (__bf16)x; }
+  __device__ static __bf16 f(_Float16 x) { return (__bf16)(float)x; }
+  __device__ static __bf16 f(__bf16 x) { return x; }
+};
+
+template <class MF> struct Acc;
+template <> struct Acc<double> { typedef f64x4 V; typedef double S; };
+template <> struct Acc<float> { typedef f32x4 V; typedef float S; };
+
+__device__ inline f64x4 mfma4(double a, double b, f64x4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ inline f32x4 mfma4(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <class TC, class S> __device__ inline void store_out(TC* p, S v) { *p = (TC)v; }
+
+// ----------------------------------------------------------------------------- k4 kernel
+// MF = double (FP64 matrix cores) or float (binary32 matrix cores).
+template <class TA, class TB, class MF, class TC, bool AK, bool BN_>
+__global__ __launch_bounds__(NT) void gemm_k4(int M, int N, int K, int kchunk, double alpha,
+                                              double beta, const TA* __restrict__ A, long sar,
+                                              long sac, const TB* __restrict__ B, long sbr,
+                                              long sbc, TC* __restrict__ C, long ldc,
+                                              TC* __restrict__ part) {
+  constexpr int BK = 16;
+  typedef typename Acc<MF>::V AV;
+  typedef typename Acc<MF>::S AS;
+  __shared__ MF As[BK][BM + 1];
+  __shared__ MF Bs[BK][BN + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int kbeg = blockIdx.z * kchunk;
+  const int kend = min(K, kbeg + kchunk);
+  AV acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = AV{0, 0, 0, 0};
+
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+#pragma unroll
+    for (int r = 0; r < (BM * BK) / NT; ++r) {
+      int e = tid + NT * r;
+      int kk, mm;
+      if (AK) { kk = e % BK; mm = e / BK; } else { mm = e % BM; kk = e / BM; }
+      int gm = m0 + mm, gk = k0 + kk;
+      MF v = (MF)0;
+      if (gm < M && gk < kend) v = Cvt<MF>::f(A[(long)gm * sar + (long)gk * sac]);
+      As[kk][mm] = v;
+    }
+#pragma unroll
+    for (int r = 0; r < (BN * BK) / NT; ++r) {
+      int e = tid + NT * r;
+      int kk, nn;
+      if (BN_) { nn = e % BN; kk = e / BN; } else { kk = e % BK; nn = e / BK; }
+      int gn = n0 + nn, gk = k0 + kk;
+      MF v = (MF)0;
+      if (gn < N && gk < kend) v = Cvt<MF>::f(B[(long)gk * sbr + (long)gn * sbc]);
+      Bs[kk][nn] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 4) {
+      const int kq = ks + (lane >> 4);
+      MF a0 = As[kq][wm + (lane & 15)];
+      MF a1 = As[kq][wm + 16 + (lane & 15)];
+      MF b0 = Bs[kq][wn + (lane & 15)];
+      MF b1 = Bs[kq][wn + 16 + (lane & 15)];
+      acc[0][0] = mfma4(a0, b0, acc[0][0]);
+      acc[0][1] = mfma4(a0, b1, acc[0][1]);
+      acc[1][0] = mfma4(a1, b0, acc[1][0]);
+      acc[1][1] = mfma4(a1, b1, acc[1][1]);
+    }
+    __syncthreads();
+  }
+  // D layout of the 16x16 tile, lane l, register i: column l % 16; row 4*i + l/16 for the
+  // FP64 instruction and 4*(l/16) + i for the binary32 one.
+  constexpr bool kF64 = sizeof(MF) == 8;
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        int rr = kF64 ? (4 * i + (lane >> 4)) : (4 * (lane >> 4) + i);
+        int gm = m0 + wm + ti * 16 + rr;
+        int gn = n0 + wn + tj * 16 + (lane & 15);
+        if (gm < M && gn < N) {
+          AS v = acc[ti][tj][i];
+          if (part) {
+            part[((long)blockIdx.z * M + gm) * N + gn] = (TC)((double)v * alpha);
+          } else {
+            TC* cp = C + (long)gm * ldc + gn;
+            double out = alpha * (double)v;
+            if (beta != 0.0) out += beta * (double)(*cp);
+            *cp = (TC)out;
+          }
+        }
+      }
+}
+
+// ---------------------------------------------------------------------------- k32 kernel
+template <class MF> struct V8;
+template <> struct V8<_Float16> { typedef f16x8 T; };
+template <> struct V8<__bf16> { typedef bf16x8 T; };
+
+__device__ inline f32x4 mfma32(f16x8 a, f16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+}
+__device__ inline f32x4 mfma32(bf16x8 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+template <class TA, class TB, class MF, class TC, bool AK, bool BN_>
+__global__ __launch_bounds__(NT) void gemm_k32(int M, int N, int K, double alpha, double beta,
+                                               const TA* __restrict__ A, long sar, long sac,
+                                               const TB* __restrict__ B, long sbr, long sbc,
+                                               TC* __restrict__ C, long ldc) {
+  constexpr int BK = 32, PK = BK + 8;
+  typedef typename V8<MF>::T VT;
+  __shared__ __attribute__((aligned(16))) MF As[BM][PK];
+  __shared__ __attribute__((aligned(16))) MF Bs[BN][PK];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
+
+  for (int k0 = 0; k0 < K; k0 += BK) {
+#pragma unroll
+    for (int r = 0; r < (BM * BK) / NT; ++r) {
+      int e = tid + NT * r;
+      int kk, mm;
+      if (AK) { kk = e % BK; mm = e / BK; } else { mm = e % BM; kk = e / BM; }
+      int gm = m0 + mm, gk = k0 + kk;
+      MF v = Cvt<MF>::f(0.0f);
+      if (gm < M && gk < K) v = Cvt<MF>::f(A[(long)gm * sar + (long)gk * sac]);
+      As[mm][kk] = v;
+    }
+#pragma unroll
+    for (int r = 0; r < (BN * BK) / NT; ++r) {
+      int e = tid + NT * r;
+      int kk, nn;
+      if (BN_) { nn = e % BN; kk = e / BN; } else { kk = e % BK; nn = e / BK; }
+      int gn = n0 + nn, gk = k0 + kk;
+      MF v = Cvt<MF>::f(0.0f);
+      if (gn < N && gk < K) v = Cvt<MF>::f(B[(long)gk * sbr + (long)gn * sbc]);
+      Bs[nn][kk] = v;
+    }
+    __syncthreads();
+    // operand layout: lane l holds row (l % 16), k = 8*(l/16) .. 8*(l/16)+7
+    const int kq = 8 * (lane >> 4);
+    VT a0 = *reinterpret_cast<const VT*>(&As[wm + (lane & 15)][kq]);
+    VT a1 = *reinterpret_cast<const VT*>(&As[wm + 16 + (lane & 15)][kq]);
+    VT b0 = *reinterpret_cast<const VT*>(&Bs[wn + (lane & 15)][kq]);
+    VT b1 = *reinterpret_cast<const VT*>(&Bs[wn + 16 + (lane & 15)][kq]);
+    acc[0][0] = mfma32(a0, b0, acc[0][0]);
+    acc[0][1] = mfma32(a0, b1, acc[0][1]);
+    acc[1][0] = mfma32(a1, b0, acc[1][0]);
+    acc[1][1] = mfma32(a1, b1, acc[1][1]);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        int gm = m0 + wm + ti * 16 + 4 * (lane >> 4) + i;
+        int gn = n0 + wn + tj * 16 + (lane & 15);
+        if (gm < M && gn < N) {
+          TC* cp = C + (long)gm * ldc + gn;
+          double out = alpha * (double)acc[ti][tj][i];
+          if (beta != 0.0) out += beta * (double)(*cp);
+          *cp = (TC)out;
+        }
+      }
+}
+
+// Sum split-K partial products in a fixed order: C = sum_z part[z] + beta * C.
+__global__ void splitk_reduce(int M, int N, int splits, const double* __restrict__ part,
+                              double beta, double* __restrict__ C, long ldc) {
+  long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  long total = (long)M * N;
+  if (idx >= total) return;
+  int gm = (int)(idx / N), gn = (int)(idx % N);
+  double s = 0.0;
+  for (int z = 0; z < splits; ++z) s += part[(long)z * total + idx];
+  double* cp = C + (long)gm * ldc + gn;
+  if (beta != 0.0) s += beta * (*cp);
+  *cp = s;
+}
+
+template <class TA, class TB, class MF, class TC>
+int launch_k4(hipStream_t s, const GemmDesc& d, int splits, TC* part) {
+  dim3 grid(ceil_div(d.N, BN), ceil_div(d.M, BM), splits);
+  int kchunk = splits > 1 ? ceil_div(ceil_div(d.K, splits), 16) * 16 : d.K;
+  bool ak = (d.sac == 1), bn = (d.sbc == 1);
+  auto A = static_cast<const TA*>(d.A);
+  auto B = static_cast<const TB*>(d.B);
+  auto C = static_cast<TC*>(d.C);
+#define K4(a, b)                                                                              \
+  hipLaunchKernelGGL((gemm_k4<TA, TB, MF, TC, a, b>), grid, dim3(NT), 0, s, d.M, d.N, d.K,   \
+                     kchunk, d.alpha, d.beta, A, d.sar, d.sac, B, d.sbr, d.sbc, C, d.ldc,  \
+                     part)
+  if (ak && bn) K4(true, true);
+  else if (ak) K4(true, false);
+  else if (bn) K4(false, true);
+  else K4(false, false);
+#undef K4
+  LYAP_HIP(hipGetLastError());
+  return LYAP_OK;
+}
+
+template <class TA, class TB, class MF, class TC>
+int launch_k32(hipStream_t s, const GemmDesc& d) {
+  dim3 grid(ceil_div(d.N, BN), ceil_div(d.M, BM), 1);
+  bool ak = (d.sac == 1), bn = (d.sbc == 1);
+  auto A = static_cast<const TA*>(d.A);
+  auto B = static_cast<const TB*>(d.B);
+  auto C = static_cast<TC*>(d.C);
+#define K32(a, b)                                                                             \
+  hipLaunchKernelGGL((gemm_k32<TA, TB, MF, TC, a, b>), grid, dim3(NT), 0, s, d.M, d.N, d.K,  \
+                     d.alpha, d.beta, A, d.sar, d.sac, B, d.sbr, d.sbc, C, d.ldc)
+  if (ak && bn) K32(true, true);
+  else if (ak) K32(true, false);
+  else if (bn) K32(false, true);
+  else K32(false, false);
+#undef K32
+  LYAP_HIP(hipGetLastError());
+  return LYAP_OK;
+}
+
+template <class TA, class TB, class TC>
+int dispatch_lp_op(hipStream_t s, Prec op, const GemmDesc& d) {
+  switch (op) {
+    case Prec::F32: return launch_k4<TA, TB, float, TC>(s, d, 1, nullptr);
+    case Prec::F16: return launch_k32<TA, TB, _Float16, TC>(s, d);
+    case Prec::BF16: return launch_k32<TA, TB, __bf16, TC>(s, d);
+    default: return LYAP_BADARG;
+  }
+}
+
+template <class TA, class TB>
+int dispatch_lp_c(hipStream_t s, Prec op, Store sc, const GemmDesc& d) {
+  if (sc == Store::F32) return dispatch_lp_op<TA, TB, float>(s, op, d);
+  if (sc == Store::F64) return dispatch_lp_op<TA, TB, double>(s, op, d);
+  return LYAP_BADARG;
+}
+
+template <class TA>
+int dispatch_lp_b(hipStream_t s, Prec op, Store sb, Store sc, const GemmDesc& d) {
+  switch (sb) {
+    case Store::F64: return dispatch_lp_c<TA, double>(s, op, sc, d);
+    case Store::F32: return dispatch_lp_c<TA, float>(s, op, sc, d);
+    case Store::F16: return dispatch_lp_c<TA, _Float16>(s, op, sc, d);
+    case Store::BF16: return dispatch_lp_c<TA, __bf16>(s, op, sc, d);
+  }
+  return LYAP_BADARG;
+}
+
+}  // namespace
+
+int gemm_f64(hipStream_t s, const GemmDesc& d, double* ws, size_t ws_elems) {
+  if (d.M <= 0 || d.N <= 0) return LYAP_OK;
+  // K == 0 is handled by the kernel itself: the k-loop is empty and C = beta * C.
+  int tiles = ceil_div(d.M, BM) * ceil_div(d.N, BN);
+  int splits = 1;
+  if (ws && tiles < 128 && d.K >= 1024) {
+    splits = std::min(64, std::max(1, 256 / tiles));
+    splits = std::min(splits, d.K / 256);
+    while (splits > 1 && (size_t)splits * d.M * d.N > ws_elems) --splits;
+  }
+  if (splits <= 1) return launch_k4<double, double, double, double>(s, d, 1, nullptr);
+  LYAP_TRY((launch_k4<double, double, double, double>(s, d, splits, ws)));
+  long total = (long)d.M * d.N;
+  hipLaunchKernelGGL(splitk_reduce, dim3((unsigned)ceil_div((int)total, 256)), dim3(256), 0, s,
+                     d.M, d.N, splits, ws, d.beta, static_cast<double*>(d.C), d.ldc);
+  LYAP_HIP(hipGetLastError());
+  return LYAP_OK;
+}
+
+int gemm_lp(hipStream_t s, Prec op, Store sa, Store sb, Store sc, const GemmDesc& d) {
+  if (d.M <= 0 || d.N <= 0) return LYAP_OK;
+  switch (sa) {
+    case Store::F64: return dispatch_lp_b<double>(s, op, sb, sc, d);
+    case Store::F32: return dispatch_lp_b<float>(s, op, sb, sc, d);
+    case Store::F16: return dispatch_lp_b<_Float16>(s, op, sb, sc, d);
+    case Store::BF16: return dispatch_lp_b<__bf16>(s, op, sb, sc, d);
+  }
+  return LYAP_BADARG;
+}
+
+}  // namespace lyap

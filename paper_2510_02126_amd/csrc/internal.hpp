@@ -1,0 +1,60 @@
+// Internal entry points shared between the kernel files and the host driver.
+#pragma once
+
+#include "common.hpp"
+
+namespace lyap {
+
+// ---- inverse.hip
+size_t inverse_workspace_bytes(Prec op, int n);
+// A^{-1} at solver precision ``op`` into ``out`` (FP64).  flags_dev[0] <- 1 on an exact zero
+// pivot, flags_dev[1] <- 1 on a non-finite input or result (device ints zeroed by caller).
+int invert(hipStream_t s, Prec op, int n, const double* A, long lda, double* out, long ldo,
+           Arena& ws, int* flags_dev);
+
+// ---- elem.hip
+int fill_int(hipStream_t s, int* p, int count, int value);
+int fill_f64(hipStream_t s, double* p, long count, double value);
+// Copy a rows x cols block (row-major, lds / ldd) with optional per-column scale (may be NULL)
+// and global scale.
+int copy_block(hipStream_t s, int rows, int cols, const double* src, long lds, double* dst,
+               long ldd, const double* colscale = nullptr, double scale = 1.0);
+// Round an FP64 rows x cols block to storage ``st`` (F64/F32/F16/BF16) into dst (ld = cols).
+int cast_store(hipStream_t s, Store st, int rows, int cols, const double* src, long lds,
+               void* dst);
+// sum of squares of a rows x cols FP64 block into out[0] (deterministic two-stage).
+int sumsq(hipStream_t s, int rows, int cols, const double* A, long lda, double* out,
+          double* partial /* >= 256 doubles */);
+// Newton update: Anew = 0.5 (mu A + Ainv / mu), mu = mu_dev[0]; accumulates into out4:
+// out4[0] = ||Anew - A||_F^2, out4[1] = ||Anew||_F^2, out4[2] = ||Anew + I||_1.
+// colsum must hold n doubles, partial >= 3*256 doubles.
+int newton_update(hipStream_t s, int n, const double* A, long lda, const double* Ainv, long ldi,
+                  const double* mu_dev, double* Anew, long ldn, double* out4, double* colsum,
+                  double* partial);
+// mu = sqrt(sqrt(inv_sumsq) / sqrt(a_sumsq)) when scaling, else 1 (device scalars).
+int newton_mu(hipStream_t s, const double* inv_sumsq, const double* a_sumsq, int scaling,
+              double* mu_dev);
+
+// sum_ij d_i d_j G_ij^2 for a symmetric c x c G into out[0]; partial >= 256 doubles.
+int wsumsq(hipStream_t s, int c, const double* G, long ldg, const double* d, double* out,
+           double* partial);
+// dst[:, k] = src[:, idx[k]] (idx on the device), rows x count.
+int gather_cols(hipStream_t s, int rows, int count, const double* src, long lds, const int* idx,
+                double* dst, long ldd);
+// out[0] = trace(A) (n x n).
+int trace(hipStream_t s, int n, const double* A, long lda, double* out);
+
+// ---- qr.hip
+size_t qr_workspace_bytes(int n, int p);
+// Thin QR F = U T (U n x min(n,p) explicit, T min(n,p) x p upper trapezoidal); F is copied
+// first.
+int qr(hipStream_t s, int n, int p, const double* F, long ldf, double* U, long ldu, double* T,
+       long ldt, Arena& ws);
+
+// ---- eig.hip
+size_t syev_workspace_bytes(int p);
+// H = V diag(w) V^T, w sorted by descending |w|.  ``sweeps_out`` (host, optional).
+int syev(hipStream_t s, int p, const double* H, long ldh, double* w, double* V, long ldv,
+         Arena& ws, double tol_rel, int* sweeps_out);
+
+}  // namespace lyap
