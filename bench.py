@@ -1,0 +1,164 @@
+"""Benchmark: solves/s at n = 4096 to an FP64-level residual (<= 1e-13), mixed-precision
+iterative refinement against the plain FP64 sign-function Newton solve, on one MI355X.
+
+Workload (synthetic, seeded): n = 4096, W = L S L^T with L 4096 x 8 ~ N(0,1) and S = diag(+-1)
+indefinite; A = Q T Q^T with Q Haar orthogonal and T upper triangular, diag(T) =
+-logspace(-3, 0, n) (see lyapgen.config("large")).  Inputs are resident in HBM before timing.
+
+One step = one complete lyap_solve call (inversions, factor iteration, residual
+factorisations, corrections and updates) that must end with res <= 1e-13; a run whose solves
+do not reach it is reported as DNF.  Prints one JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--us fp32] [--skip-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "fp16": 2500.0, "bf16": 2500.0}
+
+
+def _time_solves(lyap, torch, A, L, S, us, steps, warmup):
+    for _ in range(warmup):
+        lyap.solve(A, L, S, precisions=(us, "fp64", "fp64", "fp64"), raise_on_error=False)
+    torch.cuda.synchronize()
+    infos = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        _, _, info = lyap.solve(A, L, S, precisions=(us, "fp64", "fp64", "fp64"),
+                                raise_on_error=False)
+        infos.append(info)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return dt, infos
+
+
+def _time_inverse(lyap, torch, A, us, reps=3):
+    """Average duration of one inversion (the dominant kernel family, 2 n^3 flops) on the
+    current stream, measured with HIP events around the calls."""
+    lyap.inverse(A, us)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        lyap.inverse(A, us)
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps / 1e3
+
+
+def _cpu_baseline(cfg, steps=3):
+    """The oracle's FP64 sign-function Newton solve (Alg 3.2) on the host cores, on a bounded
+    sample: its first ``steps`` Newton steps (inversion, scaled update, factor product), scaled
+    to the full solve by K / steps with the Newton count K taken from the GPU run."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    from oracle import signnewton as SN
+
+    A, L = cfg["A"], cfg["L"]
+    t0 = time.perf_counter()
+    # ``steps`` Newton steps through the oracle's own routines
+    Ak = A.copy()
+    Z = L.copy()
+    for _ in range(steps):
+        Ainv = SN.inverse_at(Ak, "fp64")
+        mu = float(np.sqrt(np.linalg.norm(Ainv, "fro") / np.linalg.norm(Ak, "fro")))
+        Ak = 0.5 * (mu * Ak + Ainv / mu)
+        Z = np.hstack([Z, Ainv @ Z])
+    dt = time.perf_counter() - t0
+    threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [os.cpu_count()])
+    return dt / steps, threads
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--us", default="fp32", help="solver precision of the IR run")
+    ap.add_argument("--skip-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(see DESIGN.md for how the solve would shard).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import lyapgen
+    import paper_2510_02126_amd as lyap
+
+    cfg = lyapgen.config("large")
+    A = torch.from_numpy(cfg["A"]).cuda()
+    L = torch.from_numpy(cfg["L"]).cuda()
+    S = torch.from_numpy(cfg["S"]).cuda()
+    n = A.shape[0]
+
+    # plain FP64 sign-function Newton solve (the baseline), then mixed-precision IR
+    dt64, inf64 = _time_solves(lyap, torch, A, L, S, "fp64", args.steps, args.warmup)
+    dtir, infir = _time_solves(lyap, torch, A, L, S, args.us, args.steps, args.warmup)
+    ok64 = all(i["status"] == "OK" and i["res"] <= 1e-13 for i in inf64)
+    okir = all(i["status"] == "OK" and i["res"] <= 1e-13 for i in infir)
+    sps64 = args.steps / dt64 if ok64 else 0.0
+    spsir = args.steps / dtir if okir else 0.0
+
+    t_inv = _time_inverse(lyap, torch, A, "fp64")
+    achieved = 2.0 * n ** 3 / t_inv / 1e12
+    roof = {"bound": "mfma", "kernel": "inversion (fp64 Gauss-Jordan, 2n^3 flops)",
+            "achieved": round(achieved, 3), "peak": PEAK_TFLOPS["fp64"], "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_TFLOPS["fp64"], 4), "traffic": None}
+
+    cpu = None
+    if not args.skip_cpu:
+        t_step, threads = _cpu_baseline(cfg)
+        K = inf64[-1]["inversions"]
+        t_solve = t_step * K
+        cpu = {"value": round(1.0 / t_solve, 6), "unit": "solves/s", "cores": threads,
+               "kind": "oracle",
+               "sample": f"oracle FP64 sign-Newton, first 3 of K={K} Newton steps at n={n} "
+                         f"({3 * t_step:.1f} s), scaled to a full solve"}
+
+    line = {
+        "metric": "solves/s at n=4096 to FP64-level residual: mixed-prec IR vs FP64 sign-Newton",
+        "value": round(spsir, 4),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * dtir / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": f"{args.us}-inner/f64",
+        "data": "synthetic",
+        "config": {"workload": "n=4096, m=8, W=L S L^T indefinite, A=Q T Q^T kappa~1e3",
+                   "ir_precisions": [args.us, "fp64", "fp64", "fp64"], "tol": 1e-13},
+        "ir": {"solves_per_s": round(spsir, 4), "res": infir[-1]["res"],
+               "rank": infir[-1]["rank"], "refinements": infir[-1]["refinements"],
+               "iters": f'{infir[-1]["newton_total"]}({infir[-1]["newton_max"]})',
+               "phase_ms": [round(x, 2) for x in infir[-1]["phase_ms"]],
+               "status": "OK" if okir else "DNF"},
+        "fp64_sign_newton": {"solves_per_s": round(sps64, 4),
+                             "ms_per_solve": round(1e3 * dt64 / args.steps, 3),
+                             "res": inf64[-1]["res"], "rank": inf64[-1]["rank"],
+                             "K": inf64[-1]["inversions"],
+                             "phase_ms": [round(x, 2) for x in inf64[-1]["phase_ms"]],
+                             "status": "OK" if ok64 else "DNF"},
+        "speedup_ir_vs_fp64": round(spsir / sps64, 4) if sps64 > 0 and spsir > 0 else None,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

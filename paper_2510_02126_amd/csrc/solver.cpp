@@ -116,6 +116,7 @@ int Solver::a_iteration(Ctx& c) {
   bool scaling = true;
   int countdown = -1;
   double delta_prev = -1.0;
+  double last_onenorm = INFINITY;
   bool stopped = false;
   const double* a_ss = scal + 0;
   for (int k = 1; k <= c.opt.k_max; ++k) {
@@ -151,6 +152,7 @@ int Solver::a_iteration(Ctx& c) {
     std::swap(Ak_, An_);
     a_ss = scal + 4;
     c.K = k;
+    last_onenorm = onenorm;
     if (countdown >= 0) {
       if (--countdown <= 0) {
         stopped = true;
@@ -163,13 +165,13 @@ int Solver::a_iteration(Ctx& c) {
     delta_prev = delta;
   }
   if (!stopped) return LYAP_NOT_STABLE;
-  // sign(A) = -I for Hurwitz A: an eigenvalue in the right half-plane adds 2 to the trace
-  LYAP_TRY(trace(s, n, Ak, n, scal + 8));
-  double tr = 0.0;
-  LYAP_HIP(hipMemcpyAsync(&tr, scal + 8, sizeof(double), hipMemcpyDeviceToHost, s));
-  LYAP_HIP(hipStreamSynchronize(s));
-  if (!(std::fabs(tr + n) <= 1.0)) return LYAP_NOT_STABLE;
-  return LYAP_OK;
+  // sign(A) = -I exactly when A is Hurwitz.  ||A_K + I||_1 < 1 puts every eigenvalue of A_K
+  // within distance 1 of -1, so A is Hurwitz; an eigenvalue of A in the right half-plane
+  // leaves an eigenvalue of A_K near +1 and ||A_K + I||_1 >= 2 - O(u).  When tau_N >= 1
+  // (fp16/bf16 at large n) the loose stop leaves A_K too far from -I to tell, and an
+  // unstable A shows up instead as refinement that does not converge.
+  if (last_onenorm < 1.0 || tau >= 1.0) return LYAP_OK;
+  return LYAP_NOT_STABLE;
 }
 
 // -------------------------------------------------------------------- rank truncation
@@ -198,7 +200,7 @@ int Solver::rank_trunc(Ctx& c, double* Zb, long ldb, int& cols, std::vector<doub
   g.C = Hm; g.ldc = cap;
   LYAP_TRY(gemm_f64(s, g));
   c.ws->reset();
-  LYAP_TRY(syev(s, k, Hm, cap, wv, Vm, cap, *c.ws, 0.0, nullptr));
+  LYAP_TRY(syev(s, k, Hm, cap, wv, Vm, cap, *c.ws, std::max(10.0 * thr, 1e-15), nullptr));
   std::vector<double> lam(k);
   LYAP_HIP(hipMemcpyAsync(lam.data(), wv, k * sizeof(double), hipMemcpyDeviceToHost, s));
   LYAP_HIP(hipStreamSynchronize(s));
@@ -358,7 +360,7 @@ int Solver::res_factor(Ctx& c, int& rd, std::vector<double>& sd) {
   sd.clear();
   if (k == 0) return LYAP_OK;
   c.ws->reset();
-  LYAP_TRY(syev(s, k, Hm, cap, wv, Vm, cap, *c.ws, 0.0, nullptr));
+  LYAP_TRY(syev(s, k, Hm, cap, wv, Vm, cap, *c.ws, 1e-10, nullptr));
   std::vector<double> lam(k);
   LYAP_HIP(hipMemcpyAsync(lam.data(), wv, k * sizeof(double), hipMemcpyDeviceToHost, s));
   LYAP_HIP(hipStreamSynchronize(s));
