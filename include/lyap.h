@@ -136,13 +136,17 @@ int lyap_solve(lyap_handle h, void* stream, int n, int m, const double* A, int l
 /*
  * lyap_inverse -- inverse of the n x n FP64 matrix A (row-major, lda) at solver precision
  * ``dtype`` (the inversion of Alg 3.1/3.2, first line of the loop): Gauss-Jordan
- * elimination with partial pivoting (ties to the lowest row index).  For F32/F16/BF16 the
- * matrix is held in binary32, scaled by a power of two, and every block-update product
- * takes its operands rounded to ``dtype`` with binary32 accumulation.  The result is
- * written in FP64 to Ainv (row-major, ldi).  Returns LYAP_SINGULAR on an exact zero pivot.
+ * elimination.  pivot != 0: partial pivoting (ties to the lowest row index).  pivot == 0:
+ * no row interchanges, which is the same elimination whenever A is strictly column
+ * diagonally dominant (partial pivoting then never interchanges rows); for other A the
+ * unpivoted elimination may be unstable.  For F32/F16/BF16 the matrix is held in binary32,
+ * scaled by a power of two, and every block-update product takes its operands rounded to
+ * ``dtype`` with binary32 accumulation.  The result is written in FP64 to Ainv (row-major,
+ * ldi).  Returns LYAP_SINGULAR on an exact zero pivot, LYAP_NONFINITE on a NaN/Inf input or
+ * result, LYAP_BADARG for n > 4096.
  */
-int lyap_inverse(lyap_handle h, void* stream, int dtype, int n, const double* A, int lda,
-                 double* Ainv, int ldi);
+int lyap_inverse(lyap_handle h, void* stream, int dtype, int pivot, int n, const double* A,
+                 int lda, double* Ainv, int ldi);
 
 /*
  * lyap_gemm -- C = alpha * op(A) * op(B) + beta * C in FP64 on the FP64 matrix cores, or
@@ -155,11 +159,12 @@ int lyap_gemm(lyap_handle h, void* stream, int dtype, int transa, int transb, in
               double beta, double* C, int ldc);
 
 /*
- * lyap_qr -- thin QR F = U T of the n x p FP64 matrix F (n >= p), as used by the residual
+ * lyap_qr -- thin QR F = U T of the n x p FP64 matrix F, as used by the residual
  * factorisation and solution update (Fragments 2.1-2.4) and RankTruncLdlt (Alg 3.2):
- * block Gram-Schmidt with re-orthogonalisation over panels factored by a Householder
- * tall-skinny QR.  U is n x p (row-major, ldu), T is p x p upper triangular (row-major,
- * ldt).  F is not modified.
+ * right-looking blocked Householder QR whose panels are factored by a two-level
+ * tall-skinny (TSQR) reduction; stable for rank-deficient F.  With k = min(n, p), U is
+ * n x k with orthonormal columns (row-major, ldu >= k) and T is k x p upper trapezoidal
+ * (row-major, ldt >= p).  F is not modified.
  */
 int lyap_qr(lyap_handle h, void* stream, int n, int p, const double* F, int ldf, double* U,
             int ldu, double* T, int ldt);

@@ -6,7 +6,7 @@ current stream.  All arithmetic runs in the library's HIP kernels.
 
     solve(A, L, S=None, precisions=("fp16", "fp64", "fp64", "fp64"), tol=1e-13, ...)
         -> (Z, D, info) with X ~ Z diag(D) Z^T     (Alg 2.2 with Alg 3.2 as the solver)
-    inverse(A, dtype)        -- inversion at a solver precision (Gauss-Jordan, pivoting)
+    inverse(A, dtype, pivot) -- inversion at a solver precision (Gauss-Jordan)
     gemm(A, B, ...)          -- matrix-core product
     qr(F) -> (U, T)          -- thin QR of a tall matrix
     syev(H) -> (w, V)        -- symmetric spectral decomposition
@@ -56,13 +56,13 @@ def version() -> str:
     return _lib.lib().lyap_version().decode()
 
 
-def inverse(A: torch.Tensor, dtype: str = "fp64") -> torch.Tensor:
+def inverse(A: torch.Tensor, dtype: str = "fp64", pivot: bool = True) -> torch.Tensor:
     dev = _dev(A)
     n = A.shape[0]
     A, lda = _rowmajor(A)
     out = torch.empty((n, n), dtype=torch.float64, device=A.device)
-    code = _lib.lib().lyap_inverse(_lib.handle(dev), _stream(dev), DTYPES[dtype], n, _ptr(A), lda,
-                                   _ptr(out), n)
+    code = _lib.lib().lyap_inverse(_lib.handle(dev), _stream(dev), DTYPES[dtype], int(bool(pivot)),
+                                   n, _ptr(A), lda, _ptr(out), n)
     _lib.check(code, "lyap_inverse")
     return out
 

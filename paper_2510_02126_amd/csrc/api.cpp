@@ -106,8 +106,8 @@ int lyap_destroy(lyap_handle h) {
   return LYAP_OK;
 }
 
-int lyap_inverse(lyap_handle h, void* stream, int dtype, int n, const double* A, int lda,
-                 double* Ainv, int ldi) {
+int lyap_inverse(lyap_handle h, void* stream, int dtype, int pivot, int n, const double* A,
+                 int lda, double* Ainv, int ldi) {
   if (!h || !valid_dtype(dtype) || n < 0 || (n > 0 && (!A || !Ainv || lda < n || ldi < n)))
     return LYAP_BADARG;
   if (n == 0) return LYAP_OK;
@@ -116,7 +116,7 @@ int lyap_inverse(lyap_handle h, void* stream, int dtype, int n, const double* A,
   LYAP_TRY(h->ws.reserve(inverse_workspace_bytes((Prec)dtype, n) + (1 << 20)));
   h->ws.reset();
   LYAP_TRY(fill_int(s, h->flags, 2, 0));
-  LYAP_TRY(invert(s, (Prec)dtype, n, A, lda, Ainv, ldi, h->ws, h->flags));
+  LYAP_TRY(invert(s, (Prec)dtype, n, A, lda, Ainv, ldi, h->ws, h->flags, pivot != 0));
   int f[2] = {0, 0};
   LYAP_HIP(hipMemcpyAsync(f, h->flags, sizeof(f), hipMemcpyDeviceToHost, s));
   LYAP_HIP(hipStreamSynchronize(s));

@@ -81,11 +81,19 @@ __global__ void k_sumsq_partial(int rows, int cols, const double* __restrict__ A
                                 double* __restrict__ part) {
   __shared__ double red[RB];
   double acc = 0.0;
-  long total = (long)rows * cols;
-  for (long e = (long)blockIdx.x * RB + threadIdx.x; e < total; e += (long)gridDim.x * RB) {
-    int i = (int)(e / cols), j = (int)(e % cols);
-    double v = A[(long)i * lda + j];
-    acc += v * v;
+  if (cols >= RB / 4) {
+    // rows strided over blocks, columns over threads (coalesced, no index division)
+    for (int i = blockIdx.x; i < rows; i += gridDim.x) {
+      const double* a = A + (long)i * lda;
+      for (int j = threadIdx.x; j < cols; j += RB) acc += a[j] * a[j];
+    }
+  } else {
+    long total = (long)rows * cols;
+    for (long e = (long)blockIdx.x * RB + threadIdx.x; e < total; e += (long)gridDim.x * RB) {
+      int i = (int)(e / cols), j = (int)(e % cols);
+      double v = A[(long)i * lda + j];
+      acc += v * v;
+    }
   }
   double s = block_sum(acc, red);
   if (threadIdx.x == 0) part[blockIdx.x] = s;
@@ -99,66 +107,81 @@ __global__ void k_sum_parts(int nparts, const double* __restrict__ part, double*
   if (threadIdx.x == 0) *out = s;
 }
 
-// Newton update over rows; each block handles a contiguous row range and produces partial
-// sums of squares; the column sums of |Anew + I| are accumulated per block row-range into
-// colpart (RPARTS x n) and reduced afterwards in fixed order.
+// Newton update, tiled: block (x, y) handles the row range x of height ``rows_per`` and the
+// column chunk y of RB columns (one column per thread).  It writes the column partial sums of
+// |Anew + I| over its rows to colpart[x][j] and its partial sums of squares to part; all
+// partials are combined afterwards in a fixed order.
 __global__ void k_newton(int n, const double* __restrict__ A, long lda,
                          const double* __restrict__ Ai, long ldi, const double* __restrict__ mu_dev,
-                         double* __restrict__ An, long ldn, double* __restrict__ part,
+                         double* __restrict__ An, long ldn, int rows_per, double* __restrict__ part,
                          double* __restrict__ colpart) {
   __shared__ double red[RB];
   const double mu = *mu_dev;
   const double hm = 0.5 * mu, hi = 0.5 / mu;
-  int rows_per = (n + gridDim.x - 1) / gridDim.x;
-  int r0 = blockIdx.x * rows_per, r1 = min(n, r0 + rows_per);
-  double sd = 0.0, sa = 0.0;
-  for (int j = threadIdx.x; j < n; j += RB) {
-    double cs = 0.0;
+  const int r0 = blockIdx.x * rows_per, r1 = min(n, r0 + rows_per);
+  const int j = blockIdx.y * RB + threadIdx.x;
+  double sd = 0.0, sa = 0.0, cs = 0.0;
+  if (j < n) {
+#pragma unroll 4
     for (int i = r0; i < r1; ++i) {
-      double a = A[(long)i * lda + j];
-      double x = hm * a + hi * Ai[(long)i * ldi + j];
+      const double a = A[(long)i * lda + j];
+      const double x = hm * a + hi * Ai[(long)i * ldi + j];
       An[(long)i * ldn + j] = x;
-      double d = x - a;
+      const double d = x - a;
       sd += d * d;
       sa += x * x;
       cs += fabs(x + (i == j ? 1.0 : 0.0));
     }
     colpart[(long)blockIdx.x * n + j] = cs;
   }
-  double s1 = block_sum(sd, red);
-  double s2 = block_sum(sa, red);
+  const double s1 = block_sum(sd, red);
+  const double s2 = block_sum(sa, red);
   if (threadIdx.x == 0) {
-    part[blockIdx.x] = s1;
-    part[gridDim.x + blockIdx.x] = s2;
+    const int b = blockIdx.y * gridDim.x + blockIdx.x, nb = gridDim.x * gridDim.y;
+    part[b] = s1;
+    part[nb + b] = s2;
   }
 }
 
-__global__ void k_newton_finish(int n, int nparts, const double* __restrict__ part,
-                                const double* __restrict__ colpart, double* __restrict__ colsum,
-                                double* __restrict__ out4) {
+// colsum[j] = sum_x colpart[x][j] in order of x; colmax[block] = max over the block's columns.
+__global__ void k_colsum(int n, int nparts, const double* __restrict__ colpart,
+                         double* __restrict__ colsum, double* __restrict__ colmax) {
   __shared__ double red[RB];
-  double m = 0.0;
-  for (int j = threadIdx.x; j < n; j += RB) {
-    double s = 0.0;
+  const int j = blockIdx.x * RB + threadIdx.x;
+  double s = 0.0;
+  if (j < n) {
     for (int b = 0; b < nparts; ++b) s += colpart[(long)b * n + j];
     colsum[j] = s;
-    m = fmax(m, s);
   }
-  red[threadIdx.x] = m;
+  red[threadIdx.x] = s;
   __syncthreads();
-  for (int s = RB / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+  for (int h = RB / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + h]);
     __syncthreads();
   }
-  double onenorm = red[0];
+  if (threadIdx.x == 0) colmax[blockIdx.x] = red[0];
+}
+
+__global__ void k_newton_finish(int nb, const double* __restrict__ part, int nchunks,
+                                const double* __restrict__ colmax, double* __restrict__ out4) {
+  __shared__ double red[RB];
+  double m = 0.0;
+  for (int i = threadIdx.x; i < nchunks; i += RB) m = fmax(m, colmax[i]);
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int h = RB / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + h]);
+    __syncthreads();
+  }
+  const double onenorm = red[0];
   __syncthreads();
   double a = 0.0, b = 0.0;
-  for (int i = threadIdx.x; i < nparts; i += RB) {
+  for (int i = threadIdx.x; i < nb; i += RB) {
     a += part[i];
-    b += part[nparts + i];
+    b += part[nb + i];
   }
-  double sa = block_sum(a, red);
-  double sb = block_sum(b, red);
+  const double sa = block_sum(a, red);
+  const double sb = block_sum(b, red);
   if (threadIdx.x == 0) {
     out4[0] = sa;
     out4[1] = sb;
@@ -233,13 +256,19 @@ int sumsq(hipStream_t s, int rows, int cols, const double* A, long lda, double* 
 int newton_update(hipStream_t s, int n, const double* A, long lda, const double* Ainv, long ldi,
                   const double* mu_dev, double* Anew, long ldn, double* out4, double* colsum,
                   double* partial) {
-  // partial: 2*RPARTS scalars followed by RPARTS*n column partial sums
-  int nparts = std::min(RPARTS, n);
-  double* colpart = partial + 2 * RPARTS;
-  hipLaunchKernelGGL(k_newton, dim3(nparts), dim3(RB), 0, s, n, A, lda, Ainv, ldi, mu_dev, Anew,
-                     ldn, partial, colpart);
-  hipLaunchKernelGGL(k_newton_finish, dim3(1), dim3(RB), 0, s, n, nparts, partial, colpart, colsum,
-                     out4);
+  // partial layout: 2*nb block sums, then nparts*n column partial sums, then nchunks maxima
+  // (at most 2*RPARTS + RPARTS*n doubles for n >= 1)
+  const int nparts = std::min(64, n);
+  const int rows_per = (n + nparts - 1) / nparts;
+  const int nrows = (n + rows_per - 1) / rows_per;
+  const int nchunks = (n + RB - 1) / RB;
+  const int nb = nrows * nchunks;
+  double* colpart = partial + 2 * nb;
+  double* colmax = colpart + (long)nrows * n;
+  hipLaunchKernelGGL(k_newton, dim3(nrows, nchunks), dim3(RB), 0, s, n, A, lda, Ainv, ldi, mu_dev,
+                     Anew, ldn, rows_per, partial, colpart);
+  hipLaunchKernelGGL(k_colsum, dim3(nchunks), dim3(RB), 0, s, n, nrows, colpart, colsum, colmax);
+  hipLaunchKernelGGL(k_newton_finish, dim3(1), dim3(RB), 0, s, nb, partial, nchunks, colmax, out4);
   LYAP_HIP(hipGetLastError());
   return LYAP_OK;
 }

@@ -9,8 +9,10 @@ namespace lyap {
 size_t inverse_workspace_bytes(Prec op, int n);
 // A^{-1} at solver precision ``op`` into ``out`` (FP64).  flags_dev[0] <- 1 on an exact zero
 // pivot, flags_dev[1] <- 1 on a non-finite input or result (device ints zeroed by caller).
+// pivot = false skips the pivot search (pivot row = diagonal row); valid when A is strictly
+// column diagonally dominant, where partial pivoting makes no interchanges.
 int invert(hipStream_t s, Prec op, int n, const double* A, long lda, double* out, long ldo,
-           Arena& ws, int* flags_dev);
+           Arena& ws, int* flags_dev, bool pivot = true);
 
 // ---- elem.hip
 int fill_int(hipStream_t s, int* p, int count, int value);

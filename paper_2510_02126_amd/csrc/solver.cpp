@@ -126,7 +126,10 @@ int Solver::a_iteration(Ctx& c) {
     double* out = (c.us == Prec::F64) ? cache_[k - 1].as<double>() : Ainv_.as<double>();
     LYAP_TRY(fill_int(s, c.flags, 2, 0));
     c.ws->reset();
-    LYAP_TRY(invert(s, c.us, n, Ak, n, out, n, *c.ws, c.flags));
+    // ||A_{k-1} + I||_1 < 1 makes A_{k-1} strictly column diagonally dominant: partial
+    // pivoting would pick the diagonal, so the pivot search is skipped (same result)
+    const bool pivot = !(last_onenorm < 1.0);
+    LYAP_TRY(invert(s, c.us, n, Ak, n, out, n, *c.ws, c.flags, pivot));
     if (c.us != Prec::F64) LYAP_TRY(cast_store(s, c.cstore, n, n, out, n, cache_[k - 1].p));
     LYAP_TRY(sumsq(s, n, n, out, n, scal + 1, c.part));
     LYAP_TRY(newton_mu(s, scal + 1, a_ss, scaling ? 1 : 0, scal + 2));

@@ -123,3 +123,33 @@ def test_inverse_deterministic(lyap):
     a = lyap.inverse(_cuda(A), "fp16").cpu().numpy()
     b = lyap.inverse(_cuda(A), "fp16").cpu().numpy()
     assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 777, 4096])
+@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
+def test_inverse_diag_dominant_unpivoted(lyap, n, dtype):
+    # ||A + I||_1 < 1 makes A strictly column diagonally dominant: partial pivoting picks the
+    # diagonal at every step, so the solver's unpivoted route computes the same elimination
+    # (the two differ only by the blocking of the update products)
+    print(f"inverse unpivoted {dtype} n={n}", flush=True)
+    rng = np.random.default_rng(9 + n)
+    E = rng.standard_normal((n, n))
+    E *= 0.5 / np.abs(E).sum(axis=0, keepdims=True)
+    A = -np.eye(n) + E
+    Xp = lyap.inverse(_cuda(A), dtype, pivot=True).cpu().numpy()
+    Xn = lyap.inverse(_cuda(A), dtype, pivot=False).cpu().numpy()
+    u = {"fp64": 2.0 ** -53, "fp32": 2.0 ** -24}[dtype]
+    kappa = np.linalg.cond(A, 1)
+    tol = 20 * n ** 0.5 * kappa * u
+    for X in (Xp, Xn):
+        assert np.linalg.norm(A @ X - np.eye(n), 1) <= tol
+    assert np.linalg.norm(Xn - Xp, 1) / np.linalg.norm(Xp, 1) <= tol
+
+
+def test_inverse_unpivoted_zero_pivot_reports(lyap):
+    A = np.array([[0.0, 1.0], [1.0, 0.0]])
+    with pytest.raises(lyap.LyapError) as e:
+        lyap.inverse(_cuda(A), "fp64", pivot=False)
+    assert e.value.status == "SINGULAR"
+    X = lyap.inverse(_cuda(A), "fp64", pivot=True).cpu().numpy()
+    assert np.array_equal(X, A)

@@ -34,4 +34,4 @@ def test_host_only_calls():
     assert o.theta == pytest.approx(0.9) and o.delta_off == pytest.approx(1e-2)
     # a NULL handle is rejected before any device work
     assert L.lyap_destroy(None) == 0
-    assert L.lyap_inverse(None, None, 0, 4, None, 4, None, 4) == 7
+    assert L.lyap_inverse(None, None, 0, 1, 4, None, 4, None, 4) == 7
