@@ -282,19 +282,20 @@ __global__ __launch_bounds__(LEAF_THREADS) void gj_leaf(int n, T* __restrict__ W
 // -------------------------------------------------------------- non-pivoted leaf kernels
 // Invert the w x w diagonal block D = W[c0.., c0..] (w <= WN) by Gauss-Jordan without
 // pivoting; Dinv (w x w, row-major) to global; the pivots are the diagonal rows.  Thread t
-// holds column j = t % 64 of rows g + 4q (g = t / 64, q < 16) in registers; step k publishes
-// the pivot row and the multiplier column in LDS (double-buffered, one barrier per step).
+// holds row i = t % 64 of D at columns g + 4q (g = t / 64, q < 16) in registers, so the loads
+// from WT are coalesced; step k publishes the pivot row and the multiplier column in LDS
+// (double-buffered, one barrier per step).
 template <class T>
 __global__ __launch_bounds__(256) void nop_diag(int n, const T* __restrict__ WT, int c0, int w,
                                                 T* __restrict__ Dinv, int* __restrict__ used,
                                                 int* __restrict__ piv, int* __restrict__ sing) {
   __shared__ T rowk[2][WN];
   __shared__ T colk[2][WN];
-  const int t = threadIdx.x, j = t & 63, g = t >> 6;
+  const int t = threadIdx.x, i = t & 63, g = t >> 6;
   T d[WN / 4];
 #pragma unroll
   for (int q = 0; q < WN / 4; ++q) {
-    const int i = g + 4 * q;
+    const int j = g + 4 * q;
     d[q] = (i < w && j < w) ? WT[(long)(c0 + j) * n + c0 + i] : (T)(i == j ? 1 : 0);
   }
   if (t < w) {
@@ -303,16 +304,16 @@ __global__ __launch_bounds__(256) void nop_diag(int n, const T* __restrict__ WT,
   }
   for (int k = 0; k < w; ++k) {
     const int buf = k & 1;
-    if (j == k) {
+    if (i == k) {
 #pragma unroll
-      for (int q = 0; q < WN / 4; ++q) colk[buf][g + 4 * q] = d[q];
+      for (int q = 0; q < WN / 4; ++q) rowk[buf][g + 4 * q] = d[q];
     }
     if (g == (k & 3)) {
       T x = (T)0;
 #pragma unroll
       for (int q = 0; q < WN / 4; ++q)
         if (q == (k >> 2)) x = d[q];
-      rowk[buf][j] = x;
+      colk[buf][i] = x;
     }
     __syncthreads();
     T p = rowk[buf][k];
@@ -321,21 +322,18 @@ __global__ __launch_bounds__(256) void nop_diag(int n, const T* __restrict__ WT,
       p = (T)1;
     }
     const T inv = (T)1 / p;
-    const T pr = rowk[buf][j] * inv;
+    const T f = colk[buf][i];
 #pragma unroll
     for (int q = 0; q < WN / 4; ++q) {
-      const int i = g + 4 * q;
-      if (i == k) {
-        d[q] = (j == k) ? inv : pr;
-      } else {
-        const T f = colk[buf][i];
-        d[q] = (j == k) ? -f * inv : d[q] - f * pr;
-      }
+      const int j = g + 4 * q;
+      const T pr = rowk[buf][j] * inv;
+      if (i == k) d[q] = (j == k) ? inv : pr;
+      else d[q] = (j == k) ? -f * inv : d[q] - f * pr;
     }
   }
 #pragma unroll
   for (int q = 0; q < WN / 4; ++q) {
-    const int i = g + 4 * q;
+    const int j = g + 4 * q;
     if (i < w && j < w) Dinv[i * w + j] = d[q];
   }
 }

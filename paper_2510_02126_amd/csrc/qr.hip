@@ -1,17 +1,28 @@
-// Thin QR F = U T of an n x p FP64 matrix (U n x min(n,p) orthonormal, T upper trapezoidal) (the "thin QR decomposition" of
-// Fragments 2.1-2.4 and of RankTruncLdlt in Alg 3.2), by Householder reflections only.
+// Thin QR F = U T of an n x p FP64 matrix (U n x min(n,p) orthonormal, T upper trapezoidal)
+// (the "thin QR decomposition" of Fragments 2.1-2.4 and of RankTruncLdlt in Alg 3.2), by
+// Householder reflections only.
 //
 // Right-looking, panel by panel (32 columns).  Panel j covers columns [c, c+w) and rows
 // [c, n) of the working copy.  Its orthogonal factor is a two-level tree of Householder
 // reflectors (tall-skinny QR):
-//   level 1  each 256-row chunk is factored in LDS (reflectors kept in global memory),
+//   level 1  each 256-row chunk is factored by one workgroup,
 //   level 2  the stacked chunk R factors (<= 16 x 32 rows) are factored by one workgroup.
-// The panel's transformation Q_j^T is then applied to the trailing columns (level-1
-// reflectors per chunk, then level-2 reflectors on the stacked rows), which leaves the R
-// rows of the panel in rows [c, c+w).  After the last panel, U = Q_1 ... Q_k [I_p; 0] is
-// formed by applying the stored reflectors in reverse.  Because only reflectors are used,
-// U is orthonormal to working precision even for numerically rank-deficient F (such as
-// F = [Z, AZ, L] near convergence, where AZ lies almost in the span of Z and L).
+// Each set of (at most 32) reflectors is kept in compact WY form H_0 H_1 ... H_{k-1} =
+// I - V Tw V^T (V unit lower trapezoidal, Tw upper triangular), so the panel's transformation
+// Q_j^T is applied to the trailing columns as X <- X - V Tw^T (V^T X): three products on the
+// FP64 matrix cores per 32-column tile (level 1 per chunk, then level 2 on the stacked rows),
+// which leaves the R rows of the panel in rows [c, c+w).  After the last panel,
+// U = Q_1 ... Q_k [I_p; 0] is formed by applying the block reflectors in reverse.  Because
+// only reflectors are used, U is orthonormal to working precision even for numerically
+// rank-deficient F (such as F = [Z, AZ, L] near convergence, where AZ lies almost in the span
+// of Z and L).
+//
+// Panel factorisation: thread t holds rows t + 256 q of the block in registers.  Step k
+// forms, in one reduction over rows below k, the sums s_c = sum_i A[i][c] A[i][k] for all 32
+// columns: s_k is the squared norm below the diagonal, s_j (j > k) gives the reflector's
+// action on the trailing columns and s_c (c < k) gives V^T v_k for the Tw recurrence
+// (Tw[0:k, k] = -tau_k Tw[0:k, 0:k] V^T v_k).  The register columns are rotated by one per
+// step so that the pivot column always sits in register 0 (no dynamic register indexing).
 #include <algorithm>
 #include <cmath>
 
@@ -23,223 +34,330 @@ namespace {
 
 constexpr int PB = 32;     // panel width
 constexpr int CH = 256;    // chunk rows at level 1
-constexpr int NG = 8;      // row groups per workgroup (threads = NG * PB = 256)
-constexpr int NTH = NG * PB;
+constexpr int NTH = 256;   // threads per workgroup
 constexpr int MAXCH = 16;  // chunks per panel (n <= 4096)
+constexpr int SL_STACK = 128;  // row slab of the block-reflector application on the stack
 
-__device__ inline int first_row(int k0, int g) {  // smallest i >= k0 with i = g (mod NG)
-  return k0 + ((g - k0) % NG + NG) % NG;
+constexpr int CPT = 8;         // panel columns per thread
+constexpr int NCG = PB / CPT;  // column groups: thread t owns column group t % NCG
+
+struct PanelLds {
+  double part[NTH / 16][PB];  // partial sums per 16-lane row of each wave
+  double prow[PB];            // row k
+  double dvec[PB];            // tau (A[k][j] + v_k^T A[k+1:, j]) for j > k, else 0
+  double sc[2];               // beta, scale
+  double tau[PB];
+  double Zs[PB][PB + 1];      // Zs[k][c] = (V^T v_k)[c] for c < k
+  double Tw[PB][PB + 1];
+};
+
+template <int CTRL>
+__device__ inline double dpp_d(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp((int)(b & 0xffffffffll), (int)(b & 0xffffffffll),
+                                             CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(b >> 32), (int)(b >> 32), CTRL, 0xf, 0xf,
+                                             false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
-// Householder QR of an r x w block held in LDS (A[i * lda + j]), r <= 512, w <= 32.
-// Reflector k: v = (1, A[k+1..r-1][k]) stored below the diagonal, tau[k]; R on and above.
-// Thread (g, j) = (tid / PB, tid % PB) works on rows i = g (mod NG) of column j.
-__device__ void lds_householder(double* A, int lda, int r, int w, double* tau, double* red) {
-  const int tid = threadIdx.x, g = tid / PB, j = tid % PB;
+// Householder QR of an r x w block (r <= 64 RPR, w <= PB).  Thread t = NCG g + cg holds rows
+// g RPR + i (i < RPR) at columns CPT cg + jj (jj < CPT) in a[i][jj].  On return the rows hold
+// R on and above the diagonal and the reflectors v below it (unit diagonal implied); L.Tw holds
+// Tw (zero outside the kmax x kmax upper triangle).
+//
+// Step k: the pivot column reaches the other threads of a row group by quad broadcasts; the
+// sums s_c = sum_{i>k} A[i][c] A[i][k] are reduced inside each 16-lane row by DPP rotations
+// and across rows and waves in LDS by 32 threads, which then form the reflector (s_k is the
+// squared norm below the diagonal), the update coefficients of the trailing columns and
+// z = V^T v_k for the Tw recurrence.
+template <int RPR>
+__device__ void panel_factor(double (&a)[RPR][CPT], int r, int w, PanelLds& L) {
+  const int t = threadIdx.x, cg = t % NCG, g = t / NCG;
+  const int lane = t & 63, wave = t >> 6;
   const int kmax = min(r, w);
+  for (int e = t; e < PB * PB; e += NTH) L.Tw[e / PB][e % PB] = 0.0;
   for (int k = 0; k < kmax; ++k) {
-    double part = 0.0;
-    if (j == 0)
-      for (int i = first_row(k + 1, g); i < r; i += NG) {
-        double x = A[i * lda + k];
-        part += x * x;
+    const int cgk = k / CPT, jk = k % CPT;
+    double x[RPR];
+#pragma unroll
+    for (int i = 0; i < RPR; ++i) {
+      const int row = g * RPR + i;
+      double mine = 0.0;
+#pragma unroll
+      for (int jj = 0; jj < CPT; ++jj)
+        if (jj == jk) mine = a[i][jj];
+      if (row == k) {
+#pragma unroll
+        for (int jj = 0; jj < CPT; ++jj) L.prow[CPT * cg + jj] = a[i][jj];
       }
-    if (j == 0) red[g] = part;
-    __syncthreads();
-    double sigma = 0.0;
-    for (int q = 0; q < NG; ++q) sigma += red[q];
-    const double alpha = A[k * lda + k];
-    double beta, t, scale;
-    if (sigma == 0.0) {
-      beta = alpha;
-      t = 0.0;
-      scale = 0.0;
-    } else {
-      double nrm = sqrt(alpha * alpha + sigma);
-      beta = alpha <= 0.0 ? nrm : -nrm;
-      t = (beta - alpha) / beta;
-      scale = 1.0 / (alpha - beta);
+      const double b0 = dpp_d<0x00>(mine), b1 = dpp_d<0x55>(mine);  // quad lanes 0, 1
+      const double b2 = dpp_d<0xAA>(mine), b3 = dpp_d<0xFF>(mine);  // quad lanes 2, 3
+      x[i] = cgk == 0 ? b0 : (cgk == 1 ? b1 : (cgk == 2 ? b2 : b3));
     }
-    __syncthreads();
-    for (int i = k + 1 + tid; i < r; i += NTH) A[i * lda + k] *= scale;
-    if (tid == 0) {
-      A[k * lda + k] = beta;
-      tau[k] = t;
-    }
-    __syncthreads();
-    double s = 0.0;
-    if (j > k && j < w) {
-      if (g == 0) s = A[k * lda + j];
-      for (int i = first_row(k + 1, g); i < r; i += NG) s += A[i * lda + k] * A[i * lda + j];
-    }
-    red[NG + g * PB + j] = s;
-    __syncthreads();
-    if (j > k && j < w && t != 0.0) {
-      double tot = 0.0;
-      for (int q = 0; q < NG; ++q) tot += red[NG + q * PB + j];
-      tot *= t;
-      if (g == 0) A[k * lda + j] -= tot;
-      for (int i = first_row(k + 1, g); i < r; i += NG) A[i * lda + j] -= tot * A[i * lda + k];
-    }
-    __syncthreads();
-  }
-}
-
-// Apply the reflectors (V below the diagonal of an LDS block with leading dimension ldv,
-// taus in LDS) to E (r x 32, thread (g, j) holds rows g + NG*q in registers).
-// transpose = true: E <- H_{k-1} ... H_0 E (= Q^T E); false: E <- H_0 ... H_{k-1} E (= Q E).
-template <int RPT>
-__device__ void lds_apply(const double* V, int ldv, const double* tau, int r, int kmax,
-                          bool transpose, double (&E)[RPT], double* red) {
-  const int tid = threadIdx.x, g = tid / PB, j = tid % PB;
-  for (int step = 0; step < kmax; ++step) {
-    const int k = transpose ? step : kmax - 1 - step;
-    const double t = tau[k];
-    double s = 0.0;
+    double pr[CPT];
 #pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      int i = g + NG * q;
-      if (i < r && i >= k) s += (i == k ? 1.0 : V[i * ldv + k]) * E[q];
-    }
-    red[g * PB + j] = s;
-    __syncthreads();
-    double tot = 0.0;
-    for (int q = 0; q < NG; ++q) tot += red[q * PB + j];
-    tot *= t;
+    for (int jj = 0; jj < CPT; ++jj) pr[jj] = 0.0;
 #pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      int i = g + NG * q;
-      if (i < r && i >= k) E[q] -= tot * (i == k ? 1.0 : V[i * ldv + k]);
+    for (int i = 0; i < RPR; ++i) {
+      const int row = g * RPR + i;
+      if (row > k && row < r) {
+#pragma unroll
+        for (int jj = 0; jj < CPT; ++jj) pr[jj] += a[i][jj] * x[i];
+      }
+    }
+    // lanes cg, cg + 4, cg + 8, cg + 12 of each 16-lane row share a column group
+#pragma unroll
+    for (int jj = 0; jj < CPT; ++jj) {
+      pr[jj] += dpp_d<0x124>(pr[jj]);  // row_ror:4
+      pr[jj] += dpp_d<0x128>(pr[jj]);  // row_ror:8
+    }
+    if ((lane & 15) < NCG) {
+#pragma unroll
+      for (int jj = 0; jj < CPT; ++jj) L.part[wave * 4 + (lane >> 4)][CPT * cg + jj] = pr[jj];
     }
     __syncthreads();
-  }
-}
-
-// Level 1: chunk b of the panel (rows [b*CH, b*CH + rows) of P, w columns).
-__global__ __launch_bounds__(NTH) void tsqr_local(int n, int w, const double* __restrict__ P,
-                                                  long ldp, double* __restrict__ Vg,
-                                                  double* __restrict__ taug,
-                                                  double* __restrict__ Rstack) {
-  __shared__ double A[CH * (PB + 1)];
-  __shared__ double tau[PB];
-  __shared__ double red[NG + NG * PB];
-  const int b = blockIdx.x, r0 = b * CH, rows = min(CH, n - r0);
-  const int lda = PB + 1;
-  for (int e = threadIdx.x; e < CH * PB; e += NTH) {
-    int i = e / PB, j = e % PB;
-    A[i * lda + j] = (i < rows && j < w) ? P[(long)(r0 + i) * ldp + j] : 0.0;
+    if (t < PB) {
+      double sc = 0.0;
+#pragma unroll
+      for (int q = 0; q < NTH / 16; ++q) sc += L.part[q][t];
+      const double sigma = __shfl(sc, k, PB);
+      const double alpha = L.prow[k];
+      double beta, tau, scale;
+      if (sigma == 0.0) {
+        beta = alpha;
+        tau = 0.0;
+        scale = 0.0;
+      } else {
+        const double nrm = sqrt(alpha * alpha + sigma);
+        beta = alpha <= 0.0 ? nrm : -nrm;
+        tau = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
+      }
+      const double z = L.prow[t] + scale * sc;  // A[k][t] + v_k^T A[k+1:, t]
+      L.dvec[t] = t > k ? tau * z : 0.0;
+      if (t < k) L.Zs[k][t] = z;
+      if (t == 0) {
+        L.sc[0] = beta;
+        L.sc[1] = scale;
+        L.tau[k] = tau;
+      }
+    }
+    __syncthreads();
+    const double beta = L.sc[0], scale = L.sc[1];
+    double d[CPT];
+#pragma unroll
+    for (int jj = 0; jj < CPT; ++jj) d[jj] = L.dvec[CPT * cg + jj];
+#pragma unroll
+    for (int i = 0; i < RPR; ++i) {
+      const int row = g * RPR + i;
+      if (row == k) {
+#pragma unroll
+        for (int jj = 0; jj < CPT; ++jj)
+          a[i][jj] = (cg == cgk && jj == jk) ? beta : a[i][jj] - d[jj];
+      } else if (row > k && row < r) {
+        const double v = scale * x[i];
+#pragma unroll
+        for (int jj = 0; jj < CPT; ++jj)
+          a[i][jj] = (cg == cgk && jj == jk) ? v : a[i][jj] - d[jj] * v;
+      }
+    }
   }
   __syncthreads();
-  lds_householder(A, lda, rows, w, tau, red);
+  // Tw[c][c] = tau_c; Tw[c][k] = -tau_k sum_{c <= c' < k} Tw[c][c'] Zs[k][c'] (row c by thread c)
+  if (t < kmax) {
+    L.Tw[t][t] = L.tau[t];
+    for (int k = t + 1; k < kmax; ++k) {
+      double s = 0.0;
+#pragma unroll
+      for (int cp = 0; cp < PB; ++cp)
+        s += (cp >= t && cp < k) ? L.Tw[t][cp] * L.Zs[k][cp] : 0.0;
+      L.Tw[t][k] = -L.tau[k] * s;
+    }
+  }
+  __syncthreads();
+}
+
+template <int RPR>
+__device__ void panel_load(double (&a)[RPR][CPT], const double* __restrict__ src, long ld, int r,
+                           int w) {
+  const int t = threadIdx.x, cg = t % NCG, g = t / NCG;
+#pragma unroll
+  for (int i = 0; i < RPR; ++i) {
+    const int row = g * RPR + i;
+#pragma unroll
+    for (int jj = 0; jj < CPT; ++jj) {
+      const int c = CPT * cg + jj;
+      a[i][jj] = (row < r && c < w) ? src[(long)row * ld + c] : 0.0;
+    }
+  }
+}
+
+// The reflectors below the diagonal (kmax of them) as a unit lower trapezoidal r x PB matrix
+// (zero above the diagonal and beyond kmax).
+template <int RPR>
+__device__ void panel_store_v(const double (&a)[RPR][CPT], double* __restrict__ dst, int r,
+                              int kmax) {
+  const int t = threadIdx.x, cg = t % NCG, g = t / NCG;
+#pragma unroll
+  for (int i = 0; i < RPR; ++i) {
+    const int row = g * RPR + i;
+    if (row < r) {
+#pragma unroll
+      for (int jj = 0; jj < CPT; ++jj) {
+        const int c = CPT * cg + jj;
+        dst[(long)row * PB + c] = c < kmax ? (row > c ? a[i][jj] : (row == c ? 1.0 : 0.0)) : 0.0;
+      }
+    }
+  }
+}
+
+// Rows < PB of R (upper triangle of the first kmax rows, columns < w) with row stride ldr;
+// ``full`` writes zeros for the other entries of the PB x PB block, otherwise only columns < w.
+template <int RPR>
+__device__ void panel_store_r(const double (&a)[RPR][CPT], double* __restrict__ dst, long ldr,
+                              int kmax, int w, bool full) {
+  const int t = threadIdx.x, cg = t % NCG, g = t / NCG;
+#pragma unroll
+  for (int i = 0; i < RPR; ++i) {
+    const int row = g * RPR + i;
+    if (row < (full ? PB : w)) {
+#pragma unroll
+      for (int jj = 0; jj < CPT; ++jj) {
+        const int c = CPT * cg + jj;
+        const double v = (row < kmax && c >= row && c < w) ? a[i][jj] : 0.0;
+        if (full || c < w) dst[(long)row * ldr + c] = v;
+      }
+    }
+  }
+}
+
+// Level 1: chunk b of the panel (rows [b*CH, b*CH + rows) of P, w columns).  Writes the
+// reflectors (unit lower trapezoidal, zero above) to Vg rows, Tw to Twg[b] and the chunk's R
+// (PB x PB, zero below the diagonal and beyond kmax) to Rstack[b].
+__global__ __launch_bounds__(NTH) void tsqr_local(int nr, int w, const double* __restrict__ P,
+                                                  long ldp, double* __restrict__ Vg,
+                                                  double* __restrict__ Twg,
+                                                  double* __restrict__ Rstack) {
+  __shared__ PanelLds L;
+  constexpr int RPR = CH / (NTH / NCG);
+  const int b = blockIdx.x, r0 = b * CH, rows = min(CH, nr - r0), t = threadIdx.x;
+  double a[RPR][CPT];
+  panel_load<RPR>(a, P + (long)r0 * ldp, ldp, rows, w);
+  panel_factor<RPR>(a, rows, w, L);
   const int kmax = min(rows, w);
-  for (int e = threadIdx.x; e < rows * PB; e += NTH) {
-    int i = e / PB, j = e % PB;
-    Vg[(long)(r0 + i) * PB + j] = (j < kmax && i > j) ? A[i * lda + j] : 0.0;
-  }
-  if (threadIdx.x < PB) taug[b * PB + threadIdx.x] = threadIdx.x < kmax ? tau[threadIdx.x] : 0.0;
-  for (int e = threadIdx.x; e < PB * PB; e += NTH) {
-    int i = e / PB, j = e % PB;
-    Rstack[(long)(b * PB + i) * PB + j] = (i < rows && j >= i && j < w) ? A[i * lda + j] : 0.0;
-  }
+  panel_store_r<RPR>(a, Rstack + (long)b * PB * PB, PB, kmax, w, true);
+  double* Tw = Twg + (long)b * PB * PB;
+  for (int e = t; e < PB * PB; e += NTH) Tw[e] = L.Tw[e / PB][e % PB];
+  panel_store_v<RPR>(a, Vg + (long)r0 * PB, rows, kmax);
 }
 
 // Level 2: QR of the stacked R factors (nch*PB x w) by one workgroup; R (w x w) goes to T,
-// the reflectors to V2 (nch*PB x PB) and tau2.
+// the reflectors to V2 (nch*PB x PB) and the WY factor to Tw2.
 __global__ __launch_bounds__(NTH) void tsqr_stack(int nch, int w, const double* __restrict__ Rstack,
                                                   double* __restrict__ T, long ldt,
                                                   double* __restrict__ V2,
-                                                  double* __restrict__ tau2) {
-  __shared__ double A[MAXCH * PB * (PB + 1)];
-  __shared__ double tau[PB];
-  __shared__ double red[NG + NG * PB];
-  const int r = nch * PB, lda = PB + 1;
-  for (int e = threadIdx.x; e < r * PB; e += NTH) {
-    int i = e / PB, j = e % PB;
-    A[i * lda + j] = j < w ? Rstack[(long)i * PB + j] : 0.0;
-  }
-  __syncthreads();
-  lds_householder(A, lda, r, w, tau, red);
+                                                  double* __restrict__ Tw2) {
+  __shared__ PanelLds L;
+  constexpr int RPR = MAXCH * PB / (NTH / NCG);
+  const int r = nch * PB, t = threadIdx.x;
+  double a[RPR][CPT];
+  panel_load<RPR>(a, Rstack, PB, r, w);
+  panel_factor<RPR>(a, r, w, L);
   const int kmax = min(r, w);
-  for (int e = threadIdx.x; e < w * w; e += NTH) {
-    int i = e / w, j = e % w;
-    T[(long)i * ldt + j] = j >= i ? A[i * lda + j] : 0.0;
-  }
-  for (int e = threadIdx.x; e < r * PB; e += NTH) {
-    int i = e / PB, j = e % PB;
-    V2[(long)i * PB + j] = (j < kmax && i > j) ? A[i * lda + j] : 0.0;
-  }
-  if (threadIdx.x < PB) tau2[threadIdx.x] = threadIdx.x < kmax ? tau[threadIdx.x] : 0.0;
+  panel_store_r<RPR>(a, T, ldt, kmax, w, false);
+  for (int e = t; e < PB * PB; e += NTH) Tw2[e] = L.Tw[e / PB][e % PB];
+  panel_store_v<RPR>(a, V2, r, kmax);
 }
 
-// Apply the level-1 reflectors of every chunk to X (rows [0, n) of the panel's row range,
-// ncols columns starting at X): grid (nch, ceil(ncols/32)).
-__global__ __launch_bounds__(NTH) void apply_local(int n, int w, bool transpose,
-                                                   const double* __restrict__ Vg,
-                                                   const double* __restrict__ taug,
-                                                   double* __restrict__ X, long ldx, int ncols) {
-  __shared__ double V[CH * (PB + 1)];
-  __shared__ double tau[PB];
-  __shared__ double red[NG * PB];
-  const int b = blockIdx.x, r0 = b * CH, rows = min(CH, n - r0), ldv = PB + 1;
-  const int kmax = min(rows, w);
+__device__ inline f64x4 mfma_f64(double a, double b, f64x4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// X <- (I - V Tw V^T)^T X (trans) or (I - V Tw V^T) X on a set of rows of X and 32 columns
+// [32 blockIdx.y, ...).  STACK = false: the rows of chunk blockIdx.x (panel rows
+// [b*CH, b*CH + CH) clipped to nr), V = Vg rows of that chunk, Tw = Twg[b].  STACK = true:
+// the stacked rows i < nch*PB, i.e. panel row (i / PB) * CH + i % PB, V = V2, Tw = Tw2.
+// Y = V^T X, Y <- op(Tw) Y, X <- X - V Y, all on the FP64 matrix cores; wave w owns the
+// 16 x 16 tile (w / 2, w % 2) of Y.  Rows are staged through LDS in slabs of SL rows; when
+// all rows fit in one slab it is loaded once for both passes.
+template <bool STACK, int SL>
+__global__ __launch_bounds__(NTH) void apply_wy(int nr, int nch, bool trans,
+                                                const double* __restrict__ Vsrc,
+                                                const double* __restrict__ Twsrc,
+                                                double* __restrict__ X, long ldx, int ncols) {
+  __shared__ double Vs[SL][PB + 1];
+  __shared__ double Xs[SL][PB + 1];
+  __shared__ double Ys[PB][PB + 1];
+  __shared__ double Ts[PB][PB + 1];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int b = STACK ? 0 : blockIdx.x;
+  const int rows = STACK ? nch * PB : min(CH, nr - b * CH);
   const int c0 = blockIdx.y * PB;
-  for (int e = threadIdx.x; e < CH * PB; e += NTH) {
-    int i = e / PB, j = e % PB;
-    V[i * ldv + j] = i < rows ? Vg[(long)(r0 + i) * PB + j] : 0.0;
+  const double* V = STACK ? Vsrc : Vsrc + (long)b * CH * PB;
+  const double* Tw = STACK ? Twsrc : Twsrc + (long)b * PB * PB;
+  auto xrow = [&](int i) -> int {  // panel row of block row i, or -1
+    if (i >= rows) return -1;
+    const int g = STACK ? (i / PB) * CH + (i % PB) : b * CH + i;
+    return g < nr ? g : -1;
+  };
+  auto load_slab = [&](int k0) {
+    for (int e = t; e < SL * PB; e += NTH) {
+      const int i = e / PB, c = e % PB;
+      const int g = xrow(k0 + i);
+      Vs[i][c] = (k0 + i < rows) ? V[(long)(k0 + i) * PB + c] : 0.0;
+      Xs[i][c] = (g >= 0 && c0 + c < ncols) ? X[(long)g * ldx + c0 + c] : 0.0;
+    }
+  };
+  for (int e = t; e < PB * PB; e += NTH) Ts[e / PB][e % PB] = Tw[e];
+  const int ti = wave >> 1, tj = wave & 1;
+  const bool one_slab = rows <= SL;
+  f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < rows; k0 += SL) {
+    load_slab(k0);
+    __syncthreads();
+#pragma unroll 8
+    for (int kk = 0; kk < SL; kk += 4)
+      acc = mfma_f64(Vs[kk + lk][16 * ti + lr], Xs[kk + lk][16 * tj + lr], acc);
+    if (!one_slab) __syncthreads();
   }
-  if (threadIdx.x < PB) tau[threadIdx.x] = taug[b * PB + threadIdx.x];
-  constexpr int RPT = CH / NG;
-  double E[RPT];
-  const int g = threadIdx.x / PB, j = threadIdx.x % PB;
-  const bool colok = c0 + j < ncols;
+  // D layout (FP64 16x16x4): lane l, register i -> row 4 i + l / 16, column l % 16
 #pragma unroll
-  for (int q = 0; q < RPT; ++q) {
-    int i = g + NG * q;
-    E[q] = (i < rows && colok) ? X[(long)(r0 + i) * ldx + c0 + j] : 0.0;
+  for (int i = 0; i < 4; ++i) Ys[16 * ti + 4 * i + lk][16 * tj + lr] = acc[i];
+  __syncthreads();
+  f64x4 y2 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < PB; k += 4) {
+    const double aop = trans ? Ts[k + lk][16 * ti + lr] : Ts[16 * ti + lr][k + lk];
+    y2 = mfma_f64(aop, Ys[k + lk][16 * tj + lr], y2);
   }
   __syncthreads();
-  lds_apply<RPT>(V, ldv, tau, rows, kmax, transpose, E, red);
 #pragma unroll
-  for (int q = 0; q < RPT; ++q) {
-    int i = g + NG * q;
-    if (i < rows && colok) X[(long)(r0 + i) * ldx + c0 + j] = E[q];
-  }
-}
-
-// Apply the level-2 reflectors to the stacked rows (top PB rows of each chunk) of X:
-// grid ceil(ncols/32).
-__global__ __launch_bounds__(NTH) void apply_stack(int n, int nch, int w, bool transpose,
-                                                   const double* __restrict__ V2,
-                                                   const double* __restrict__ tau2,
-                                                   double* __restrict__ X, long ldx, int ncols) {
-  __shared__ double V[MAXCH * PB * (PB + 1)];
-  __shared__ double tau[PB];
-  __shared__ double red[NG * PB];
-  const int r = nch * PB, ldv = PB + 1;
-  const int kmax = min(r, w);
-  const int c0 = blockIdx.x * PB;
-  for (int e = threadIdx.x; e < r * PB; e += NTH) {
-    int i = e / PB, j = e % PB;
-    V[i * ldv + j] = V2[(long)i * PB + j];
-  }
-  if (threadIdx.x < PB) tau[threadIdx.x] = tau2[threadIdx.x];
-  constexpr int RPT = MAXCH * PB / NG;
-  double E[RPT];
-  const int g = threadIdx.x / PB, j = threadIdx.x % PB;
-  const bool colok = c0 + j < ncols;
-#pragma unroll
-  for (int q = 0; q < RPT; ++q) {
-    int i = g + NG * q;  // stack row: chunk i / PB, row i % PB of that chunk
-    int row = (i / PB) * CH + (i % PB);
-    E[q] = (i < r && row < n && colok) ? X[(long)row * ldx + c0 + j] : 0.0;
-  }
+  for (int i = 0; i < 4; ++i) Ys[16 * ti + 4 * i + lk][16 * tj + lr] = y2[i];
   __syncthreads();
-  lds_apply<RPT>(V, ldv, tau, r, kmax, transpose, E, red);
+  constexpr int WR = SL / 4;  // slab rows per wave in the update
+  for (int k0 = 0; k0 < rows; k0 += SL) {
+    if (!one_slab) {
+      load_slab(k0);
+      __syncthreads();
+    }
 #pragma unroll
-  for (int q = 0; q < RPT; ++q) {
-    int i = g + NG * q;
-    int row = (i / PB) * CH + (i % PB);
-    if (i < r && row < n && colok) X[(long)row * ldx + c0 + j] = E[q];
+    for (int rt = 0; rt < WR / 16; ++rt)
+#pragma unroll
+      for (int cj = 0; cj < 2; ++cj) {
+        const int r0 = WR * wave + 16 * rt;
+        f64x4 u = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < PB; k += 4) u = mfma_f64(Vs[r0 + lr][k + lk], Ys[k + lk][16 * cj + lr], u);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int li = r0 + 4 * i + lk, c = 16 * cj + lr;
+          const int g = xrow(k0 + li);
+          if (g >= 0 && c0 + c < ncols) X[(long)g * ldx + c0 + c] = Xs[li][c] - u[i];
+        }
+      }
+    if (!one_slab) __syncthreads();
   }
 }
 
@@ -274,9 +392,9 @@ size_t qr_workspace_bytes(int n, int p) {
   size_t s = 0;
   s += align_up((size_t)n * p * 8, 256);                       // working copy
   s += npan * align_up((size_t)n * PB * 8, 256);               // level-1 reflectors per panel
-  s += npan * align_up((size_t)MAXCH * PB * 8, 256);           // level-1 taus
+  s += npan * align_up((size_t)MAXCH * PB * PB * 8, 256);      // level-1 WY factors
   s += npan * align_up((size_t)MAXCH * PB * PB * 8, 256);      // level-2 reflectors
-  s += npan * align_up((size_t)PB * 8, 256);                   // level-2 taus
+  s += npan * align_up((size_t)PB * PB * 8, 256);              // level-2 WY factor
   s += align_up((size_t)MAXCH * PB * PB * 8, 256);             // stacked R factors
   return s + 4096;
 }
@@ -290,14 +408,14 @@ int qr(hipStream_t s, int n, int p, const double* F, long ldf, double* U, long l
   double* W = ws.take<double>((size_t)n * p);
   double* Rstack = ws.take<double>((size_t)MAXCH * PB * PB);
   if (!W || !Rstack) return LYAP_NO_MEMORY;
-  struct Pan { double *Vg, *taug, *V2, *tau2; };
+  struct Pan { double *Vg, *Twg, *V2, *Tw2; };
   Pan pans[4096 / PB];
   for (int j = 0; j < npan; ++j) {
     pans[j].Vg = ws.take<double>((size_t)n * PB);
-    pans[j].taug = ws.take<double>((size_t)MAXCH * PB);
+    pans[j].Twg = ws.take<double>((size_t)MAXCH * PB * PB);
     pans[j].V2 = ws.take<double>((size_t)MAXCH * PB * PB);
-    pans[j].tau2 = ws.take<double>(PB);
-    if (!pans[j].Vg || !pans[j].taug || !pans[j].V2 || !pans[j].tau2) return LYAP_NO_MEMORY;
+    pans[j].Tw2 = ws.take<double>((size_t)PB * PB);
+    if (!pans[j].Vg || !pans[j].Twg || !pans[j].V2 || !pans[j].Tw2) return LYAP_NO_MEMORY;
   }
   LYAP_TRY(copy_block(s, n, p, F, ldf, W, p));
   hipLaunchKernelGGL(zero_block, dim3(nb256((long)kk * p)), dim3(256), 0, s, kk, p, T, ldt);
@@ -305,16 +423,17 @@ int qr(hipStream_t s, int n, int p, const double* F, long ldf, double* U, long l
     const int c = j * PB, w = std::min(PB, kk - c), nr = n - c, nch = ceil_div(nr, CH);
     double* P = W + (long)c * p + c;  // rows [c, n), columns [c, c+w)
     hipLaunchKernelGGL(tsqr_local, dim3(nch), dim3(NTH), 0, s, nr, w, P, (long)p, pans[j].Vg,
-                       pans[j].taug, Rstack);
+                       pans[j].Twg, Rstack);
     hipLaunchKernelGGL(tsqr_stack, dim3(1), dim3(NTH), 0, s, nch, w, Rstack,
-                       T + (long)c * ldt + c, ldt, pans[j].V2, pans[j].tau2);
+                       T + (long)c * ldt + c, ldt, pans[j].V2, pans[j].Tw2);
     const int rest = p - c - w;
     if (rest > 0) {
       double* X = P + w;  // rows [c, n), columns [c+w, p)
-      hipLaunchKernelGGL(apply_local, dim3(nch, ceil_div(rest, PB)), dim3(NTH), 0, s, nr, w, true,
-                         pans[j].Vg, pans[j].taug, X, (long)p, rest);
-      hipLaunchKernelGGL(apply_stack, dim3(ceil_div(rest, PB)), dim3(NTH), 0, s, nr, nch, w, true,
-                         pans[j].V2, pans[j].tau2, X, (long)p, rest);
+      const unsigned ct = (unsigned)ceil_div(rest, PB);
+      hipLaunchKernelGGL((apply_wy<false, CH>), dim3(nch, ct), dim3(NTH), 0, s, nr, nch, true,
+                         pans[j].Vg, pans[j].Twg, X, (long)p, rest);
+      hipLaunchKernelGGL((apply_wy<true, SL_STACK>), dim3(1, ct), dim3(NTH), 0, s, nr, nch, true,
+                         pans[j].V2, pans[j].Tw2, X, (long)p, rest);
       hipLaunchKernelGGL(copy_rows, dim3(nb256((long)w * rest)), dim3(256), 0, s, w, rest, X,
                          (long)p, T + (long)c * ldt + c + w, ldt);
     }
@@ -323,13 +442,14 @@ int qr(hipStream_t s, int n, int p, const double* F, long ldf, double* U, long l
   // U = Q_1 ... Q_k [I_kk; 0]
   hipLaunchKernelGGL(eye_block, dim3(nb256((long)n * kk)), dim3(256), 0, s, n, kk, U, ldu);
   for (int j = npan - 1; j >= 0; --j) {
-    const int c = j * PB, w = std::min(PB, kk - c), nr = n - c, nch = ceil_div(nr, CH);
+    const int c = j * PB, nr = n - c, nch = ceil_div(nr, CH);
     const int cols = kk - c;
+    const unsigned ct = (unsigned)ceil_div(cols, PB);
     double* X = U + (long)c * ldu + c;
-    hipLaunchKernelGGL(apply_stack, dim3(ceil_div(cols, PB)), dim3(NTH), 0, s, nr, nch, w, false,
-                       pans[j].V2, pans[j].tau2, X, ldu, cols);
-    hipLaunchKernelGGL(apply_local, dim3(nch, ceil_div(cols, PB)), dim3(NTH), 0, s, nr, w, false,
-                       pans[j].Vg, pans[j].taug, X, ldu, cols);
+    hipLaunchKernelGGL((apply_wy<true, SL_STACK>), dim3(1, ct), dim3(NTH), 0, s, nr, nch, false,
+                       pans[j].V2, pans[j].Tw2, X, ldu, cols);
+    hipLaunchKernelGGL((apply_wy<false, CH>), dim3(nch, ct), dim3(NTH), 0, s, nr, nch, false,
+                       pans[j].Vg, pans[j].Twg, X, ldu, cols);
     LYAP_HIP(hipGetLastError());
   }
   return LYAP_OK;
