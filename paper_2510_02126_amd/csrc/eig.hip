@@ -3,15 +3,20 @@
 //
 // The matrix (padded to a multiple of 32 with zero rows/columns, which stay decoupled) is cut
 // into blocks of 16 indices.  A sweep visits every pair of blocks once in a round-robin
-// tournament (nb - 1 rounds of nb / 2 disjoint pairs).  Per round:
-//   jac_solve : one workgroup per pair runs cyclic Jacobi sweeps on its 32 x 32 diagonal
-//               subproblem in LDS (16 disjoint rotations per inner step) and stores the
-//               accumulated 32 x 32 rotation R_p;
-//   jac_apply : A <- G^T A G and V <- V G, with G the block-diagonal (in pair order) of the
-//               R_p; block (p, q) of A becomes R_p^T A_pq R_q, computed independently per
-//               block by one workgroup, and each 32 x 32 tile of V is multiplied by R_q.
-// Sweeps repeat until ||offdiag(A)||_F <= tol ||A||_F.  Eigenvalues are then sorted by
-// descending magnitude (ties by index) and the eigenvectors gathered accordingly.
+// tournament (nb - 1 rounds of nb / 2 disjoint pairs).  Round r computes, for each of its
+// pairs, the 32 x 32 orthogonal R_p that diagonalises the pair's subproblem (one cyclic Jacobi
+// sweep in LDS), and then A <- G^T A G, V <- V G with G the block-diagonal (in pair order) of
+// the R_p: block (p, q) of A becomes R_p^T A_pq R_q (FP64 matrix cores).
+//
+// One kernel per round, with A ping-ponged between two buffers: its first workgroups solve the
+// subproblems of round r + 1 while the others apply round r.  The subproblem of a round-(r+1)
+// pair is formed directly from the matrix before round r and round r's rotations (each of its
+// four 16 x 16 blocks is a slice of R_P^T A_PQ R_Q), so the solves do not wait for the update.
+//
+// Rotations are skipped when |a_pq| is below an absolute floor (tol ||A||_F / (4 pp)) or below
+// tol sqrt(|a_pp a_qq|).  Sweeps stop when ||offdiag(A)||_F <= tol ||A||_F or when the solves
+// of a whole sweep applied no rotation.  Eigenvalues are then sorted by descending magnitude
+// (ties by index) and the eigenvectors gathered accordingly.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -26,125 +31,235 @@ constexpr int HB = 16;        // block size (indices per block)
 constexpr int SB = 2 * HB;    // subproblem size
 constexpr int LDS_PAD = SB + 1;
 
-// Rotation zeroing a_pq of the 2 x 2 block [[app, apq], [apq, aqq]].  The rotation is skipped
-// (c = 1, s = 0) when |a_pq| <= thr (absolute floor) or |a_pq| <= eps sqrt(|a_pp a_qq|)
-// (relative to the coupled diagonal entries); returns whether it is applied.
+// Reciprocal and reciprocal square root from the hardware estimates refined by Newton steps
+// (each step roughly doubles the number of correct bits of the estimate).
+__device__ inline double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ inline double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double h = 0.5 * x * y;  // Newton step y <- y (3 - x y^2) / 2, twice
+  y = fma(y, fma(-h, y, 0.5), y);
+  h = 0.5 * x * y;
+  return fma(y, fma(-h, y, 0.5), y);
+}
+
+// Rotation zeroing a_pq of the 2 x 2 block [[app, apq], [apq, aqq]], or none (c = 1, s = 0)
+// when |a_pq| <= thr or |a_pq| <= eps sqrt(|a_pp a_qq|); returns whether it is applied.
+// t = tan(angle) is the smaller root of t^2 + 2 theta t - 1 = 0, c = 1 / sqrt(1 + t^2).
 __device__ inline bool rot_params(double app, double aqq, double apq, double thr, double eps,
                                   double& c, double& s) {
   const double a = fabs(apq);
-  if (a <= thr || a <= eps * sqrt(fabs(app) * fabs(aqq))) {
+  if (a <= thr || a * a <= eps * eps * fabs(app * aqq)) {
     c = 1.0;
     s = 0.0;
     return false;
   }
-  double theta = (aqq - app) / (2.0 * apq);
+  const double theta = (aqq - app) * recip(2.0 * apq);
+  const double at = fabs(theta);
   double t;
-  if (fabs(theta) > 1e150) t = 0.5 / theta;
-  else t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(1.0 + theta * theta));
-  c = 1.0 / sqrt(1.0 + t * t);
+  if (at > 1e150) {
+    t = 0.5 * recip(theta);
+  } else {
+    const double q = 1.0 + theta * theta;
+    const double h = q * rsqrt_nr(q);  // sqrt(1 + theta^2)
+    t = copysign(recip(at + h), theta);
+  }
+  c = rsqrt_nr(1.0 + t * t);
   s = t * c;
   return true;
 }
 
-// Index of the partner of position k in round r of a circle-method tournament on m slots
-// (m even): slot 0 fixed, the others rotate.  Returns the element at slot k.
+// Element at slot k in round r of a circle-method tournament on m slots (m even): slot 0
+// fixed, the others rotate.
 __device__ inline int circle_elem(int slot, int r, int m) {
   if (slot == 0) return 0;
   return 1 + (slot - 1 + r) % (m - 1);
 }
 
-// One workgroup per pair: cyclic Jacobi on the 32 x 32 subproblem in LDS.  Each inner step
-// applies 16 disjoint rotations G_a; thread t owns the 2 x 2 blocks (pair a = t / 16 rows,
-// pair b = t % 16 columns) of S and R, which the step rewrites as G_a^T S_ab G_b and R_ab G_b.
-// Each thread computes the parameters of G_a and G_b itself from the diagonal blocks, reads
-// everything it needs, and writes only after a barrier (the diagonal blocks are owned by
-// other threads).
-__global__ __launch_bounds__(256) void jac_solve(int pp, const double* __restrict__ A,
-                                                 const int* __restrict__ pairs, int inner_sweeps,
-                                                 const double* __restrict__ thr_dev, double eps,
-                                                 double* __restrict__ Rout,
-                                                 int* __restrict__ applied) {
-  __shared__ double S[SB][LDS_PAD];
-  __shared__ double R[SB][LDS_PAD];
-  __shared__ int any;
-  const int pair = blockIdx.x, t = threadIdx.x;
-  if (t == 0) any = 0;
-  const int bI = pairs[2 * pair], bJ = pairs[2 * pair + 1];
-  const double thr = *thr_dev;
-  for (int e = t; e < SB * SB; e += 256) {
-    const int i = e / SB, j = e % SB;
-    const int gi = (i < HB ? bI * HB + i : bJ * HB + (i - HB));
-    const int gj = (j < HB ? bI * HB + j : bJ * HB + (j - HB));
-    S[i][j] = A[(long)gi * pp + gj];
-    R[i][j] = (i == j) ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  const int a = t / (SB / 2), b = t % (SB / 2);
-  for (int sw = 0; sw < inner_sweeps; ++sw) {
-    for (int r = 0; r < SB - 1; ++r) {
-      int p0 = circle_elem(a, r, SB), q0 = circle_elem(SB - 1 - a, r, SB);
-      if (p0 > q0) { const int x = p0; p0 = q0; q0 = x; }
-      int p1 = circle_elem(b, r, SB), q1 = circle_elem(SB - 1 - b, r, SB);
-      if (p1 > q1) { const int x = p1; p1 = q1; q1 = x; }
-      const double app = S[p0][p0], aqq = S[q0][q0], apq = S[p0][q0];
-      const double bpp = S[p1][p1], bqq = S[q1][q1], bpq = S[p1][q1];
-      const double m00 = S[p0][p1], m01 = S[p0][q1], m10 = S[q0][p1], m11 = S[q0][q1];
-      const double r00 = R[p0][p1], r01 = R[p0][q1], r10 = R[q0][p1], r11 = R[q0][q1];
-      double ca, sa, cb, sb;
-      if (rot_params(app, aqq, apq, thr, eps, ca, sa) && b == 0) any = 1;
-      rot_params(bpp, bqq, bpq, thr, eps, cb, sb);
-      // G_a^T M, then (G_a^T M) G_b
-      const double x00 = ca * m00 - sa * m10, x01 = ca * m01 - sa * m11;
-      const double x10 = sa * m00 + ca * m10, x11 = sa * m01 + ca * m11;
-      __syncthreads();
-      S[p0][p1] = x00 * cb - x01 * sb;
-      S[p0][q1] = x00 * sb + x01 * cb;
-      S[q0][p1] = x10 * cb - x11 * sb;
-      S[q0][q1] = x10 * sb + x11 * cb;
-      R[p0][p1] = r00 * cb - r01 * sb;
-      R[p0][q1] = r00 * sb + r01 * cb;
-      R[q0][p1] = r10 * cb - r11 * sb;
-      R[q0][q1] = r10 * sb + r11 * cb;
-      __syncthreads();
-    }
-  }
-  double* Ro = Rout + (long)pair * SB * SB;
-  for (int e = t; e < SB * SB; e += 256) Ro[e] = R[e / SB][e % SB];
-  if (t == 0 && any) atomicAdd(applied, 1);
-}
-
-// Blocks [0, np*np): A block (pair P rows, pair Q cols) <- R_P^T A_PQ R_Q.
-// Blocks [np*np, np*np + np*(pp/SB)): V tile (rows 32*t .., cols of pair Q) <- V_tile R_Q.
-// The 32 x 32 products run on the FP64 matrix cores (v_mfma_f64_16x16x4f64): wave w owns the
-// 16 x 16 output tile (w / 2, w % 2); operands are staged in LDS.
 __device__ inline f64x4 mfma_f64(double a, double b, f64x4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-__global__ __launch_bounds__(256) void jac_apply(int pp, int np, double* __restrict__ A,
+__device__ inline int gidx(int i, int bi, int bj) { return i < HB ? bi * HB + i : bj * HB + (i - HB); }
+
+// LDS of a round workgroup.  A solve uses S[0..1] and R[0..1] for the sweep and, while it
+// forms its subproblem, S[1] / R[1] / E as staging (X / RA / RB); an update workgroup uses
+// S[1], R[1], E and S[0].
+struct SolveLds {
+  double S[2][SB][LDS_PAD];  // subproblem, double-buffered by step parity
+  double R[2][SB][LDS_PAD];  // accumulated rotation
+  double E[SB][LDS_PAD];
+  int any;
+};
+
+// One cyclic Jacobi sweep on L.S[0] (R starts as I in L.R[0]); the result is in buffer 1
+// (SB - 1 = 31 steps, odd).  Thread t owns the 2 x 2 blocks (pair a = t / 16 rows,
+// pair b = t % 16 columns).  Lanes 0..15 of each wave compute the 16 rotations of the step
+// and the other lanes fetch theirs by lane permutation; every thread reads the current
+// buffer and writes its block of the other one, so a step needs a single barrier.
+__device__ void subproblem_sweep(SolveLds& L, double thr, double eps) {
+  const int t = threadIdx.x, lane = t & 63;
+  const int a = t / (SB / 2), b = t % (SB / 2);
+  for (int r = 0; r < SB - 1; ++r) {
+    const int cur = r & 1, nxt = cur ^ 1;
+    double c = 1.0, sn = 0.0;
+    if (lane < SB / 2) {
+      int p = circle_elem(lane, r, SB), q = circle_elem(SB - 1 - lane, r, SB);
+      if (p > q) { const int x = p; p = q; q = x; }
+      if (rot_params(L.S[cur][p][p], L.S[cur][q][q], L.S[cur][p][q], thr, eps, c, sn) &&
+          t == lane)
+        L.any = 1;
+    }
+    const double ca = __shfl(c, a), sa = __shfl(sn, a);
+    const double cb = __shfl(c, b), sb = __shfl(sn, b);
+    int p0 = circle_elem(a, r, SB), q0 = circle_elem(SB - 1 - a, r, SB);
+    if (p0 > q0) { const int x = p0; p0 = q0; q0 = x; }
+    int p1 = circle_elem(b, r, SB), q1 = circle_elem(SB - 1 - b, r, SB);
+    if (p1 > q1) { const int x = p1; p1 = q1; q1 = x; }
+    const double m00 = L.S[cur][p0][p1], m01 = L.S[cur][p0][q1];
+    const double m10 = L.S[cur][q0][p1], m11 = L.S[cur][q0][q1];
+    const double r00 = L.R[cur][p0][p1], r01 = L.R[cur][p0][q1];
+    const double r10 = L.R[cur][q0][p1], r11 = L.R[cur][q0][q1];
+    // G_a^T M G_b and R G_b
+    const double x00 = ca * m00 - sa * m10, x01 = ca * m01 - sa * m11;
+    const double x10 = sa * m00 + ca * m10, x11 = sa * m01 + ca * m11;
+    L.S[nxt][p0][p1] = x00 * cb - x01 * sb;
+    L.S[nxt][p0][q1] = x00 * sb + x01 * cb;
+    L.S[nxt][q0][p1] = x10 * cb - x11 * sb;
+    L.S[nxt][q0][q1] = x10 * sb + x11 * cb;
+    L.R[nxt][p0][p1] = r00 * cb - r01 * sb;
+    L.R[nxt][p0][q1] = r00 * sb + r01 * cb;
+    L.R[nxt][q0][p1] = r10 * cb - r11 * sb;
+    L.R[nxt][q0][q1] = r10 * sb + r11 * cb;
+    __syncthreads();
+  }
+}
+
+// Solve workgroup for pair j = (bI, bJ) of ``pn``: form its subproblem, run one sweep, store
+// the rotation to Rn[j].  With Rc == nullptr the subproblem is read from A directly; otherwise
+// A is the matrix before the round whose pairs ``pc`` and rotations Rc are given.
+__device__ void solve_pair(SolveLds& L, int pp, int np, const double* __restrict__ A,
+                           const int* __restrict__ pc, const double* __restrict__ Rc,
+                           const int* __restrict__ pn, int j, double thr, double eps,
+                           double* __restrict__ Rn, int* __restrict__ applied) {
+  const int t = threadIdx.x;
+  const int nI = pn[2 * j], nJ = pn[2 * j + 1];
+  double (&X)[SB][LDS_PAD] = L.S[1];
+  double (&RA)[SB][LDS_PAD] = L.R[1];
+  double (&RB)[SB][LDS_PAD] = L.E;
+  if (t == 0) L.any = 0;
+  for (int e = t; e < SB * SB; e += 256) {
+    const int i = e / SB, k = e % SB;
+    L.R[0][i][k] = (i == k) ? 1.0 : 0.0;
+  }
+  if (!Rc) {
+    for (int e = t; e < SB * SB; e += 256) {
+      const int i = e / SB, k = e % SB;
+      L.S[0][i][k] = A[(long)gidx(i, nI, nJ) * pp + gidx(k, nI, nJ)];
+    }
+  } else {
+    // block b of the new pair sits in current pair P(b) at half h(b)
+    int P[2], H[2];
+    for (int h = 0; h < 2; ++h) {
+      const int blk = h == 0 ? nI : nJ;
+      P[h] = 0;
+      H[h] = 0;
+      for (int k = 0; k < np; ++k) {
+        if (pc[2 * k] == blk) { P[h] = k; H[h] = 0; }
+        if (pc[2 * k + 1] == blk) { P[h] = k; H[h] = 1; }
+      }
+    }
+    for (int h1 = 0; h1 < 2; ++h1)
+      for (int h2 = 0; h2 < 2; ++h2) {
+        const int P1 = P[h1], P2 = P[h2];
+        const int aI = pc[2 * P1], aJ = pc[2 * P1 + 1], bI = pc[2 * P2], bJ = pc[2 * P2 + 1];
+        __syncthreads();
+        for (int e = t; e < SB * SB; e += 256) {
+          const int i = e / SB, k = e % SB;
+          X[i][k] = A[(long)gidx(i, aI, aJ) * pp + gidx(k, bI, bJ)];
+          RA[i][k] = Rc[(long)P1 * SB * SB + e];
+          RB[i][k] = Rc[(long)P2 * SB * SB + e];
+        }
+        __syncthreads();
+        // Y = X R_P2[:, half h2]  (32 x 16): thread (i = t / 8, columns 2 (t % 8) + {0, 1})
+        const int yi = t / 8, yc = 2 * (t % 8);
+        double y0 = 0.0, y1 = 0.0;
+        for (int k = 0; k < SB; ++k) {
+          const double x = X[yi][k];
+          y0 += x * RB[k][HB * H[h2] + yc];
+          y1 += x * RB[k][HB * H[h2] + yc + 1];
+        }
+        __syncthreads();
+        X[yi][yc] = y0;  // X now holds Y in its first 16 columns
+        X[yi][yc + 1] = y1;
+        __syncthreads();
+        // S block = R_P1[:, half h1]^T Y  (16 x 16): thread (i = t / 16, c = t % 16)
+        const int si = t / HB, sc = t % HB;
+        double s = 0.0;
+        for (int k = 0; k < SB; ++k) s += RA[k][HB * H[h1] + si] * X[k][sc];
+        L.S[0][HB * h1 + si][HB * h2 + sc] = s;
+      }
+  }
+  __syncthreads();
+  subproblem_sweep(L, thr, eps);
+  double* Ro = Rn + (long)j * SB * SB;
+  for (int e = t; e < SB * SB; e += 256) Ro[e] = L.R[1][e / SB][e % SB];
+  if (t == 0 && L.any) atomicAdd(applied, 1);
+}
+
+// First solve of the iteration (subproblems read from A).
+__global__ __launch_bounds__(256) void jac_solve0(int pp, int np, const double* __restrict__ A,
+                                                  const int* __restrict__ pn,
+                                                  const double* __restrict__ thr_dev, double eps,
+                                                  double* __restrict__ Rn,
+                                                  int* __restrict__ applied) {
+  __shared__ SolveLds L;
+  solve_pair(L, pp, np, A, nullptr, nullptr, pn, blockIdx.x, *thr_dev, eps, Rn, applied);
+}
+
+// One round.  Blocks [0, np): solves of the next round's pairs pn (rotations to Rn).
+// Blocks [np, np + np*np): Aout block (pair P rows, pair Q cols) = R_P^T Ain_PQ R_Q.
+// Blocks [np + np*np, ...): V tile (rows 32 t.., cols of pair Q) <- V_tile R_Q (in place).
+// The block products run on the FP64 matrix cores: wave w owns the 16 x 16 tile (w/2, w%2).
+__global__ __launch_bounds__(256) void jac_round(int pp, int np, const double* __restrict__ Ain,
+                                                 double* __restrict__ Aout,
                                                  double* __restrict__ V,
-                                                 const int* __restrict__ pairs,
-                                                 const double* __restrict__ Rall) {
-  __shared__ double M[SB][LDS_PAD];
-  __shared__ double RQ[SB][LDS_PAD];
-  __shared__ double RP[SB][LDS_PAD];
-  __shared__ double T1[SB][LDS_PAD];
-  const int blk = blockIdx.x;
+                                                 const int* __restrict__ pc,
+                                                 const double* __restrict__ Rc,
+                                                 const int* __restrict__ pn,
+                                                 double* __restrict__ Rn,
+                                                 const double* __restrict__ thr_dev, double eps,
+                                                 int* __restrict__ applied) {
+  __shared__ SolveLds L;
+  int blk = blockIdx.x;
+  if (blk < np) {
+    solve_pair(L, pp, np, Ain, pc, Rc, pn, blk, *thr_dev, eps, Rn, applied);
+    return;
+  }
+  blk -= np;
+  double (&M)[SB][LDS_PAD] = L.S[1];
+  double (&RQ)[SB][LDS_PAD] = L.E;
+  double (&RP)[SB][LDS_PAD] = L.R[1];
+  double (&T1)[SB][LDS_PAD] = L.S[0];
   const bool isA = blk < np * np;
   int P, Q, tile = 0;
   if (isA) { P = blk / np; Q = blk % np; }
-  else { int b2 = blk - np * np; Q = b2 % np; tile = b2 / np; P = 0; }
-  const int qI = pairs[2 * Q], qJ = pairs[2 * Q + 1];
-  const int pI = pairs[2 * P], pJ = pairs[2 * P + 1];
-  auto gidx = [](int i, int bi, int bj) { return i < HB ? bi * HB + i : bj * HB + (i - HB); };
-  const double* RQg = Rall + (long)Q * SB * SB;
-  const double* RPg = Rall + (long)P * SB * SB;
+  else { const int b2 = blk - np * np; Q = b2 % np; tile = b2 / np; P = 0; }
+  const int qI = pc[2 * Q], qJ = pc[2 * Q + 1];
+  const int pI = pc[2 * P], pJ = pc[2 * P + 1];
+  const double* RQg = Rc + (long)Q * SB * SB;
+  const double* RPg = Rc + (long)P * SB * SB;
   for (int e = threadIdx.x; e < SB * SB; e += 256) {
     const int i = e / SB, j = e % SB;
     RQ[i][j] = RQg[e];
     if (isA) {
       RP[i][j] = RPg[e];
-      M[i][j] = A[(long)gidx(i, pI, pJ) * pp + gidx(j, qI, qJ)];
+      M[i][j] = Ain[(long)gidx(i, pI, pJ) * pp + gidx(j, qI, qJ)];
     } else {
       M[i][j] = V[(long)(tile * SB + i) * pp + gidx(j, qI, qJ)];
     }
@@ -153,7 +268,6 @@ __global__ __launch_bounds__(256) void jac_apply(int pp, int np, double* __restr
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int ti = wave >> 1, tj = wave & 1;
   const int lr = lane & 15, lk = lane >> 4;
-  // T1 = M R_Q
   f64x4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int k0 = 0; k0 < SB; k0 += 4)
@@ -170,7 +284,6 @@ __global__ __launch_bounds__(256) void jac_apply(int pp, int np, double* __restr
 #pragma unroll
   for (int i = 0; i < 4; ++i) T1[16 * ti + 4 * i + lk][16 * tj + lr] = acc[i];
   __syncthreads();
-  // out = R_P^T T1
   f64x4 out = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int k0 = 0; k0 < SB; k0 += 4)
@@ -178,7 +291,7 @@ __global__ __launch_bounds__(256) void jac_apply(int pp, int np, double* __restr
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int r = 16 * ti + 4 * i + lk, c = 16 * tj + lr;
-    A[(long)gidx(r, pI, pJ) * pp + gidx(c, qI, qJ)] = out[i];
+    Aout[(long)gidx(r, pI, pJ) * pp + gidx(c, qI, qJ)] = out[i];
   }
 }
 
@@ -193,18 +306,17 @@ __global__ void jac_load(int p, int pp, const double* __restrict__ H, long ldh,
   V[idx] = (i == j) ? 1.0 : 0.0;
 }
 
-// partial sums: [0] off-diagonal squares, [1] all squares
+// partial sums: [0] off-diagonal squares, [1] all squares (rows strided over blocks)
 __global__ void jac_norms(int pp, const double* __restrict__ A, double* __restrict__ part) {
   __shared__ double r0[256], r1[256];
   double off = 0.0, all = 0.0;
-  long total = (long)pp * pp;
-  for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < total; e += (long)gridDim.x * 256) {
-    int i = (int)(e / pp), j = (int)(e % pp);
-    double v = A[e];
-    double v2 = v * v;
-    all += v2;
-    if (i != j) off += v2;
-  }
+  for (int i = blockIdx.x; i < pp; i += gridDim.x)
+    for (int j = threadIdx.x; j < pp; j += 256) {
+      const double v = A[(long)i * pp + j];
+      const double v2 = v * v;
+      all += v2;
+      if (i != j) off += v2;
+    }
   r0[threadIdx.x] = off;
   r1[threadIdx.x] = all;
   __syncthreads();
@@ -222,7 +334,7 @@ __global__ void jac_norms(int pp, const double* __restrict__ A, double* __restri
 }
 
 // out[0] = ||offdiag||_F^2, out[1] = ||A||_F^2, out[2] = number of subproblems that applied a
-// rotation since the last call (the counter is reset).
+// rotation since the last call (the counter is reset); *thr_dev = thr_rel ||A||_F.
 __global__ void jac_norms_finish(int nparts, const double* __restrict__ part,
                                  double* __restrict__ out, double thr_rel,
                                  double* __restrict__ thr_dev, int* __restrict__ applied) {
@@ -238,8 +350,8 @@ __global__ void jac_norms_finish(int nparts, const double* __restrict__ part,
   *thr_dev = thr_rel * sqrt(all);
 }
 
-// Sort the first p diagonal entries by descending |value| (ties by index) and gather the
-// eigenvectors: one workgroup, rank computed by counting.
+// Sort the first p diagonal entries by descending |value| (ties by index): one workgroup, rank
+// computed by counting.
 __global__ __launch_bounds__(1024) void jac_sort(int p, int pp, const double* __restrict__ A,
                                                  int* __restrict__ perm, double* __restrict__ w) {
   __shared__ double dg[4096];
@@ -271,10 +383,10 @@ size_t syev_workspace_bytes(int p) {
   size_t pp = (size_t)ceil_div(p, SB) * SB;
   size_t nb = pp / HB, np = nb / 2;
   size_t s = 0;
-  s += 2 * align_up(pp * pp * 8, 256);
-  s += align_up(np * SB * SB * 8, 256);
+  s += 3 * align_up(pp * pp * 8, 256);
+  s += 2 * align_up(np * SB * SB * 8, 256);
   s += align_up((nb - 1) * np * 2 * 4 + 8, 256);
-  s += align_up(2 * 256 * 8, 256) + align_up(4 * 8, 256) + align_up(pp * 4, 256);
+  s += align_up(2 * 256 * 8, 256) + align_up(4 * 8, 256) + align_up(pp * 4, 256) + 256;
   return s + 4096;
 }
 
@@ -284,15 +396,17 @@ int syev(hipStream_t s, int p, const double* H, long ldh, double* w, double* V, 
   if (p > 4096) return LYAP_BADARG;
   const int pp = ceil_div(p, SB) * SB;
   const int nb = pp / HB, np = nb / 2, rounds = nb - 1;
-  double* Aw = ws.take<double>((size_t)pp * pp);
+  double* Aw[2] = {ws.take<double>((size_t)pp * pp), ws.take<double>((size_t)pp * pp)};
   double* Vw = ws.take<double>((size_t)pp * pp);
-  double* Rall = ws.take<double>((size_t)np * SB * SB);
+  double* Rb[2] = {ws.take<double>((size_t)np * SB * SB), ws.take<double>((size_t)np * SB * SB)};
   int* pairs = ws.take<int>((size_t)rounds * np * 2 + 2);
   double* part = ws.take<double>(2 * 256);
   double* scal = ws.take<double>(4);
   int* perm = ws.take<int>(pp);
   int* applied = ws.take<int>(1);
-  if (!Aw || !Vw || !Rall || !pairs || !part || !scal || !perm || !applied) return LYAP_NO_MEMORY;
+  if (!Aw[0] || !Aw[1] || !Vw || !Rb[0] || !Rb[1] || !pairs || !part || !scal || !perm ||
+      !applied)
+    return LYAP_NO_MEMORY;
   if (tol_rel <= 0.0) tol_rel = 1e-15;
   // round-robin schedule of block pairs (host-computed, uploaded once)
   std::vector<int> sched((size_t)rounds * np * 2);
@@ -307,12 +421,10 @@ int syev(hipStream_t s, int p, const double* H, long ldh, double* w, double* V, 
   LYAP_HIP(hipMemcpyAsync(pairs, sched.data(), sched.size() * sizeof(int), hipMemcpyHostToDevice,
                           s));
   hipLaunchKernelGGL(jac_load, dim3((unsigned)ceil_div(pp * pp, 256)), dim3(256), 0, s, p, pp, H,
-                     ldh, Aw, Vw);
+                     ldh, Aw[0], Vw);
   const int nparts = 64;
   double* thr = scal + 3;
-  // rotations are skipped when the entry is below tol / (4 pp) * ||A||_F, or below
-  // tol sqrt(|a_pp a_qq|)
-  hipLaunchKernelGGL(jac_norms, dim3(nparts), dim3(256), 0, s, pp, Aw, part);
+  hipLaunchKernelGGL(jac_norms, dim3(nparts), dim3(256), 0, s, pp, Aw[0], part);
   const double thr_rel = 0.25 * tol_rel / pp;
   hipLaunchKernelGGL(jac_norms_finish, dim3(1), dim3(1), 0, s, nparts, part, scal, thr_rel, thr,
                      applied);
@@ -323,19 +435,26 @@ int syev(hipStream_t s, int p, const double* H, long ldh, double* w, double* V, 
   LYAP_HIP(hipMemcpyAsync(host, scal, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
   LYAP_HIP(hipStreamSynchronize(s));
   const double total = host[1];
-  // Stop when ||offdiag||_F <= tol ||A||_F, or when a whole sweep found no entry worth a
-  // rotation (every |a_pq| below both skip thresholds).
+  int cur = 0, rc = 0;  // A in Aw[cur], rotations of the next round in Rb[rc]
+  bool solved = false;
   while (sweep < max_sweeps && np > 0) {
     if (host[0] <= tol_rel * tol_rel * total) break;
     if (sweep > 0 && host[2] == 0.0) break;
-    for (int r = 0; r < rounds; ++r) {
-      const int* pr = pairs + (size_t)r * np * 2;
-      hipLaunchKernelGGL(jac_solve, dim3(np), dim3(256), 0, s, pp, Aw, pr, 1, thr, tol_rel, Rall,
-                         applied);
-      hipLaunchKernelGGL(jac_apply, dim3(np * np + np * (pp / SB)), dim3(256), 0, s, pp, np, Aw,
-                         Vw, pr, Rall);
+    if (!solved) {
+      hipLaunchKernelGGL(jac_solve0, dim3(np), dim3(256), 0, s, pp, np, Aw[cur], pairs, thr,
+                         tol_rel, Rb[rc], applied);
+      solved = true;
     }
-    hipLaunchKernelGGL(jac_norms, dim3(nparts), dim3(256), 0, s, pp, Aw, part);
+    for (int r = 0; r < rounds; ++r) {
+      const int* pc = pairs + (size_t)r * np * 2;
+      const int* pn = pairs + (size_t)((r + 1) % rounds) * np * 2;
+      hipLaunchKernelGGL(jac_round, dim3(np + np * np + np * (pp / SB)), dim3(256), 0, s, pp, np,
+                         Aw[cur], Aw[cur ^ 1], Vw, pc, Rb[rc], pn, Rb[rc ^ 1], thr, tol_rel,
+                         applied);
+      cur ^= 1;
+      rc ^= 1;
+    }
+    hipLaunchKernelGGL(jac_norms, dim3(nparts), dim3(256), 0, s, pp, Aw[cur], part);
     hipLaunchKernelGGL(jac_norms_finish, dim3(1), dim3(1), 0, s, nparts, part, scal, thr_rel, thr,
                        applied);
     LYAP_HIP(hipGetLastError());
@@ -344,7 +463,7 @@ int syev(hipStream_t s, int p, const double* H, long ldh, double* w, double* V, 
     ++sweep;
   }
   if (sweeps_out) *sweeps_out = sweep;
-  hipLaunchKernelGGL(jac_sort, dim3(1), dim3(1024), 0, s, p, pp, Aw, perm, w);
+  hipLaunchKernelGGL(jac_sort, dim3(1), dim3(1024), 0, s, p, pp, Aw[cur], perm, w);
   hipLaunchKernelGGL(jac_gather, dim3((unsigned)ceil_div(p * p, 256)), dim3(256), 0, s, p, pp, Vw,
                      perm, V, ldv);
   LYAP_HIP(hipGetLastError());
