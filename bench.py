@@ -23,6 +23,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "fp16": 2500.0, "bf16": 2500.0}
+PEAK_HBM_GBS = 8000.0
 
 
 def _time_solves(lyap, torch, A, L, S, us, steps, warmup):
@@ -52,6 +53,28 @@ def _time_inverse(lyap, torch, A, us, reps=3):
     e1.record(stream)
     e1.synchronize()
     return e0.elapsed_time(e1) / reps / 1e3
+
+
+def _measured_traffic(kernel):
+    """HBM bytes per launch of ``kernel`` from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    summary, or None when there is none or the kernel's source changed since it was taken."""
+    import hashlib
+    import re
+
+    if kernel != "jac_round":
+        return None
+    path = os.path.join(ROOT, "profiles", "jac_round_n4096_ir_fp32_hbm_traffic.md")
+    src = os.path.join(ROOT, "paper_2510_02126_amd", "csrc", "eig.hip")
+    try:
+        text = open(path).read()
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    t = re.search(r"^traffic_bytes_per_launch: (\d+)", text, re.M)
+    h = re.search(r"^eig_hip_sha256: ([0-9a-f]+)", text, re.M)
+    if not t or not h or h.group(1) != digest:
+        return None
+    return float(t.group(1))
 
 
 def _cpu_baseline(cfg, steps=3):
@@ -111,11 +134,36 @@ def main():
     sps64 = args.steps / dt64 if ok64 else 0.0
     spsir = args.steps / dtir if okir else 0.0
 
+    # roofline of the dominant kernel family of the timed IR solves, from the HIP-event
+    # accounting the library keeps per solve (summed over the timed solves)
+    fam_ms = [sum(i["kern_ms"][f] for i in infir) for f in range(4)]
+    fam_work = [sum(i["kern_work"][f] for i in infir) for f in range(4)]
+    fam_calls = [sum(i["kern_calls"][f] for i in infir) for f in range(4)]
+    fams = {
+        0: ("inversion (Gauss-Jordan leaves + MFMA block updates, 2n^3 flops)", "mfma",
+            "TFLOP/s", 1e12, PEAK_TFLOPS["fp32" if args.us == "fp32" else args.us]),
+        1: ("jac_round (Jacobi round: block rotation update of A and V, 32 pp^2 bytes)",
+            "hbm", "GB/s", 1e9, PEAK_HBM_GBS),
+        2: ("thin QR (Householder TSQR panels + compact-WY MFMA updates)", "mfma", "TFLOP/s",
+            1e12, PEAK_TFLOPS["fp64"]),
+    }
+    dom = max(fams, key=lambda f: fam_ms[f])
+    name, bound, unit, scale, peak = fams[dom]
+    achieved = fam_work[dom] / (fam_ms[dom] * 1e-3) / scale if fam_ms[dom] > 0 else 0.0
+    traffic = _measured_traffic(name.split(" ")[0])
+    roof = {"bound": bound, "kernel": name, "achieved": round(achieved, 3), "peak": peak,
+            "unit": unit, "frac": round(achieved / peak, 4), "traffic": traffic,
+            "launches": fam_calls[dom], "avg_launch_us": round(1e3 * fam_ms[dom] /
+                                                                max(1, fam_calls[dom]), 2)}
+    breakdown = {}
+    for f, (nm, bd, un, sc, pk) in fams.items():
+        if fam_ms[f] > 0:
+            ach = fam_work[f] / (fam_ms[f] * 1e-3) / sc
+            breakdown[nm.split(" ")[0]] = {"ms_per_solve": round(fam_ms[f] / args.steps, 2),
+                                           "achieved": round(ach, 3), "unit": un,
+                                           "frac": round(ach / pk, 4)}
     t_inv = _time_inverse(lyap, torch, A, "fp64")
-    achieved = 2.0 * n ** 3 / t_inv / 1e12
-    roof = {"bound": "mfma", "kernel": "inversion (fp64 Gauss-Jordan, 2n^3 flops)",
-            "achieved": round(achieved, 3), "peak": PEAK_TFLOPS["fp64"], "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK_TFLOPS["fp64"], 4), "traffic": None}
+    inv64 = 2.0 * n ** 3 / t_inv / 1e12
 
     cpu = None
     if not args.skip_cpu:
@@ -155,6 +203,9 @@ def main():
                              "status": "OK" if ok64 else "DNF"},
         "speedup_ir_vs_fp64": round(spsir / sps64, 4) if sps64 > 0 and spsir > 0 else None,
         "roofline": roof,
+        "kernel_families_ir": breakdown,
+        "inversion_fp64_alone": {"ms": round(1e3 * t_inv, 3), "tflops": round(inv64, 3),
+                                 "frac_fp64_peak": round(inv64 / PEAK_TFLOPS["fp64"], 4)},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -87,6 +87,15 @@ typedef struct {
   double phase_ms[8];     /* 0 inversions, 1 Newton update+norms, 2 factor products,
                              3 in-solver truncation, 4 residual factorisation,
                              5 solution update, 6 other, 7 total                          */
+  /* Kernel families timed with HIP events on the solve's stream (for roofline reports):
+     0 inversions (work = 2 n^3 flops each), 1 Jacobi round kernels of the spectral
+     decompositions (work = bytes of A and V read and written by the block updates),
+     2 thin QR factorisations including the formation of U (work = Householder flops),
+     3 unused.  kern_ms is the summed event time, kern_calls the number of kernel
+     launches (family 1) or calls (families 0 and 2).                                    */
+  double kern_ms[4];
+  double kern_work[4];
+  int kern_calls[4];
 } lyap_info;
 
 typedef struct lyap_handle_s* lyap_handle;

@@ -48,7 +48,8 @@ class Info(ctypes.Structure):
                 ("newton_max", ctypes.c_int), ("inversions", ctypes.c_int),
                 ("refinements", ctypes.c_int), ("rank", ctypes.c_int), ("n_mu", ctypes.c_int),
                 ("mus", ctypes.c_double * 64), ("onenorm", ctypes.c_double * 64),
-                ("phase_ms", ctypes.c_double * 8)]
+                ("phase_ms", ctypes.c_double * 8), ("kern_ms", ctypes.c_double * 4),
+                ("kern_work", ctypes.c_double * 4), ("kern_calls", ctypes.c_int * 4)]
 
     def as_dict(self) -> dict:
         return {
@@ -63,6 +64,9 @@ class Info(ctypes.Structure):
             "mus": list(self.mus[: self.n_mu]),
             "onenorm": list(self.onenorm[: self.n_mu]),
             "phase_ms": list(self.phase_ms),
+            "kern_ms": list(self.kern_ms),
+            "kern_work": list(self.kern_work),
+            "kern_calls": list(self.kern_calls),
         }
 
 

@@ -33,6 +33,56 @@ void Arena::release() {
   top = 0;
 }
 
+int KernTimer::mark(hipStream_t s, hipEvent_t* e) {
+  if (pool.empty()) {
+    hipEvent_t x;
+    LYAP_HIP(hipEventCreate(&x));
+    pool.push_back(x);
+  }
+  *e = pool.back();
+  pool.pop_back();
+  LYAP_HIP(hipEventRecord(*e, s));
+  return LYAP_OK;
+}
+
+int KernTimer::collect() {
+  int code = LYAP_OK;
+  for (const Pending& q : pend) {
+    float t = 0.0f;
+    if (code == LYAP_OK && hipEventSynchronize(q.b) == hipSuccess &&
+        hipEventElapsedTime(&t, q.a, q.b) == hipSuccess) {
+      ms[q.fam] += t;
+      work[q.fam] += q.work;
+      calls[q.fam] += q.calls;
+    } else {
+      code = LYAP_HIP_ERROR;
+    }
+    pool.push_back(q.a);
+    pool.push_back(q.b);
+  }
+  pend.clear();
+  return code;
+}
+
+void KernTimer::reset() {
+  for (int f = 0; f < NF; ++f) {
+    ms[f] = 0.0;
+    work[f] = 0.0;
+    calls[f] = 0;
+  }
+  for (const Pending& q : pend) {
+    pool.push_back(q.a);
+    pool.push_back(q.b);
+  }
+  pend.clear();
+}
+
+void KernTimer::release() {
+  reset();
+  for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+  pool.clear();
+}
+
 }  // namespace lyap
 
 struct lyap_handle_s {

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <vector>
 #include <hip/hip_fp16.h>
 #include <hip/hip_bf16.h>
 
@@ -66,6 +67,34 @@ struct Arena {
     top = need;
     return reinterpret_cast<T*>(base + off);
   }
+  void release();
+};
+
+// Event timing of kernel families, for the roofline report of a solve: each timed interval
+// is a pair of events on the stream, resolved after the solve.  Families: 0 inversions
+// (work in flops, 2 n^3 each), 1 Jacobi round kernels (work in bytes, the A and V traffic of
+// the block update), 2 thin QR factorisations (work in flops), 3 unused.
+struct KernTimer {
+  static constexpr int NF = 4;
+  double ms[NF] = {0, 0, 0, 0};
+  double work[NF] = {0, 0, 0, 0};
+  int calls[NF] = {0, 0, 0, 0};
+  struct Pending {
+    hipEvent_t a, b;
+    int fam;
+    double work;
+    int calls;
+  };
+  std::vector<Pending> pend;
+  std::vector<hipEvent_t> pool;
+  // Records an event on s into *e (from the pool).
+  int mark(hipStream_t s, hipEvent_t* e);
+  void add(hipEvent_t a, hipEvent_t b, int fam, double work, int calls) {
+    pend.push_back({a, b, fam, work, calls});
+  }
+  // Waits for the pending intervals and accumulates them.
+  int collect();
+  void reset();
   void release();
 };
 

@@ -391,7 +391,7 @@ size_t syev_workspace_bytes(int p) {
 }
 
 int syev(hipStream_t s, int p, const double* H, long ldh, double* w, double* V, long ldv,
-         Arena& ws, double tol_rel, int* sweeps_out) {
+         Arena& ws, double tol_rel, int* sweeps_out, KernTimer* kt) {
   if (p <= 0) return LYAP_OK;
   if (p > 4096) return LYAP_BADARG;
   const int pp = ceil_div(p, SB) * SB;
@@ -445,6 +445,8 @@ int syev(hipStream_t s, int p, const double* H, long ldh, double* w, double* V, 
                          tol_rel, Rb[rc], applied);
       solved = true;
     }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (kt) LYAP_TRY(kt->mark(s, &e0));
     for (int r = 0; r < rounds; ++r) {
       const int* pc = pairs + (size_t)r * np * 2;
       const int* pn = pairs + (size_t)((r + 1) % rounds) * np * 2;
@@ -453,6 +455,11 @@ int syev(hipStream_t s, int p, const double* H, long ldh, double* w, double* V, 
                          applied);
       cur ^= 1;
       rc ^= 1;
+    }
+    if (kt) {
+      // block update traffic: A read and written, V read and written
+      LYAP_TRY(kt->mark(s, &e1));
+      kt->add(e0, e1, 1, (double)rounds * 32.0 * pp * pp, rounds);
     }
     hipLaunchKernelGGL(jac_norms, dim3(nparts), dim3(256), 0, s, pp, Aw[cur], part);
     hipLaunchKernelGGL(jac_norms_finish, dim3(1), dim3(1), 0, s, nparts, part, scal, thr_rel, thr,

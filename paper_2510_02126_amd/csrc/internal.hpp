@@ -12,7 +12,7 @@ size_t inverse_workspace_bytes(Prec op, int n);
 // pivot = false skips the pivot search (pivot row = diagonal row); valid when A is strictly
 // column diagonally dominant, where partial pivoting makes no interchanges.
 int invert(hipStream_t s, Prec op, int n, const double* A, long lda, double* out, long ldo,
-           Arena& ws, int* flags_dev, bool pivot = true);
+           Arena& ws, int* flags_dev, bool pivot = true, KernTimer* kt = nullptr);
 
 // ---- elem.hip
 int fill_int(hipStream_t s, int* p, int count, int value);
@@ -51,12 +51,12 @@ size_t qr_workspace_bytes(int n, int p);
 // Thin QR F = U T (U n x min(n,p) explicit, T min(n,p) x p upper trapezoidal); F is copied
 // first.
 int qr(hipStream_t s, int n, int p, const double* F, long ldf, double* U, long ldu, double* T,
-       long ldt, Arena& ws);
+       long ldt, Arena& ws, KernTimer* kt = nullptr);
 
 // ---- eig.hip
 size_t syev_workspace_bytes(int p);
 // H = V diag(w) V^T, w sorted by descending |w|.  ``sweeps_out`` (host, optional).
 int syev(hipStream_t s, int p, const double* H, long ldh, double* w, double* V, long ldv,
-         Arena& ws, double tol_rel, int* sweeps_out);
+         Arena& ws, double tol_rel, int* sweeps_out, KernTimer* kt = nullptr);
 
 }  // namespace lyap

@@ -529,11 +529,18 @@ size_t inverse_workspace_bytes(Prec op, int n) {
 // flags_dev[0] = singular pivot seen, flags_dev[1] = non-finite input/output (device ints,
 // zeroed by the caller).
 int invert(hipStream_t s, Prec op, int n, const double* A, long lda, double* out, long ldo,
-           Arena& ws, int* flags_dev, bool pivot) {
+           Arena& ws, int* flags_dev, bool pivot, KernTimer* kt) {
   if (n <= 0) return LYAP_OK;
   if (n > 8 * LEAF_THREADS) return LYAP_BADARG;
-  if (op == Prec::F64) return invert_t<double>(s, op, n, A, lda, out, ldo, ws, flags_dev, pivot);
-  return invert_t<float>(s, op, n, A, lda, out, ldo, ws, flags_dev, pivot);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (kt) LYAP_TRY(kt->mark(s, &e0));
+  if (op == Prec::F64) LYAP_TRY(invert_t<double>(s, op, n, A, lda, out, ldo, ws, flags_dev, pivot));
+  else LYAP_TRY(invert_t<float>(s, op, n, A, lda, out, ldo, ws, flags_dev, pivot));
+  if (kt) {
+    LYAP_TRY(kt->mark(s, &e1));
+    kt->add(e0, e1, 0, 2.0 * (double)n * n * n, 1);
+  }
+  return LYAP_OK;
 }
 
 }  // namespace lyap

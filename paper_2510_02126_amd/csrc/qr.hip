@@ -400,8 +400,10 @@ size_t qr_workspace_bytes(int n, int p) {
 }
 
 int qr(hipStream_t s, int n, int p, const double* F, long ldf, double* U, long ldu, double* T,
-       long ldt, Arena& ws) {
+       long ldt, Arena& ws, KernTimer* kt) {
   if (p <= 0 || n <= 0) return LYAP_OK;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (kt) LYAP_TRY(kt->mark(s, &e0));
   if (n > MAXCH * CH) return LYAP_BADARG;
   const int kk = std::min(n, p);  // U is n x kk, T is kk x p (upper trapezoidal)
   const int npan = ceil_div(kk, PB);
@@ -451,6 +453,12 @@ int qr(hipStream_t s, int n, int p, const double* F, long ldf, double* U, long l
     hipLaunchKernelGGL((apply_wy<false, CH>), dim3(nch, ct), dim3(NTH), 0, s, nr, nch, false,
                        pans[j].Vg, pans[j].Twg, X, ldu, cols);
     LYAP_HIP(hipGetLastError());
+  }
+  if (kt) {
+    // Householder factorisation 2 n k^2 - 2 k^3 / 3 and the same again to form U (k = kk)
+    LYAP_TRY(kt->mark(s, &e1));
+    const double k = kk;
+    kt->add(e0, e1, 2, 4.0 * n * k * k - 4.0 * k * k * k / 3.0, 1);
   }
   return LYAP_OK;
 }

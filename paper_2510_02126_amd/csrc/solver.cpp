@@ -45,6 +45,7 @@ void Solver::release() {
   for (DevBuf* b : all) b->release();
   for (auto& b : cache_) b.release();
   cache_.clear();
+  kt_.release();
 }
 
 namespace {
@@ -92,6 +93,7 @@ struct Solver::Ctx {
   lyap_info* info;
   double* scal;
   double* part;
+  KernTimer* kt = nullptr;
 };
 
 int Solver::upload_d(Ctx& c, const std::vector<double>& d, double* dst) {
@@ -129,7 +131,7 @@ int Solver::a_iteration(Ctx& c) {
     // ||A_{k-1} + I||_1 < 1 makes A_{k-1} strictly column diagonally dominant: partial
     // pivoting would pick the diagonal, so the pivot search is skipped (same result)
     const bool pivot = !(last_onenorm < 1.0);
-    LYAP_TRY(invert(s, c.us, n, Ak, n, out, n, *c.ws, c.flags, pivot));
+    LYAP_TRY(invert(s, c.us, n, Ak, n, out, n, *c.ws, c.flags, pivot, c.kt));
     if (c.us != Prec::F64) LYAP_TRY(cast_store(s, c.cstore, n, n, out, n, cache_[k - 1].p));
     LYAP_TRY(sumsq(s, n, n, out, n, scal + 1, c.part));
     LYAP_TRY(newton_mu(s, scal + 1, a_ss, scaling ? 1 : 0, scal + 2));
@@ -193,7 +195,7 @@ int Solver::rank_trunc(Ctx& c, double* Zb, long ldb, int& cols, std::vector<doub
   double* Vm = Vm_.as<double>();
   double* wv = wv_.as<double>();
   c.ws->reset();
-  LYAP_TRY(qr(s, n, cols, Zb, ldb, Uq, cap, Tq, cap, *c.ws));
+  LYAP_TRY(qr(s, n, cols, Zb, ldb, Uq, cap, Tq, cap, *c.ws, c.kt));
   LYAP_TRY(upload_d(c, d, dvec_.as<double>()));
   LYAP_TRY(copy_block(s, k, cols, Tq, cap, TN, cap, dvec_.as<double>()));
   GemmDesc g;
@@ -203,7 +205,7 @@ int Solver::rank_trunc(Ctx& c, double* Zb, long ldb, int& cols, std::vector<doub
   g.C = Hm; g.ldc = cap;
   LYAP_TRY(gemm_f64(s, g));
   c.ws->reset();
-  LYAP_TRY(syev(s, k, Hm, cap, wv, Vm, cap, *c.ws, std::max(10.0 * thr, 1e-15), nullptr));
+  LYAP_TRY(syev(s, k, Hm, cap, wv, Vm, cap, *c.ws, std::max(10.0 * thr, 1e-15), nullptr, c.kt));
   std::vector<double> lam(k);
   LYAP_HIP(hipMemcpyAsync(lam.data(), wv, k * sizeof(double), hipMemcpyDeviceToHost, s));
   LYAP_HIP(hipStreamSynchronize(s));
@@ -322,7 +324,7 @@ int Solver::res_fac(Ctx& c, const double* Zb, long ldb, int cols, const std::vec
   }
   LYAP_TRY(copy_block(s, n, m, c.L, c.ldl, F + 2 * cols, cap));
   c.ws->reset();
-  LYAP_TRY(qr(s, n, p, F, cap, Uq, cap, Tq, cap, *c.ws));
+  LYAP_TRY(qr(s, n, p, F, cap, Uq, cap, Tq, cap, *c.ws, c.kt));
   // TN = T N = [T2 D, T1 D, T3 S]
   LYAP_TRY(upload_d(c, d, dvec_.as<double>()));
   LYAP_TRY(upload_d(c, c.svec, dvec2_.as<double>()));
@@ -363,7 +365,7 @@ int Solver::res_factor(Ctx& c, int& rd, std::vector<double>& sd) {
   sd.clear();
   if (k == 0) return LYAP_OK;
   c.ws->reset();
-  LYAP_TRY(syev(s, k, Hm, cap, wv, Vm, cap, *c.ws, 1e-10, nullptr));
+  LYAP_TRY(syev(s, k, Hm, cap, wv, Vm, cap, *c.ws, 1e-10, nullptr, c.kt));
   std::vector<double> lam(k);
   LYAP_HIP(hipMemcpyAsync(lam.data(), wv, k * sizeof(double), hipMemcpyDeviceToHost, s));
   LYAP_HIP(hipStreamSynchronize(s));
@@ -404,7 +406,7 @@ int Solver::sol_upt(Ctx& c, int& cols, std::vector<double>& d, int cd,
   LYAP_TRY(copy_block(s, n, cols, Zc, cap, F, cap));
   LYAP_TRY(copy_block(s, n, cd, Zs_.as<double>(), cap, F + cols, cap));
   c.ws->reset();
-  LYAP_TRY(qr(s, n, q, F, cap, Uq, cap, Tq, cap, *c.ws));
+  LYAP_TRY(qr(s, n, q, F, cap, Uq, cap, Tq, cap, *c.ws, c.kt));
   std::vector<double> ups(d);
   ups.insert(ups.end(), dd.begin(), dd.end());
   LYAP_TRY(upload_d(c, ups, dvec_.as<double>()));
@@ -416,7 +418,7 @@ int Solver::sol_upt(Ctx& c, int& cols, std::vector<double>& d, int cd,
   g.C = Hm; g.ldc = cap;
   LYAP_TRY(gemm_f64(s, g));
   c.ws->reset();
-  LYAP_TRY(syev(s, k, Hm, cap, wv, Vm, cap, *c.ws, 0.0, nullptr));
+  LYAP_TRY(syev(s, k, Hm, cap, wv, Vm, cap, *c.ws, 0.0, nullptr, c.kt));
   std::vector<double> sig(k);
   LYAP_HIP(hipMemcpyAsync(sig.data(), wv, k * sizeof(double), hipMemcpyDeviceToHost, s));
   LYAP_HIP(hipStreamSynchronize(s));
@@ -461,6 +463,8 @@ int Solver::solve(hipStream_t s, Arena& ws, int* flags, int n, int m, const doub
   c.cstore = store_of(us);
   c.opt = opt;
   c.info = info;
+  kt_.reset();
+  c.kt = &kt_;
   c.svec.assign(m, 1.0);
   if (S) {
     LYAP_HIP(hipMemcpyAsync(c.svec.data(), S, m * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -584,6 +588,13 @@ int Solver::solve(hipStream_t s, Arena& ws, int* flags, int n, int m, const doub
   if (cols > 0)
     LYAP_HIP(hipMemcpyAsync(D, d.data(), cols * sizeof(double), hipMemcpyHostToDevice, s));
   LYAP_HIP(hipStreamSynchronize(s));
+  if (kt_.collect() == LYAP_OK) {
+    for (int f = 0; f < KernTimer::NF; ++f) {
+      info->kern_ms[f] = kt_.ms[f];
+      info->kern_work[f] = kt_.work[f];
+      info->kern_calls[f] = kt_.calls[f];
+    }
+  }
   info->phase_ms[7] = ms_since(t_start);
   return status;
 }

@@ -45,6 +45,7 @@ class Solver {
   DevBuf Zs_, Zc_, Zd_, F_, Uq_, Tq_, TN_, Hm_, Vm_, wv_, Gm_;
   std::vector<DevBuf> cache_;
   int last_k_ = 0;
+  KernTimer kt_;
 };
 
 }  // namespace lyap

@@ -35,3 +35,32 @@ def test_host_only_calls():
     # a NULL handle is rejected before any device work
     assert L.lyap_destroy(None) == 0
     assert L.lyap_inverse(None, None, 0, 1, 4, None, 4, None, 4) == 7
+
+
+def test_struct_layouts_match_header(tmp_path):
+    # compile a tiny host program against include/lyap.h and compare sizes and field offsets
+    # with the ctypes structures of the binding
+    import subprocess
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    src = tmp_path / "layout.c"
+    fields = {"lyap_info": [f for f, _ in _lib.Info._fields_],
+              "lyap_options": [f for f, _ in _lib.Options._fields_],
+              "lyap_precisions": [f for f, _ in _lib.Precisions._fields_]}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "lyap.h"', "int main(void) {"]
+    for st, fs in fields.items():
+        lines.append(f'  printf("{st} %zu\\n", sizeof({st}));')
+        for f in fs:
+            lines.append(f'  printf("{st}.{f} %zu\\n", offsetof({st}, {f}));')
+    lines += ["  return 0;", "}"]
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(root, "include"), str(src), "-o",
+                    str(exe)], check=True)
+    out = dict(l.rsplit(" ", 1) for l in
+               subprocess.run([str(exe)], check=True, capture_output=True, text=True)
+               .stdout.split("\n") if l)
+    for st, cls in (("lyap_info", _lib.Info), ("lyap_options", _lib.Options),
+                    ("lyap_precisions", _lib.Precisions)):
+        assert int(out[st]) == ctypes.sizeof(cls), st
+        for f, _ in cls._fields_:
+            assert int(out[f"{st}.{f}"]) == getattr(cls, f).offset, (st, f)
