@@ -137,6 +137,46 @@ int lyap_solve(lyap_handle h, void* stream, int n, int m, const double* A, int l
                const lyap_options* opt, double* Z, int ldz, int z_cap, double* D, int* rank,
                lyap_info* info);
 
+/*
+ * lyap_trace_loss -- loss = tr(C X C^T) for X = Z diag(D) Z^T: sum_j D_j ||C z_j||^2.
+ *  C  k x n FP64 row-major (ldc >= n); Z n x r (ldz >= r); D r values; loss: host double.
+ */
+int lyap_trace_loss(lyap_handle h, void* stream, int n, int k, const double* C, int ldc, int r,
+                    const double* Z, int ldz, const double* D, double* loss);
+
+/*
+ * lyap_trace_loss_grad -- gradients of scale * tr(C X C^T), X solving
+ * A X + X A^T + L diag(S) L^T = 0, from the factors X = Z diag(D) Z^T (r columns) and
+ * Y = ZY diag(DY) ZY^T (ry columns) of the adjoint solution A^T Y + Y A + C^T C = 0
+ * (lyap_solve_adjoint with L = C^T):
+ *   dA = 2 scale Y X (n x n, ldda), dL = 2 scale Y L diag(S) (n x m, lddl),
+ *   dS = scale diag(L^T Y L) (m), dC = 2 scale C X (k x n, lddc).
+ * S NULL means S = I.  Any of dA, dL, dS, dC may be NULL (not computed).  All products run
+ * on the FP64 matrix cores; only dA is dense n x n.  Device pointers, row-major; the call
+ * returns after the results are written.
+ */
+int lyap_trace_loss_grad(lyap_handle h, void* stream, int n, int m, int k, const double* L,
+                         int ldl, const double* S, const double* C, int ldc, int r,
+                         const double* Z, int ldz, const double* D, int ry, const double* ZY,
+                         int ldzy, const double* DY, double scale, double* dA, int ldda,
+                         double* dL, int lddl, double* dS, double* dC, int lddc);
+
+/*
+ * lyap_solve_adjoint -- the adjoint equation A^T Y + Y A + L diag(S) L^T = 0 of the same A,
+ * by the same method (Alg 2.2 with Alg 3.2 as the solver), for gradients of losses of X:
+ * with G = dloss/dX symmetric and Y solving A^T Y + Y A + G = 0, dloss/dA = 2 Y X and
+ * dloss/dL = 2 Y L diag(S).  Arguments, outputs and return codes as for lyap_solve
+ * (Y ~ Z diag(D) Z^T).  The sign iteration of A^T is the transpose of that of A, so when
+ * the previous lyap_solve on this handle was called with the same A (pointer, n, lda and
+ * ||A||_F) and the same u_s, its inverse sequence is replayed with transposed products and
+ * no inversion is computed (info->inversions = 0); the caller must not have modified A in
+ * between.  Otherwise the sequence is computed from A.
+ */
+int lyap_solve_adjoint(lyap_handle h, void* stream, int n, int m, const double* A, int lda,
+                       const double* L, int ldl, const double* S, lyap_precisions prec,
+                       const lyap_options* opt, double* Z, int ldz, int z_cap, double* D,
+                       int* rank, lyap_info* info);
+
 /* ---------------------------------------------------------------------------------
  * Component entry points.  Each runs one hot-path kernel family on the handle's stream
  * ordering; they exist so that each step of the path can be checked on its own.

@@ -15,6 +15,7 @@ Modules
   signnewton -- the scaled sign-function Newton iteration: the dense form (eq 3.1), the
                 factored Cholesky form (eq 3.2, Alg 3.1) and the factored LDL^T form
                 (eq 3.3, Alg 3.2) with their rank truncations and the stopping rule (3.4).
+  adjoint    -- gradients of tr(C X C^T) through the adjoint equation A^T Y + Y A + C^T C = 0.
   refine     -- the residual factorisations and solution updates (Fragments 2.1-2.4) and
                 the mixed-precision IR loops (Alg 2.1, Alg 2.2) with the Section 4.1
                 parameters and the stagnation test (4.2).

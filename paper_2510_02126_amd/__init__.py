@@ -6,6 +6,8 @@ current stream.  All arithmetic runs in the library's HIP kernels.
 
     solve(A, L, S=None, precisions=("fp16", "fp64", "fp64", "fp64"), tol=1e-13, ...)
         -> (Z, D, info) with X ~ Z diag(D) Z^T     (Alg 2.2 with Alg 3.2 as the solver)
+    solve_adjoint(A, L, S=None, ...)  -- A^T Y + Y A + L S L^T = 0, replaying the inverses
+    lyapunov_trace_loss(A, L, S, C)   -- tr(C X C^T), differentiable (adjoint backward)
     inverse(A, dtype, pivot) -- inversion at a solver precision (Gauss-Jordan)
     gemm(A, B, ...)          -- matrix-core product
     qr(F) -> (U, T)          -- thin QR of a tall matrix
@@ -20,7 +22,8 @@ import torch
 from . import _lib
 from ._lib import DTYPES, Info, LyapError, Options, Precisions
 
-__all__ = ["solve", "inverse", "gemm", "qr", "syev", "LyapError", "version"]
+__all__ = ["solve", "solve_adjoint", "trace_loss", "trace_loss_grad", "LyapunovTraceLoss",
+           "lyapunov_trace_loss", "inverse", "gemm", "qr", "syev", "LyapError", "version"]
 
 
 def _dev(*ts):
@@ -111,9 +114,7 @@ def syev(H: torch.Tensor):
     return w, V
 
 
-def solve(A, L, S=None, precisions=("fp16", "fp64", "fp64", "fp64"), tol=1e-13, refine=True,
-          z_cap=None, raise_on_error=True, **opts):
-    """Alg 2.2 (LDL^T-type mixed-precision IR) on the GPU.  Returns (Z, D, info)."""
+def _solve(fn_name, A, L, S, precisions, tol, refine, z_cap, raise_on_error, opts):
     dev = _dev(A, L, S)
     n = A.shape[0]
     m = L.shape[1]
@@ -135,11 +136,104 @@ def solve(A, L, S=None, precisions=("fp16", "fp64", "fp64", "fp64"), tol=1e-13, 
     prec = Precisions(*[DTYPES[p] for p in precisions])
     rank = ctypes.c_int(0)
     info = Info()
-    code = _lib.lib().lyap_solve(_lib.handle(dev), _stream(dev), n, m, _ptr(A), lda, _ptr(L), ldl,
-                                 _ptr(S), prec, ctypes.byref(o), _ptr(Z), z_cap, z_cap, _ptr(Dv),
-                                 ctypes.byref(rank), ctypes.byref(info))
+    fn = getattr(_lib.lib(), fn_name)
+    code = fn(_lib.handle(dev), _stream(dev), n, m, _ptr(A), lda, _ptr(L), ldl, _ptr(S), prec,
+              ctypes.byref(o), _ptr(Z), z_cap, z_cap, _ptr(Dv), ctypes.byref(rank),
+              ctypes.byref(info))
     d = info.as_dict()
     if code != 0 and raise_on_error and code not in (1, 2):
-        _lib.check(code, "lyap_solve")
+        _lib.check(code, fn_name)
     r = rank.value
     return Z[:, :r], Dv[:r], d
+
+
+def solve(A, L, S=None, precisions=("fp16", "fp64", "fp64", "fp64"), tol=1e-13, refine=True,
+          z_cap=None, raise_on_error=True, **opts):
+    """Alg 2.2 (LDL^T-type mixed-precision IR) on the GPU for A X + X A^T + L S L^T = 0.
+    Returns (Z, D, info) with X ~ Z diag(D) Z^T."""
+    return _solve("lyap_solve", A, L, S, precisions, tol, refine, z_cap, raise_on_error, opts)
+
+
+def solve_adjoint(A, L, S=None, precisions=("fp16", "fp64", "fp64", "fp64"), tol=1e-13,
+                  refine=True, z_cap=None, raise_on_error=True, **opts):
+    """The adjoint equation A^T Y + Y A + L S L^T = 0 (same method).  Replays the inverse
+    sequence of the previous ``solve`` on the same tensor A.  Returns (Z, D, info) with
+    Y ~ Z diag(D) Z^T."""
+    return _solve("lyap_solve_adjoint", A, L, S, precisions, tol, refine, z_cap, raise_on_error,
+                  opts)
+
+
+def trace_loss(C, Z, D):
+    """tr(C X C^T) for X = Z diag(D) Z^T (library kernels; returns a Python float)."""
+    dev = _dev(C, Z, D)
+    C, ldc = _rowmajor(C)
+    Z, ldz = _rowmajor(Z)
+    D = D.contiguous()
+    out = ctypes.c_double(0.0)
+    code = _lib.lib().lyap_trace_loss(_lib.handle(dev), _stream(dev), Z.shape[0], C.shape[0],
+                                      _ptr(C), ldc, Z.shape[1], _ptr(Z), ldz, _ptr(D),
+                                      ctypes.byref(out))
+    _lib.check(code, "lyap_trace_loss")
+    return out.value
+
+
+def trace_loss_grad(L, S, C, Z, D, ZY, DY, scale=1.0):
+    """(dA, dL, dS, dC) of scale * tr(C X C^T) from the factors of X and of the adjoint
+    solution Y (see lyap_trace_loss_grad in include/lyap.h); dS is None when S is None."""
+    dev = _dev(L, S, C, Z, D, ZY, DY)
+    L, ldl = _rowmajor(L)
+    C, ldc = _rowmajor(C)
+    Z, ldz = _rowmajor(Z)
+    ZY, ldzy = _rowmajor(ZY)
+    D, DY = D.contiguous(), DY.contiguous()
+    if S is not None:
+        S = S.contiguous()
+    n, m = L.shape
+    k = C.shape[0]
+    opts = dict(dtype=torch.float64, device=L.device)
+    dA = torch.empty((n, n), **opts)
+    dL = torch.empty((n, m), **opts)
+    dS = torch.empty(m, **opts) if S is not None else None
+    dC = torch.empty((k, n), **opts)
+    code = _lib.lib().lyap_trace_loss_grad(
+        _lib.handle(dev), _stream(dev), n, m, k, _ptr(L), ldl, _ptr(S), _ptr(C), ldc,
+        Z.shape[1], _ptr(Z), ldz, _ptr(D), ZY.shape[1], _ptr(ZY), ldzy, _ptr(DY),
+        float(scale), _ptr(dA), n, _ptr(dL), m, _ptr(dS), _ptr(dC), n)
+    _lib.check(code, "lyap_trace_loss_grad")
+    return dA, dL, dS, dC
+
+
+class LyapunovTraceLoss(torch.autograd.Function):
+    """loss = tr(C X C^T) with A X + X A^T + L diag(S) L^T = 0, differentiable in A, L, S and C.
+
+    The backward solves the adjoint equation A^T Y + Y A + C^T C = 0 with the same solver
+    (replaying the forward's inverse sequence) and forms dA = 2 Y X, dL = 2 Y L diag(S),
+    dS = diag(L^T Y L) and dC = 2 C X with the library's matrix-core products; Y and X stay
+    factored except in the dense dA.  Usage:
+    ``LyapunovTraceLoss.apply(A, L, S, C, precisions, tol)`` (S may be None: W = L L^T)."""
+
+    @staticmethod
+    def forward(ctx, A, L, S, C, precisions=("fp64", "fp64", "fp64", "fp64"), tol=1e-13):
+        Z, D, info = solve(A, L, S, precisions=precisions, tol=tol)
+        loss = trace_loss(C, Z, D)
+        ctx.save_for_backward(A, L, C, Z, D, *([S] if S is not None else []))
+        ctx.has_s = S is not None
+        ctx.precisions, ctx.tol = precisions, tol
+        ctx.info = info
+        return torch.tensor(loss, dtype=A.dtype, device=A.device)
+
+    @staticmethod
+    def backward(ctx, g):
+        saved = ctx.saved_tensors
+        A, L, C, Z, D = saved[:5]
+        S = saved[5] if ctx.has_s else None
+        ZY, DY, info = solve_adjoint(A, C.t().contiguous(), None, precisions=ctx.precisions,
+                                     tol=ctx.tol)
+        ctx.adjoint_info = info
+        dA, dL, dS, dC = trace_loss_grad(L, S, C, Z, D, ZY, DY, scale=float(g))
+        return dA, dL, dS, dC, None, None
+
+
+def lyapunov_trace_loss(A, L, S, C, precisions=("fp64", "fp64", "fp64", "fp64"), tol=1e-13):
+    """tr(C X C^T) for the solution X of A X + X A^T + L diag(S) L^T = 0 (autograd-aware)."""
+    return LyapunovTraceLoss.apply(A, L, S, C, precisions, tol)

@@ -85,6 +85,11 @@ _SIGS = {
     "lyap_version": (ctypes.c_char_p, []),
     "lyap_solve": (I, [P, P, I, I, P, I, P, I, P, Precisions, ctypes.POINTER(Options), P, I, I,
                        P, ctypes.POINTER(I), ctypes.POINTER(Info)]),
+    "lyap_trace_loss": (I, [P, P, I, I, P, I, I, P, I, P, ctypes.POINTER(D)]),
+    "lyap_trace_loss_grad": (I, [P, P, I, I, I, P, I, P, P, I, I, P, I, P, I, P, I, P, D, P, I,
+                                 P, I, P, P, I]),
+    "lyap_solve_adjoint": (I, [P, P, I, I, P, I, P, I, P, Precisions, ctypes.POINTER(Options), P,
+                               I, I, P, ctypes.POINTER(I), ctypes.POINTER(Info)]),
     "lyap_inverse": (I, [P, P, I, I, I, P, I, P, I]),
     "lyap_gemm": (I, [P, P, I, I, I, I, I, I, D, P, I, P, I, D, P, I]),
     "lyap_qr": (I, [P, P, I, I, P, I, P, I, P, I]),

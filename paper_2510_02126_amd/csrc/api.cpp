@@ -234,10 +234,12 @@ int lyap_syev(lyap_handle h, void* stream, int p, const double* H, int ldh, doub
   return LYAP_OK;
 }
 
-int lyap_solve(lyap_handle h, void* stream, int n, int m, const double* A, int lda,
-               const double* L, int ldl, const double* S, lyap_precisions prec,
-               const lyap_options* opt, double* Z, int ldz, int z_cap, double* D, int* rank,
-               lyap_info* info) {
+}  // extern "C"
+
+static int solve_impl(bool adjoint, lyap_handle h, void* stream, int n, int m, const double* A,
+                      int lda, const double* L, int ldl, const double* S, lyap_precisions prec,
+                      const lyap_options* opt, double* Z, int ldz, int z_cap, double* D,
+                      int* rank, lyap_info* info) {
   if (!h || n <= 0 || m <= 0 || m > n || !A || !L || !Z || !D || !rank || lda < n || ldl < m ||
       z_cap < 1 || ldz < z_cap)
     return LYAP_BADARG;
@@ -255,9 +257,160 @@ int lyap_solve(lyap_handle h, void* stream, int n, int m, const double* A, int l
   lyap_info* inf = info ? info : &local;
   std::memset(inf, 0, sizeof(*inf));
   int code = h->solver.solve((hipStream_t)stream, h->ws, h->flags, n, m, A, lda, L, ldl, S,
-                             (Prec)prec.u_s, o, Z, ldz, z_cap, D, rank, inf);
+                             (Prec)prec.u_s, o, Z, ldz, z_cap, D, rank, inf, adjoint);
   inf->status = code;
   return code;
+}
+
+
+extern "C" {
+
+int lyap_trace_loss(lyap_handle h, void* stream, int n, int k, const double* C, int ldc, int r,
+                    const double* Z, int ldz, const double* D, double* loss) {
+  if (!h || n <= 0 || k <= 0 || r < 0 || !loss || (r > 0 && (!C || !Z || !D)) || ldc < n ||
+      (r > 0 && ldz < r))
+    return LYAP_BADARG;
+  *loss = 0.0;
+  if (r == 0) return LYAP_OK;
+  hipStream_t s = (hipStream_t)stream;
+  LYAP_TRY(h->ws.reserve(((size_t)k * r + 64) * sizeof(double) + (1 << 20)));
+  h->ws.reset();
+  double* CZ = h->ws.take<double>((size_t)k * r);
+  double* out = h->ws.take<double>(1);
+  if (!CZ || !out) return LYAP_NO_MEMORY;
+  GemmDesc g;
+  g.M = k; g.N = r; g.K = n;
+  g.A = C; g.sar = ldc; g.sac = 1;
+  g.B = Z; g.sbr = ldz; g.sbc = 1;
+  g.C = CZ; g.ldc = r;
+  LYAP_TRY(gemm_f64(s, g));
+  LYAP_TRY(colw_sumsq(s, k, r, CZ, r, D, out));
+  LYAP_HIP(hipMemcpyAsync(loss, out, sizeof(double), hipMemcpyDeviceToHost, s));
+  LYAP_HIP(hipStreamSynchronize(s));
+  return LYAP_OK;
+}
+
+int lyap_trace_loss_grad(lyap_handle h, void* stream, int n, int m, int k, const double* L,
+                         int ldl, const double* S, const double* C, int ldc, int r,
+                         const double* Z, int ldz, const double* D, int ry, const double* ZY,
+                         int ldzy, const double* DY, double scale, double* dA, int ldda,
+                         double* dL, int lddl, double* dS, double* dC, int lddc) {
+  if (!h || n <= 0 || m <= 0 || k <= 0 || r < 0 || ry < 0 || !L || !C || ldl < m || ldc < n ||
+      (r > 0 && (!Z || !D || ldz < r)) || (ry > 0 && (!ZY || !DY || ldzy < ry)) ||
+      (dA && ldda < n) || (dL && lddl < m) || (dC && lddc < n))
+    return LYAP_BADARG;
+  hipStream_t s = (hipStream_t)stream;
+  const size_t need = (size_t)n * ry + (size_t)n * r + (size_t)ry * r + (size_t)n * r +
+                      2 * (size_t)ry * m + (size_t)k * r + (size_t)m + 64;
+  LYAP_TRY(h->ws.reserve(need * sizeof(double) + (16 << 20)));
+  h->ws.reset();
+  double* ZYD = h->ws.take<double>((size_t)n * std::max(ry, 1));   // ZY diag(DY)
+  double* ZD = h->ws.take<double>((size_t)n * std::max(r, 1));     // Z diag(D)
+  double* M = h->ws.take<double>((size_t)std::max(ry, 1) * std::max(r, 1));
+  double* P = h->ws.take<double>((size_t)n * std::max(r, 1));
+  double* N = h->ws.take<double>((size_t)std::max(ry, 1) * m);
+  double* NS = h->ws.take<double>((size_t)std::max(ry, 1) * m);
+  double* CZD = h->ws.take<double>((size_t)k * std::max(r, 1));
+  double* ones = h->ws.take<double>((size_t)m);
+  if (!ZYD || !ZD || !M || !P || !N || !NS || !CZD || !ones) return LYAP_NO_MEMORY;
+  if (r > 0) LYAP_TRY(copy_block(s, n, r, Z, ldz, ZD, r, D));
+  if (ry > 0) LYAP_TRY(copy_block(s, n, ry, ZY, ldzy, ZYD, ry, DY));
+  GemmDesc g;
+  if (dA) {
+    // dA = 2 Y X = 2 (ZY diag(DY)) (ZY^T (Z diag(D))) Z^T
+    if (r == 0 || ry == 0) {
+      LYAP_TRY(fill_f64(s, dA, (long)(n - 1) * ldda + n, 0.0));
+    } else {
+      g = GemmDesc();
+      g.M = ry; g.N = r; g.K = n;
+      g.A = ZY; g.sar = 1; g.sac = ldzy;
+      g.B = ZD; g.sbr = r; g.sbc = 1;
+      g.C = M; g.ldc = r;
+      LYAP_TRY(gemm_f64(s, g));
+      g = GemmDesc();
+      g.M = n; g.N = r; g.K = ry;
+      g.A = ZYD; g.sar = ry; g.sac = 1;
+      g.B = M; g.sbr = r; g.sbc = 1;
+      g.C = P; g.ldc = r;
+      LYAP_TRY(gemm_f64(s, g));
+      g = GemmDesc();
+      g.M = n; g.N = n; g.K = r;
+      g.alpha = 2.0 * scale;
+      g.A = P; g.sar = r; g.sac = 1;
+      g.B = Z; g.sbr = 1; g.sbc = ldz;
+      g.C = dA; g.ldc = ldda;
+      LYAP_TRY(gemm_f64(s, g));
+    }
+  }
+  if (dL || dS) {
+    // N = ZY^T L; dL = 2 ZY diag(DY) N diag(S); dS = diag(L^T Y L) = sum_j DY_j N_j.^2
+    if (ry > 0) {
+      g = GemmDesc();
+      g.M = ry; g.N = m; g.K = n;
+      g.A = ZY; g.sar = 1; g.sac = ldzy;
+      g.B = L; g.sbr = ldl; g.sbc = 1;
+      g.C = N; g.ldc = m;
+      LYAP_TRY(gemm_f64(s, g));
+    }
+    if (dL) {
+      if (ry == 0) {
+        LYAP_TRY(fill_f64(s, dL, (long)(n - 1) * lddl + m, 0.0));
+      } else {
+        if (!S) LYAP_TRY(fill_f64(s, ones, m, 1.0));
+        LYAP_TRY(copy_block(s, ry, m, N, m, NS, m, S ? S : ones));
+        g = GemmDesc();
+        g.M = n; g.N = m; g.K = ry;
+        g.alpha = 2.0 * scale;
+        g.A = ZYD; g.sar = ry; g.sac = 1;
+        g.B = NS; g.sbr = m; g.sbc = 1;
+        g.C = dL; g.ldc = lddl;
+        LYAP_TRY(gemm_f64(s, g));
+      }
+    }
+    if (dS) {
+      if (ry == 0) LYAP_TRY(fill_f64(s, dS, m, 0.0));
+      else LYAP_TRY(roww_colsumsq(s, ry, m, N, m, DY, dS));
+      if (scale != 1.0 && ry > 0) LYAP_TRY(copy_block(s, 1, m, dS, m, dS, m, nullptr, scale));
+    }
+  }
+  if (dC) {
+    // dC = 2 C X = 2 (C Z diag(D)) Z^T
+    if (r == 0) {
+      LYAP_TRY(fill_f64(s, dC, (long)(k - 1) * lddc + n, 0.0));
+    } else {
+      g = GemmDesc();
+      g.M = k; g.N = r; g.K = n;
+      g.A = C; g.sar = ldc; g.sac = 1;
+      g.B = ZD; g.sbr = r; g.sbc = 1;
+      g.C = CZD; g.ldc = r;
+      LYAP_TRY(gemm_f64(s, g));
+      g = GemmDesc();
+      g.M = k; g.N = n; g.K = r;
+      g.alpha = 2.0 * scale;
+      g.A = CZD; g.sar = r; g.sac = 1;
+      g.B = Z; g.sbr = 1; g.sbc = ldz;
+      g.C = dC; g.ldc = lddc;
+      LYAP_TRY(gemm_f64(s, g));
+    }
+  }
+  LYAP_HIP(hipStreamSynchronize(s));
+  return LYAP_OK;
+}
+
+int lyap_solve(lyap_handle h, void* stream, int n, int m, const double* A, int lda,
+               const double* L, int ldl, const double* S, lyap_precisions prec,
+               const lyap_options* opt, double* Z, int ldz, int z_cap, double* D, int* rank,
+               lyap_info* info) {
+  return solve_impl(false, h, stream, n, m, A, lda, L, ldl, S, prec, opt, Z, ldz, z_cap, D, rank,
+                    info);
+}
+
+int lyap_solve_adjoint(lyap_handle h, void* stream, int n, int m, const double* A, int lda,
+                       const double* L, int ldl, const double* S, lyap_precisions prec,
+                       const lyap_options* opt, double* Z, int ldz, int z_cap, double* D,
+                       int* rank, lyap_info* info) {
+  return solve_impl(true, h, stream, n, m, A, lda, L, ldl, S, prec, opt, Z, ldz, z_cap, D, rank,
+                    info);
 }
 
 }  // extern "C"

@@ -194,6 +194,33 @@ __global__ void k_mu(const double* inv_ss, const double* a_ss, int scaling, doub
   else *mu = 1.0;
 }
 
+// out[0] = sum_ij w[j] X_ij^2 (one block, fixed order).
+__global__ void k_colw_sumsq(int rows, int cols, const double* __restrict__ X, long ldx,
+                             const double* __restrict__ w, double* __restrict__ out) {
+  __shared__ double red[RB];
+  double acc = 0.0;
+  for (long e = threadIdx.x; e < (long)rows * cols; e += RB) {
+    const int i = (int)(e / cols), j = (int)(e % cols);
+    const double x = X[(long)i * ldx + j];
+    acc += w[j] * x * x;
+  }
+  const double t = block_sum(acc, red);
+  if (threadIdx.x == 0) out[0] = t;
+}
+
+// out[c] = sum_i w[i] X_ic^2, one thread per column.
+__global__ void k_roww_colsumsq(int rows, int cols, const double* __restrict__ X, long ldx,
+                                const double* __restrict__ w, double* __restrict__ out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= cols) return;
+  double acc = 0.0;
+  for (int i = 0; i < rows; ++i) {
+    const double x = X[(long)i * ldx + c];
+    acc += w[i] * x * x;
+  }
+  out[c] = acc;
+}
+
 inline unsigned nblk(long total, int bs = 256) { return (unsigned)((total + bs - 1) / bs); }
 
 }  // namespace
@@ -333,6 +360,22 @@ int gather_cols(hipStream_t s, int rows, int count, const double* src, long lds,
   if (total <= 0) return LYAP_OK;
   hipLaunchKernelGGL(k_gather_cols, dim3(nblk(total)), dim3(256), 0, s, rows, count, src, lds, idx,
                      dst, ldd);
+  LYAP_HIP(hipGetLastError());
+  return LYAP_OK;
+}
+
+int colw_sumsq(hipStream_t s, int rows, int cols, const double* X, long ldx, const double* w,
+               double* out) {
+  hipLaunchKernelGGL(k_colw_sumsq, dim3(1), dim3(RB), 0, s, rows, cols, X, ldx, w, out);
+  LYAP_HIP(hipGetLastError());
+  return LYAP_OK;
+}
+
+int roww_colsumsq(hipStream_t s, int rows, int cols, const double* X, long ldx, const double* w,
+                  double* out) {
+  if (cols <= 0) return LYAP_OK;
+  hipLaunchKernelGGL(k_roww_colsumsq, dim3(nblk(cols)), dim3(256), 0, s, rows, cols, X, ldx, w,
+                     out);
   LYAP_HIP(hipGetLastError());
   return LYAP_OK;
 }

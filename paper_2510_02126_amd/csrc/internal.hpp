@@ -43,6 +43,12 @@ int wsumsq(hipStream_t s, int c, const double* G, long ldg, const double* d, dou
 // dst[:, k] = src[:, idx[k]] (idx on the device), rows x count.
 int gather_cols(hipStream_t s, int rows, int count, const double* src, long lds, const int* idx,
                 double* dst, long ldd);
+// out[0] = sum_ij w[j] X_ij^2 (rows x cols, one block).
+int colw_sumsq(hipStream_t s, int rows, int cols, const double* X, long ldx, const double* w,
+               double* out);
+// out[c] = sum_i w[i] X_ic^2.
+int roww_colsumsq(hipStream_t s, int rows, int cols, const double* X, long ldx, const double* w,
+                  double* out);
 // out[0] = trace(A) (n x n).
 int trace(hipStream_t s, int n, const double* A, long lda, double* out);
 

@@ -20,9 +20,13 @@ struct DevBuf {
 class Solver {
  public:
   void release();
+  // adjoint = false: A X + X A^T + L S L^T = 0.  adjoint = true: A^T Y + Y A + L S L^T = 0,
+  // replaying the inverse sequence of the previous forward solve when it was computed for
+  // the same A (pointer, n, lda, ||A||_F) and solver precision.
   int solve(hipStream_t s, Arena& ws, int* flags, int n, int m, const double* A, int lda,
             const double* L, int ldl, const double* S, Prec us, const lyap_options& opt,
-            double* Z, int ldz, int z_cap, double* D, int* rank, lyap_info* info);
+            double* Z, int ldz, int z_cap, double* D, int* rank, lyap_info* info,
+            bool adjoint = false);
 
  private:
   struct Ctx;
@@ -46,6 +50,15 @@ class Solver {
   std::vector<DevBuf> cache_;
   int last_k_ = 0;
   KernTimer kt_;
+  // the matrix the cached inverse sequence belongs to
+  struct CacheKey {
+    const double* A = nullptr;
+    int n = 0, lda = 0;
+    Prec us = Prec::F64;
+    double normA = -1.0;
+    std::vector<double> mus, onenorm;
+    int K = 0;
+  } key_;
 };
 
 }  // namespace lyap
