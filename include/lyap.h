@@ -138,6 +138,25 @@ int lyap_solve(lyap_handle h, void* stream, int n, int m, const double* A, int l
                lyap_info* info);
 
 /*
+ * lyap_solve_batched -- ``count`` independent equations A_i X_i + X_i A_i^T + L_i S_i L_i^T = 0
+ * of uneven n_i (<= 4096) and m_i, each solved exactly as lyap_solve would on its own.  The
+ * instances are taken longest first (by n_i) by ``workers`` host threads (0: 8; at most
+ * 32), each driving its own HIP stream and solver state kept in the handle, so the
+ * latency-bound steps of different instances overlap on the GPU.  Per-instance arrays of
+ * device pointers and leading dimensions (host arrays of length count); S may be NULL (all
+ * instances W = L L^T) or hold NULL entries.  rank, infos (may be NULL) and codes are host
+ * arrays of length count receiving each instance's rank, info and return code.  The call
+ * waits for ``stream`` before starting and returns when every instance is complete; it
+ * returns the first nonzero per-instance code in instance order, or LYAP_OK.
+ */
+int lyap_solve_batched(lyap_handle h, void* stream, int count, const int* n, const int* m,
+                       const double* const* A, const int* lda, const double* const* L,
+                       const int* ldl, const double* const* S, lyap_precisions prec,
+                       const lyap_options* opt, double* const* Z, const int* ldz,
+                       const int* z_cap, double* const* D, int* rank, lyap_info* infos,
+                       int* codes, int workers);
+
+/*
  * lyap_trace_loss -- loss = tr(C X C^T) for X = Z diag(D) Z^T: sum_j D_j ||C z_j||^2.
  *  C  k x n FP64 row-major (ldc >= n); Z n x r (ldz >= r); D r values; loss: host double.
  */

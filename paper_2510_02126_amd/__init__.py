@@ -6,6 +6,7 @@ current stream.  All arithmetic runs in the library's HIP kernels.
 
     solve(A, L, S=None, precisions=("fp16", "fp64", "fp64", "fp64"), tol=1e-13, ...)
         -> (Z, D, info) with X ~ Z diag(D) Z^T     (Alg 2.2 with Alg 3.2 as the solver)
+    solve_batched(As, Ls, Ss=None, ...) -- independent equations of uneven sizes, concurrently
     solve_adjoint(A, L, S=None, ...)  -- A^T Y + Y A + L S L^T = 0, replaying the inverses
     lyapunov_trace_loss(A, L, S, C)   -- tr(C X C^T), differentiable (adjoint backward)
     inverse(A, dtype, pivot) -- inversion at a solver precision (Gauss-Jordan)
@@ -22,7 +23,7 @@ import torch
 from . import _lib
 from ._lib import DTYPES, Info, LyapError, Options, Precisions
 
-__all__ = ["solve", "solve_adjoint", "trace_loss", "trace_loss_grad", "LyapunovTraceLoss",
+__all__ = ["solve", "solve_batched", "solve_adjoint", "trace_loss", "trace_loss_grad", "LyapunovTraceLoss",
            "lyapunov_trace_loss", "inverse", "gemm", "qr", "syev", "LyapError", "version"]
 
 
@@ -152,6 +153,49 @@ def solve(A, L, S=None, precisions=("fp16", "fp64", "fp64", "fp64"), tol=1e-13, 
     """Alg 2.2 (LDL^T-type mixed-precision IR) on the GPU for A X + X A^T + L S L^T = 0.
     Returns (Z, D, info) with X ~ Z diag(D) Z^T."""
     return _solve("lyap_solve", A, L, S, precisions, tol, refine, z_cap, raise_on_error, opts)
+
+
+def solve_batched(As, Ls, Ss=None, precisions=("fp16", "fp64", "fp64", "fp64"), tol=1e-13,
+                  refine=True, z_caps=None, workers=0, raise_on_error=True, **opts):
+    """Independent equations A_i X_i + X_i A_i^T + L_i S_i L_i^T = 0 of uneven sizes solved
+    concurrently (lyap_solve_batched).  Returns a list of (Z_i, D_i, info_i)."""
+    count = len(As)
+    if len(Ls) != count or (Ss is not None and len(Ss) != count):
+        raise ValueError("As, Ls (and Ss) must have the same length")
+    Ss = list(Ss) if Ss is not None else [None] * count
+    dev = _dev(*As, *Ls, *[s for s in Ss if s is not None])
+    As = [_rowmajor(a) for a in As]
+    Ls = [_rowmajor(l) for l in Ls]
+    Ss = [s.contiguous() if s is not None else None for s in Ss]
+    ns = [a.shape[0] for a, _ in As]
+    caps = list(z_caps) if z_caps is not None else ns
+    device = As[0][0].device
+    Zs = [torch.zeros((n, c), dtype=torch.float64, device=device) for n, c in zip(ns, caps)]
+    Ds = [torch.zeros(c, dtype=torch.float64, device=device) for c in caps]
+    IA = ctypes.c_int * count
+    PA = ctypes.c_void_p * count
+    o = _lib.default_options()
+    o.tol = tol
+    o.refine = int(bool(refine))
+    for k, v in opts.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown option {k}")
+        setattr(o, k, v)
+    prec = Precisions(*[DTYPES[p] for p in precisions])
+    rank = IA()
+    codes = IA()
+    infos = (Info * count)()
+    s_ptrs = PA(*[s.data_ptr() if s is not None else None for s in Ss])
+    code = _lib.lib().lyap_solve_batched(
+        _lib.handle(dev), _stream(dev), count, IA(*ns), IA(*[l.shape[1] for l, _ in Ls]),
+        PA(*[a.data_ptr() for a, _ in As]), IA(*[ld for _, ld in As]),
+        PA(*[l.data_ptr() for l, _ in Ls]), IA(*[ld for _, ld in Ls]),
+        s_ptrs if any(s is not None for s in Ss) else None, prec, ctypes.byref(o),
+        PA(*[z.data_ptr() for z in Zs]), IA(*caps), IA(*caps), PA(*[d.data_ptr() for d in Ds]),
+        rank, infos, codes, int(workers))
+    if code != 0 and raise_on_error and code not in (1, 2):
+        _lib.check(code, "lyap_solve_batched")
+    return [(Zs[i][:, :rank[i]], Ds[i][:rank[i]], infos[i].as_dict()) for i in range(count)]
 
 
 def solve_adjoint(A, L, S=None, precisions=("fp16", "fp64", "fp64", "fp64"), tol=1e-13,

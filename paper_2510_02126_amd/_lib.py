@@ -85,6 +85,8 @@ _SIGS = {
     "lyap_version": (ctypes.c_char_p, []),
     "lyap_solve": (I, [P, P, I, I, P, I, P, I, P, Precisions, ctypes.POINTER(Options), P, I, I,
                        P, ctypes.POINTER(I), ctypes.POINTER(Info)]),
+    "lyap_solve_batched": (I, [P, P, I, P, P, P, P, P, P, P, Precisions, ctypes.POINTER(Options),
+                               P, P, P, P, P, P, P, I]),
     "lyap_trace_loss": (I, [P, P, I, I, P, I, I, P, I, P, ctypes.POINTER(D)]),
     "lyap_trace_loss_grad": (I, [P, P, I, I, I, P, I, P, P, I, I, P, I, P, I, P, I, P, D, P, I,
                                  P, I, P, P, I]),

@@ -2,8 +2,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstring>
+#include <memory>
 #include <new>
+#include <numeric>
+#include <thread>
+#include <vector>
 
 #include "common.hpp"
 #include "internal.hpp"
@@ -85,12 +90,64 @@ void KernTimer::release() {
 
 }  // namespace lyap
 
+// Solver state of one batched-solve worker: its own stream, scratch, buffers and flags.
+struct BatchWorker {
+  hipStream_t stream = nullptr;
+  Arena ws;
+  Solver solver;
+  int* flags = nullptr;
+  ~BatchWorker() {
+    solver.release();
+    ws.release();
+    if (flags) (void)hipFree(flags);
+    if (stream) (void)hipStreamDestroy(stream);
+  }
+};
+
 struct lyap_handle_s {
   int device = 0;
   Arena ws;          // per-call scratch
   Solver solver;     // owns the cached inverse sequence and persistent buffers
   int* flags = nullptr;  // device status flags
+  std::vector<std::unique_ptr<BatchWorker>> workers;  // batched solves
 };
+
+static bool valid_dtype(int d);
+
+static int solve_on(Solver& solver, Arena& ws, int* flags, hipStream_t stream, int n, int m,
+                    const double* A, int lda, const double* L, int ldl, const double* S,
+                    lyap_precisions prec, const lyap_options* opt, double* Z, int ldz,
+                    int z_cap, double* D, int* rank, lyap_info* info, bool adjoint) {
+  if (n <= 0 || m <= 0 || m > n || !A || !L || !Z || !D || !rank || lda < n || ldl < m ||
+      z_cap < 1 || ldz < z_cap)
+    return LYAP_BADARG;
+  if (!valid_dtype(prec.u_s) || prec.u != LYAP_F64 || prec.u_r != LYAP_F64 ||
+      prec.u_c != LYAP_F64)
+    return LYAP_BADARG;
+  if (n > 4096) return LYAP_BADARG;
+  lyap_options o;
+  if (opt) o = *opt;
+  else lyap_default_options(&o);
+  if (!(o.tol >= 0) || o.i_max < 0 || o.i_max > 63 || o.k_max < 1 || o.k_max > 64 ||
+      !(o.rho > 0) || !(o.eta_r >= 0) || !(o.theta > 0))
+    return LYAP_BADARG;
+  lyap_info local;
+  lyap_info* inf = info ? info : &local;
+  std::memset(inf, 0, sizeof(*inf));
+  int code = solver.solve(stream, ws, flags, n, m, A, lda, L, ldl, S, (Prec)prec.u_s, o, Z, ldz,
+                          z_cap, D, rank, inf, adjoint);
+  inf->status = code;
+  return code;
+}
+
+static int solve_impl(bool adjoint, lyap_handle h, void* stream, int n, int m, const double* A,
+                      int lda, const double* L, int ldl, const double* S, lyap_precisions prec,
+                      const lyap_options* opt, double* Z, int ldz, int z_cap, double* D,
+                      int* rank, lyap_info* info) {
+  if (!h) return LYAP_BADARG;
+  return solve_on(h->solver, h->ws, h->flags, (hipStream_t)stream, n, m, A, lda, L, ldl, S, prec,
+                  opt, Z, ldz, z_cap, D, rank, info, adjoint);
+}
 
 static bool valid_dtype(int d) { return d >= LYAP_F64 && d <= LYAP_BF16; }
 
@@ -149,6 +206,7 @@ int lyap_create(lyap_handle* h, int device) {
 int lyap_destroy(lyap_handle h) {
   if (!h) return LYAP_OK;
   (void)hipDeviceSynchronize();
+  h->workers.clear();
   h->solver.release();
   h->ws.release();
   if (h->flags) (void)hipFree(h->flags);
@@ -233,37 +291,6 @@ int lyap_syev(lyap_handle h, void* stream, int p, const double* H, int ldh, doub
   LYAP_HIP(hipStreamSynchronize(s));
   return LYAP_OK;
 }
-
-}  // extern "C"
-
-static int solve_impl(bool adjoint, lyap_handle h, void* stream, int n, int m, const double* A,
-                      int lda, const double* L, int ldl, const double* S, lyap_precisions prec,
-                      const lyap_options* opt, double* Z, int ldz, int z_cap, double* D,
-                      int* rank, lyap_info* info) {
-  if (!h || n <= 0 || m <= 0 || m > n || !A || !L || !Z || !D || !rank || lda < n || ldl < m ||
-      z_cap < 1 || ldz < z_cap)
-    return LYAP_BADARG;
-  if (!valid_dtype(prec.u_s) || prec.u != LYAP_F64 || prec.u_r != LYAP_F64 ||
-      prec.u_c != LYAP_F64)
-    return LYAP_BADARG;
-  if (n > 4096) return LYAP_BADARG;
-  lyap_options o;
-  if (opt) o = *opt;
-  else lyap_default_options(&o);
-  if (!(o.tol >= 0) || o.i_max < 0 || o.i_max > 63 || o.k_max < 1 || o.k_max > 64 ||
-      !(o.rho > 0) || !(o.eta_r >= 0) || !(o.theta > 0))
-    return LYAP_BADARG;
-  lyap_info local;
-  lyap_info* inf = info ? info : &local;
-  std::memset(inf, 0, sizeof(*inf));
-  int code = h->solver.solve((hipStream_t)stream, h->ws, h->flags, n, m, A, lda, L, ldl, S,
-                             (Prec)prec.u_s, o, Z, ldz, z_cap, D, rank, inf, adjoint);
-  inf->status = code;
-  return code;
-}
-
-
-extern "C" {
 
 int lyap_trace_loss(lyap_handle h, void* stream, int n, int k, const double* C, int ldc, int r,
                     const double* Z, int ldz, const double* D, double* loss) {
@@ -394,6 +421,56 @@ int lyap_trace_loss_grad(lyap_handle h, void* stream, int n, int m, int k, const
     }
   }
   LYAP_HIP(hipStreamSynchronize(s));
+  return LYAP_OK;
+}
+
+int lyap_solve_batched(lyap_handle h, void* stream, int count, const int* n, const int* m,
+                       const double* const* A, const int* lda, const double* const* L,
+                       const int* ldl, const double* const* S, lyap_precisions prec,
+                       const lyap_options* opt, double* const* Z, const int* ldz,
+                       const int* z_cap, double* const* D, int* rank, lyap_info* infos,
+                       int* codes, int workers) {
+  if (!h || count < 0 || (count > 0 && (!n || !m || !A || !lda || !L || !ldl || !Z || !ldz ||
+                                        !z_cap || !D || !rank || !codes)))
+    return LYAP_BADARG;
+  if (count == 0) return LYAP_OK;
+  for (int i = 0; i < count; ++i)
+    if (n[i] <= 0 || m[i] <= 0 || m[i] > n[i] || n[i] > 4096 || !A[i] || !L[i] || !Z[i] ||
+        !D[i] || lda[i] < n[i] || ldl[i] < m[i] || z_cap[i] < 1 || ldz[i] < z_cap[i])
+      return LYAP_BADARG;
+  const int W = std::max(1, std::min(workers > 0 ? workers : 8, std::min(count, 32)));
+  // inputs are ready once the caller's stream has drained; outputs are complete on return
+  LYAP_HIP(hipStreamSynchronize((hipStream_t)stream));
+  while ((int)h->workers.size() < W) {
+    std::unique_ptr<BatchWorker> w(new (std::nothrow) BatchWorker());
+    if (!w) return LYAP_NO_MEMORY;
+    LYAP_HIP(hipStreamCreateWithFlags(&w->stream, hipStreamNonBlocking));
+    if (hipMalloc(&w->flags, 16 * sizeof(int)) != hipSuccess) return LYAP_NO_MEMORY;
+    h->workers.push_back(std::move(w));
+  }
+  // longest-processing-time first: instances by decreasing n^3
+  std::vector<int> order(count);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return n[a] > n[b]; });
+  std::atomic<int> next(0);
+  auto run = [&](int wi) {
+    BatchWorker& w = *h->workers[wi];
+    if (hipSetDevice(h->device) != hipSuccess) return;
+    for (int q = next.fetch_add(1); q < count; q = next.fetch_add(1)) {
+      const int i = order[q];
+      lyap_info local;
+      lyap_info* inf = infos ? &infos[i] : &local;
+      codes[i] = solve_on(w.solver, w.ws, w.flags, w.stream, n[i], m[i], A[i], lda[i], L[i],
+                          ldl[i], S ? S[i] : nullptr, prec, opt, Z[i], ldz[i], z_cap[i], D[i],
+                          &rank[i], inf, false);
+    }
+  };
+  std::vector<std::thread> pool;
+  for (int wi = 1; wi < W; ++wi) pool.emplace_back(run, wi);
+  run(0);
+  for (auto& t : pool) t.join();
+  for (int i = 0; i < count; ++i)
+    if (codes[i] != LYAP_OK) return codes[i];
   return LYAP_OK;
 }
 
