@@ -55,6 +55,40 @@ def _time_inverse(lyap, torch, A, us, reps=3):
     return e0.elapsed_time(e1) / reps / 1e3
 
 
+def _batched(lyap, torch, us):
+    """256 independent equations (n ~ U{64..512}, m ~ U{1..8}): a host loop of FP64 solves
+    against the batched entry point (FP64 and IR at ``us``).  One warm-up pass each."""
+    import lyapgen
+
+    batch = lyapgen.batch_family()
+    As = [torch.from_numpy(a).cuda() for a, _ in batch]
+    Ls = [torch.from_numpy(l).cuda() for _, l in batch]
+    out = {}
+
+    def loop():
+        return [lyap.solve(a, l, None, precisions=("fp64",) * 4, raise_on_error=False)[2]
+                for a, l in zip(As, Ls)]
+
+    def batched(p):
+        return [o[2] for o in lyap.solve_batched(As, Ls, None, precisions=p,
+                                                 raise_on_error=False)]
+
+    for label, fn in (("loop_fp64", loop),
+                      ("batched_fp64", lambda: batched(("fp64",) * 4)),
+                      (f"batched_{us}_ir", lambda: batched((us, "fp64", "fp64", "fp64")))):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infos = fn()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ok = all(i["status"] == "OK" and i["res"] <= 1e-13 for i in infos)
+        out[label] = {"solves_per_s": round(len(infos) / dt, 2) if ok else 0.0,
+                      "max_res": max(i["res"] for i in infos),
+                      "status": "OK" if ok else "DNF"}
+    return out
+
+
 def _measured_traffic(kernel):
     """HBM bytes per launch of ``kernel`` from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
     summary, or None when there is none or the kernel's source changed since it was taken."""
@@ -108,6 +142,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--us", default="fp32", help="solver precision of the IR run")
     ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--batched", action="store_true",
+                    help="also time 256 independent equations, n in [64, 512] (batched mode)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -165,6 +201,8 @@ def main():
     t_inv = _time_inverse(lyap, torch, A, "fp64")
     inv64 = 2.0 * n ** 3 / t_inv / 1e12
 
+    batched = _batched(lyap, torch, args.us) if args.batched else None
+
     cpu = None
     if not args.skip_cpu:
         t_step, threads = _cpu_baseline(cfg)
@@ -208,6 +246,8 @@ def main():
                                  "frac_fp64_peak": round(inv64 / PEAK_TFLOPS["fp64"], 4)},
         "cpu_baseline": cpu,
     }
+    if batched is not None:
+        line["batched_256_n64_512"] = batched
     print(json.dumps(line), flush=True)
 
 

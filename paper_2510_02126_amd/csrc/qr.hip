@@ -17,12 +17,11 @@
 // rank-deficient F (such as F = [Z, AZ, L] near convergence, where AZ lies almost in the span
 // of Z and L).
 //
-// Panel factorisation: thread t holds rows t + 256 q of the block in registers.  Step k
-// forms, in one reduction over rows below k, the sums s_c = sum_i A[i][c] A[i][k] for all 32
-// columns: s_k is the squared norm below the diagonal, s_j (j > k) gives the reflector's
-// action on the trailing columns and s_c (c < k) gives V^T v_k for the Tw recurrence
-// (Tw[0:k, k] = -tau_k Tw[0:k, 0:k] V^T v_k).  The register columns are rotated by one per
-// step so that the pivot column always sits in register 0 (no dynamic register indexing).
+// Panel factorisation: the r x 32 block is held in registers, 4 (or 8) rows x 8 columns per
+// thread.  Step k forms, in one reduction over rows below k, the sums s_c = sum_i A[i][c] A[i][k]
+// for all 32 columns: s_k is the squared norm below the diagonal, s_j (j > k) gives the
+// reflector's action on the trailing columns and s_c (c < k) gives V^T v_k for the Tw
+// recurrence (Tw[0:k, k] = -tau_k Tw[0:k, 0:k] V^T v_k), which is evaluated after the loop.
 #include <algorithm>
 #include <cmath>
 
