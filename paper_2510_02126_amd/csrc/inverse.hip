@@ -338,39 +338,41 @@ __global__ __launch_bounds__(256) void nop_diag(int n, const T* __restrict__ WT,
   }
 }
 
-// Panel rows: rows in [c0, c0+w) take Dinv, the others become -row * Dinv.  Block (x, y)
-// handles rows [64x, 64x+64) and panel columns [16y, 16y+16); thread t computes row
-// 64x + t % 64 at columns 16y + 4 (t / 64) + s, s < 4 (coalesced along rows in WT).
+// Panel rows: rows in [c0, c0+w) take Dinv, the others become -row * Dinv.  Block x owns
+// rows [AR x, AR x + AR) at every panel column, so the panel entries it reads are the ones it
+// overwrites (no other block touches them); thread t computes row AR x + t % AR at columns
+// 8 (t / AR) + s, s < 8 (coalesced along rows in WT).
+constexpr int AR = 32;
 template <class T>
 __global__ __launch_bounds__(256) void nop_apply(int n, T* __restrict__ WT, int c0, int w,
                                                  const T* __restrict__ Dinv) {
-  __shared__ T Di[WN][16];
-  __shared__ T X[WN][64];
-  const int t = threadIdx.x, il = t & 63, jg = t >> 6;
-  const int i0 = blockIdx.x * 64, jb = blockIdx.y * 16;
-  if (jb >= w) return;  // uniform per block
-  for (int q = t; q < WN * 16; q += 256) {
-    const int k = q >> 4, j = q & 15;
-    Di[k][j] = (k < w && jb + j < w) ? Dinv[k * w + jb + j] : (T)0;
+  static_assert(WN == 8 * (256 / AR), "one thread per row and 8 panel columns");
+  __shared__ T Di[WN][WN];
+  __shared__ T X[WN][AR];
+  const int t = threadIdx.x, il = t % AR, jg = t / AR;
+  const int i0 = blockIdx.x * AR;
+  for (int q = t; q < WN * WN; q += 256) {
+    const int k = q / WN, j = q % WN;
+    Di[k][j] = (k < w && j < w) ? Dinv[k * w + j] : (T)0;
   }
-  for (int q = t; q < WN * 64; q += 256) {
-    const int k = q >> 6, i = q & 63;
+  for (int q = t; q < WN * AR; q += 256) {
+    const int k = q / AR, i = q % AR;
     X[k][i] = (k < w && i0 + i < n) ? WT[(long)(c0 + k) * n + i0 + i] : (T)0;
   }
   __syncthreads();
   const int gi = i0 + il;
   if (gi >= n) return;
-  T acc[4] = {(T)0, (T)0, (T)0, (T)0};
+  T acc[8] = {};
   for (int k = 0; k < w; ++k) {
     const T x = X[k][il];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) acc[s] += x * Di[k][4 * jg + s];
+    for (int s = 0; s < 8; ++s) acc[s] += x * Di[k][8 * jg + s];
   }
   const bool diag = gi >= c0 && gi < c0 + w;
 #pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    const int j = jb + 4 * jg + s;
-    if (j < w) WT[(long)(c0 + j) * n + gi] = diag ? Dinv[(gi - c0) * w + j] : -acc[s];
+  for (int s = 0; s < 8; ++s) {
+    const int j = 8 * jg + s;
+    if (j < w) WT[(long)(c0 + j) * n + gi] = diag ? Di[gi - c0][j] : -acc[s];
   }
 }
 
@@ -437,8 +439,8 @@ template <class T> struct Inv {
     if (!pivot) {
       hipLaunchKernelGGL((nop_diag<T>), dim3(1), dim3(256), 0, s, n, WT, c0, wc, Dinv, used, piv,
                          sing);
-      hipLaunchKernelGGL((nop_apply<T>), dim3((unsigned)ceil_div(n, 64), WN / 16), dim3(256), 0,
-                         s, n, WT, c0, wc, Dinv);
+      hipLaunchKernelGGL((nop_apply<T>), dim3((unsigned)ceil_div(n, AR)), dim3(256), 0, s, n, WT,
+                         c0, wc, Dinv);
       LYAP_HIP(hipGetLastError());
       return LYAP_OK;
     }

@@ -146,6 +146,24 @@ def test_inverse_diag_dominant_unpivoted(lyap, n, dtype):
     assert np.linalg.norm(Xn - Xp, 1) / np.linalg.norm(Xp, 1) <= tol
 
 
+@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
+def test_inverse_unpivoted_repeatable(lyap, dtype):
+    # every workgroup of the unpivoted panel update reads only the panel entries it writes
+    # itself, so repeated inversions agree bit for bit whatever ran before them
+    print(f"inverse unpivoted repeatability {dtype}", flush=True)
+    rng = np.random.default_rng(31)
+    mats = []
+    for n in (131, 777, 2048):
+        E = rng.standard_normal((n, n))
+        E *= 0.9 / np.abs(E).sum(axis=0, keepdims=True)
+        mats.append(_cuda(-np.eye(n) + E))
+    first = [lyap.inverse(M, dtype, pivot=False) for M in mats]
+    for rep in range(6):
+        for k in ((rep + 1) % 3, rep % 3, (rep + 2) % 3):
+            X = lyap.inverse(mats[k], dtype, pivot=False)
+            assert torch.equal(X, first[k]), (rep, k)
+
+
 def test_inverse_unpivoted_zero_pivot_reports(lyap):
     A = np.array([[0.0, 1.0], [1.0, 0.0]])
     with pytest.raises(lyap.LyapError) as e:
