@@ -13,7 +13,8 @@
 // pair is formed directly from the matrix before round r and round r's rotations (each of its
 // four 16 x 16 blocks is a slice of R_P^T A_PQ R_Q), so the solves do not wait for the update.
 //
-// Rotations are skipped when |a_pq| is below an absolute floor (tol ||A||_F / (4 pp)) or below
+// Rotations are skipped when |a_pq| is below an absolute floor (tol ||A||_F / (4 pp)) or, when
+// the caller asks for eigenvalues accurate relative to their own size, below
 // tol sqrt(|a_pp a_qq|).  Sweeps stop when ||offdiag(A)||_F <= tol ||A||_F or when the solves
 // of a whole sweep applied no rotation.  Eigenvalues are then sorted by descending magnitude
 // (ties by index) and the eigenvectors gathered accordingly.
@@ -97,6 +98,16 @@ struct SolveLds {
   int any;
 };
 
+// Round and first-solve workgroups: 4 waves (the 2 x 2 block updates of a sweep step, the
+// matrix-core tiles of the A and V update).
+constexpr int NTJ = 256;
+
+// Slot of element e in round r of the circle tournament on m slots (inverse of circle_elem).
+__device__ inline int circle_slot(int e, int r, int m) {
+  if (e == 0) return 0;
+  return 1 + ((e - 1 - r) % (m - 1) + (m - 1)) % (m - 1);
+}
+
 // One cyclic Jacobi sweep on L.S[0] (R starts as I in L.R[0]); the result is in buffer 1
 // (SB - 1 = 31 steps, odd).  Thread t owns the 2 x 2 blocks (pair a = t / 16 rows,
 // pair b = t % 16 columns).  Lanes 0..15 of each wave compute the 16 rotations of the step
@@ -144,7 +155,7 @@ __device__ void subproblem_sweep(SolveLds& L, double thr, double eps) {
 // the rotation to Rn[j].  With Rc == nullptr the subproblem is read from A directly; otherwise
 // A is the matrix before the round whose pairs ``pc`` and rotations Rc are given.
 __device__ void solve_pair(SolveLds& L, int pp, int np, const double* __restrict__ A,
-                           const int* __restrict__ pc, const double* __restrict__ Rc,
+                           const int* __restrict__ pc, int rc, const double* __restrict__ Rc,
                            const int* __restrict__ pn, int j, double thr, double eps,
                            double* __restrict__ Rn, int* __restrict__ applied) {
   const int t = threadIdx.x;
@@ -153,83 +164,107 @@ __device__ void solve_pair(SolveLds& L, int pp, int np, const double* __restrict
   double (&RA)[SB][LDS_PAD] = L.R[1];
   double (&RB)[SB][LDS_PAD] = L.E;
   if (t == 0) L.any = 0;
-  for (int e = t; e < SB * SB; e += 256) {
+  for (int e = t; e < SB * SB; e += NTJ) {
     const int i = e / SB, k = e % SB;
     L.R[0][i][k] = (i == k) ? 1.0 : 0.0;
   }
   if (!Rc) {
-    for (int e = t; e < SB * SB; e += 256) {
+    for (int e = t; e < SB * SB; e += NTJ) {
       const int i = e / SB, k = e % SB;
       L.S[0][i][k] = A[(long)gidx(i, nI, nJ) * pp + gidx(k, nI, nJ)];
     }
   } else {
-    // block b of the new pair sits in current pair P(b) at half h(b)
+    // block b of the new pair sits in current pair P(b) at half h(b): its slot in round rc
+    // of the block tournament gives the pair, the stored (min, max) order the half
+    const int nbk = 2 * np;
     int P[2], H[2];
     for (int h = 0; h < 2; ++h) {
       const int blk = h == 0 ? nI : nJ;
-      P[h] = 0;
-      H[h] = 0;
-      for (int k = 0; k < np; ++k) {
-        if (pc[2 * k] == blk) { P[h] = k; H[h] = 0; }
-        if (pc[2 * k + 1] == blk) { P[h] = k; H[h] = 1; }
+      const int slot = circle_slot(blk, rc, nbk);
+      P[h] = slot < np ? slot : nbk - 1 - slot;
+      H[h] = pc[2 * P[h]] == blk ? 0 : 1;
+    }
+    int bi[2], bj[2];
+    for (int h = 0; h < 2; ++h) {
+      bi[h] = pc[2 * P[h]];
+      bj[h] = pc[2 * P[h] + 1];
+    }
+    // all four blocks of the current matrix and both rotations, loaded at once (thread t
+    // owns elements t + 256 q)
+    double xr[4][4], ra[4], rb[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = t + NTJ * q, i = e / SB, k = e % SB;
+      ra[q] = Rc[(long)P[0] * SB * SB + e];
+      rb[q] = Rc[(long)P[1] * SB * SB + e];
+#pragma unroll
+      for (int cmb = 0; cmb < 4; ++cmb) {
+        const int h1 = cmb >> 1, h2 = cmb & 1;
+        xr[cmb][q] = A[(long)gidx(i, bi[h1], bj[h1]) * pp + gidx(k, bi[h2], bj[h2])];
       }
     }
-    for (int h1 = 0; h1 < 2; ++h1)
-      for (int h2 = 0; h2 < 2; ++h2) {
-        const int P1 = P[h1], P2 = P[h2];
-        const int aI = pc[2 * P1], aJ = pc[2 * P1 + 1], bI = pc[2 * P2], bJ = pc[2 * P2 + 1];
-        __syncthreads();
-        for (int e = t; e < SB * SB; e += 256) {
-          const int i = e / SB, k = e % SB;
-          X[i][k] = A[(long)gidx(i, aI, aJ) * pp + gidx(k, bI, bJ)];
-          RA[i][k] = Rc[(long)P1 * SB * SB + e];
-          RB[i][k] = Rc[(long)P2 * SB * SB + e];
-        }
-        __syncthreads();
-        // Y = X R_P2[:, half h2]  (32 x 16): thread (i = t / 8, columns 2 (t % 8) + {0, 1})
-        const int yi = t / 8, yc = 2 * (t % 8);
-        double y0 = 0.0, y1 = 0.0;
-        for (int k = 0; k < SB; ++k) {
-          const double x = X[yi][k];
-          y0 += x * RB[k][HB * H[h2] + yc];
-          y1 += x * RB[k][HB * H[h2] + yc + 1];
-        }
-        __syncthreads();
-        X[yi][yc] = y0;  // X now holds Y in its first 16 columns
-        X[yi][yc + 1] = y1;
-        __syncthreads();
-        // S block = R_P1[:, half h1]^T Y  (16 x 16): thread (i = t / 16, c = t % 16)
-        const int si = t / HB, sc = t % HB;
-        double s = 0.0;
-        for (int k = 0; k < SB; ++k) s += RA[k][HB * H[h1] + si] * X[k][sc];
-        L.S[0][HB * h1 + si][HB * h2 + sc] = s;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = t + NTJ * q, i = e / SB, k = e % SB;
+      RA[i][k] = ra[q];  // R_P[0]
+      RB[i][k] = rb[q];  // R_P[1]
+    }
+#pragma unroll
+    for (int cmb = 0; cmb < 4; ++cmb) {
+      const int h1 = cmb >> 1, h2 = cmb & 1;
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int e = t + NTJ * q;
+        X[e / SB][e % SB] = xr[cmb][q];
       }
+      __syncthreads();
+      // Y = X R_P[h2][:, half H[h2]]  (32 x 16): thread (i = t / 8, columns 2 (t % 8) + {0, 1})
+      double (&R2)[SB][LDS_PAD] = h2 == 0 ? RA : RB;
+      double (&R1)[SB][LDS_PAD] = h1 == 0 ? RA : RB;
+      const int yi = t / 8, yc = 2 * (t % 8);
+      double y0 = 0.0, y1 = 0.0;
+      for (int k = 0; k < SB; ++k) {
+        const double x = X[yi][k];
+        y0 += x * R2[k][HB * H[h2] + yc];
+        y1 += x * R2[k][HB * H[h2] + yc + 1];
+      }
+      __syncthreads();
+      X[yi][yc] = y0;  // X now holds Y in its first 16 columns
+      X[yi][yc + 1] = y1;
+      __syncthreads();
+      // S block = R_P[h1][:, half H[h1]]^T Y  (16 x 16): thread (i = t / 16, c = t % 16)
+      const int si = t / HB, sc = t % HB;
+      double sum = 0.0;
+      for (int k = 0; k < SB; ++k) sum += R1[k][HB * H[h1] + si] * X[k][sc];
+      L.S[0][HB * h1 + si][HB * h2 + sc] = sum;
+    }
   }
   __syncthreads();
   subproblem_sweep(L, thr, eps);
   double* Ro = Rn + (long)j * SB * SB;
-  for (int e = t; e < SB * SB; e += 256) Ro[e] = L.R[1][e / SB][e % SB];
+  for (int e = t; e < SB * SB; e += NTJ) Ro[e] = L.R[1][e / SB][e % SB];
   if (t == 0 && L.any) atomicAdd(applied, 1);
 }
 
 // First solve of the iteration (subproblems read from A).
-__global__ __launch_bounds__(256) void jac_solve0(int pp, int np, const double* __restrict__ A,
+__global__ __launch_bounds__(NTJ) void jac_solve0(int pp, int np, const double* __restrict__ A,
                                                   const int* __restrict__ pn,
                                                   const double* __restrict__ thr_dev, double eps,
                                                   double* __restrict__ Rn,
                                                   int* __restrict__ applied) {
   __shared__ SolveLds L;
-  solve_pair(L, pp, np, A, nullptr, nullptr, pn, blockIdx.x, *thr_dev, eps, Rn, applied);
+  solve_pair(L, pp, np, A, nullptr, 0, nullptr, pn, blockIdx.x, *thr_dev, eps, Rn, applied);
 }
 
 // One round.  Blocks [0, np): solves of the next round's pairs pn (rotations to Rn).
 // Blocks [np, np + np*np): Aout block (pair P rows, pair Q cols) = R_P^T Ain_PQ R_Q.
 // Blocks [np + np*np, ...): V tile (rows 32 t.., cols of pair Q) <- V_tile R_Q (in place).
 // The block products run on the FP64 matrix cores: wave w owns the 16 x 16 tile (w/2, w%2).
-__global__ __launch_bounds__(256) void jac_round(int pp, int np, const double* __restrict__ Ain,
+__global__ __launch_bounds__(NTJ) void jac_round(int pp, int np, const double* __restrict__ Ain,
                                                  double* __restrict__ Aout,
                                                  double* __restrict__ V,
-                                                 const int* __restrict__ pc,
+                                                 const int* __restrict__ pc, int rc,
                                                  const double* __restrict__ Rc,
                                                  const int* __restrict__ pn,
                                                  double* __restrict__ Rn,
@@ -238,7 +273,7 @@ __global__ __launch_bounds__(256) void jac_round(int pp, int np, const double* _
   __shared__ SolveLds L;
   int blk = blockIdx.x;
   if (blk < np) {
-    solve_pair(L, pp, np, Ain, pc, Rc, pn, blk, *thr_dev, eps, Rn, applied);
+    solve_pair(L, pp, np, Ain, pc, rc, Rc, pn, blk, *thr_dev, eps, Rn, applied);
     return;
   }
   blk -= np;
@@ -254,7 +289,7 @@ __global__ __launch_bounds__(256) void jac_round(int pp, int np, const double* _
   const int pI = pc[2 * P], pJ = pc[2 * P + 1];
   const double* RQg = Rc + (long)Q * SB * SB;
   const double* RPg = Rc + (long)P * SB * SB;
-  for (int e = threadIdx.x; e < SB * SB; e += 256) {
+  for (int e = threadIdx.x; e < SB * SB; e += NTJ) {
     const int i = e / SB, j = e % SB;
     RQ[i][j] = RQg[e];
     if (isA) {
@@ -391,7 +426,7 @@ size_t syev_workspace_bytes(int p) {
 }
 
 int syev(hipStream_t s, int p, const double* H, long ldh, double* w, double* V, long ldv,
-         Arena& ws, double tol_rel, int* sweeps_out, KernTimer* kt) {
+         Arena& ws, double tol_rel, int* sweeps_out, KernTimer* kt, bool relative) {
   if (p <= 0) return LYAP_OK;
   if (p > 4096) return LYAP_BADARG;
   const int pp = ceil_div(p, SB) * SB;
@@ -408,6 +443,7 @@ int syev(hipStream_t s, int p, const double* H, long ldh, double* w, double* V, 
       !applied)
     return LYAP_NO_MEMORY;
   if (tol_rel <= 0.0) tol_rel = 1e-15;
+  const double eps = relative ? tol_rel : 0.0;
   // round-robin schedule of block pairs (host-computed, uploaded once)
   std::vector<int> sched((size_t)rounds * np * 2);
   for (int r = 0; r < rounds; ++r)
@@ -441,8 +477,8 @@ int syev(hipStream_t s, int p, const double* H, long ldh, double* w, double* V, 
     if (host[0] <= tol_rel * tol_rel * total) break;
     if (sweep > 0 && host[2] == 0.0) break;
     if (!solved) {
-      hipLaunchKernelGGL(jac_solve0, dim3(np), dim3(256), 0, s, pp, np, Aw[cur], pairs, thr,
-                         tol_rel, Rb[rc], applied);
+      hipLaunchKernelGGL(jac_solve0, dim3(np), dim3(NTJ), 0, s, pp, np, Aw[cur], pairs, thr,
+                         eps, Rb[rc], applied);
       solved = true;
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -450,8 +486,8 @@ int syev(hipStream_t s, int p, const double* H, long ldh, double* w, double* V, 
     for (int r = 0; r < rounds; ++r) {
       const int* pc = pairs + (size_t)r * np * 2;
       const int* pn = pairs + (size_t)((r + 1) % rounds) * np * 2;
-      hipLaunchKernelGGL(jac_round, dim3(np + np * np + np * (pp / SB)), dim3(256), 0, s, pp, np,
-                         Aw[cur], Aw[cur ^ 1], Vw, pc, Rb[rc], pn, Rb[rc ^ 1], thr, tol_rel,
+      hipLaunchKernelGGL(jac_round, dim3(np + np * np + np * (pp / SB)), dim3(NTJ), 0, s, pp, np,
+                         Aw[cur], Aw[cur ^ 1], Vw, pc, r, Rb[rc], pn, Rb[rc ^ 1], thr, eps,
                          applied);
       cur ^= 1;
       rc ^= 1;

@@ -206,7 +206,11 @@ int Solver::rank_trunc(Ctx& c, double* Zb, long ldb, int& cols, std::vector<doub
   g.C = Hm; g.ldc = cap;
   LYAP_TRY(gemm_f64(s, g));
   c.ws->reset();
-  LYAP_TRY(syev(s, k, Hm, cap, wv, Vm, cap, *c.ws, std::max(10.0 * thr, 1e-15), nullptr, c.kt));
+  // Inside the solver only eigenvalues above thr max|lambda| are kept and the solver works
+  // at u_s: accuracy relative to ||H|| (absolute rotation threshold) is what it can use;
+  // relative accuracy for the discarded small eigenvalues would cost many extra sweeps.
+  LYAP_TRY(syev(s, k, Hm, cap, wv, Vm, cap, *c.ws, std::max(10.0 * thr, 1e-15), nullptr, c.kt,
+                false));
   std::vector<double> lam(k);
   LYAP_HIP(hipMemcpyAsync(lam.data(), wv, k * sizeof(double), hipMemcpyDeviceToHost, s));
   LYAP_HIP(hipStreamSynchronize(s));
