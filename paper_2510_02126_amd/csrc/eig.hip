@@ -4,9 +4,12 @@
 // The matrix (padded to a multiple of 32 with zero rows/columns, which stay decoupled) is cut
 // into blocks of 16 indices.  A sweep visits every pair of blocks once in a round-robin
 // tournament (nb - 1 rounds of nb / 2 disjoint pairs).  Round r computes, for each of its
-// pairs, the 32 x 32 orthogonal R_p that diagonalises the pair's subproblem (one cyclic Jacobi
-// sweep in LDS), and then A <- G^T A G, V <- V G with G the block-diagonal (in pair order) of
-// the R_p: block (p, q) of A becomes R_p^T A_pq R_q (FP64 matrix cores).
+// pairs, a 32 x 32 orthogonal R_p from Jacobi rotations of the pair's subproblem in LDS, and
+// then A <- G^T A G, V <- V G with G the block-diagonal (in pair order) of the R_p: block
+// (p, q) of A becomes R_p^T A_pq R_q (FP64 matrix cores).  In the first round of a sweep the
+// subproblems get a full cyclic sweep (every pair of their 32 indices, so every pair inside a
+// block is rotated once per sweep); later rounds rotate only the 16 x 16 pairs across the two
+// blocks (16 steps instead of 31), so each index pair of the matrix is rotated once per sweep.
 //
 // One kernel per round, with A ping-ponged between two buffers: its first workgroups solve the
 // subproblems of round r + 1 while the others apply round r.  The subproblem of a round-(r+1)
@@ -88,13 +91,12 @@ __device__ inline f64x4 mfma_f64(double a, double b, f64x4 c) {
 
 __device__ inline int gidx(int i, int bi, int bj) { return i < HB ? bi * HB + i : bj * HB + (i - HB); }
 
-// LDS of a round workgroup.  A solve uses S[0..1] and R[0..1] for the sweep and, while it
-// forms its subproblem, S[1] / R[1] / E as staging (X / RA / RB); an update workgroup uses
-// S[1], R[1], E and S[0].
+// LDS of a round workgroup (four 32 x 32 buffers, so four workgroups fit on a CU).  A solve
+// uses S[0..1] and R[0..1] for the sweep and, while it forms its subproblem, S[1] / R[1] /
+// R[0] as staging (X / RA / RB); an update workgroup uses all four for its operands.
 struct SolveLds {
   double S[2][SB][LDS_PAD];  // subproblem, double-buffered by step parity
   double R[2][SB][LDS_PAD];  // accumulated rotation
-  double E[SB][LDS_PAD];
   int any;
 };
 
@@ -108,30 +110,45 @@ __device__ inline int circle_slot(int e, int r, int m) {
   return 1 + ((e - 1 - r) % (m - 1) + (m - 1)) % (m - 1);
 }
 
-// One cyclic Jacobi sweep on L.S[0] (R starts as I in L.R[0]); the result is in buffer 1
-// (SB - 1 = 31 steps, odd).  Thread t owns the 2 x 2 blocks (pair a = t / 16 rows,
-// pair b = t % 16 columns).  Lanes 0..15 of each wave compute the 16 rotations of the step
-// and the other lanes fetch theirs by lane permutation; every thread reads the current
-// buffer and writes its block of the other one, so a step needs a single barrier.
-__device__ void subproblem_sweep(SolveLds& L, double thr, double eps) {
+// Index pair k of step r of a subproblem sweep (p < q).  A full sweep (SB - 1 steps of the
+// circle tournament on SB indices) rotates every pair of the subproblem once; a cross sweep
+// (HB steps, pair k of step r = (k, HB + (k + r) mod HB)) rotates only the pairs with one
+// index in each block.
+__device__ inline void step_pair(bool full, int k, int r, int& p, int& q) {
+  if (full) {
+    p = circle_elem(k, r, SB);
+    q = circle_elem(SB - 1 - k, r, SB);
+    if (p > q) { const int x = p; p = q; q = x; }
+  } else {
+    p = k;
+    q = HB + (k + r) % HB;
+  }
+}
+
+// One sweep on L.S[0] (R starts as I in L.R[0]); returns the buffer holding the result (the
+// parity of the step count).  Thread t owns the 2 x 2 blocks (pair a = t / 16 rows, pair
+// b = t % 16 columns).  Lanes 0..15 of each wave compute the 16 rotations of the step and the
+// other lanes fetch theirs by lane permutation; every thread reads the current buffer and
+// writes its block of the other one, so a step needs a single barrier.
+__device__ int subproblem_sweep(SolveLds& L, double thr, double eps, bool full) {
   const int t = threadIdx.x, lane = t & 63;
   const int a = t / (SB / 2), b = t % (SB / 2);
-  for (int r = 0; r < SB - 1; ++r) {
+  const int steps = full ? SB - 1 : HB;
+  for (int r = 0; r < steps; ++r) {
     const int cur = r & 1, nxt = cur ^ 1;
     double c = 1.0, sn = 0.0;
     if (lane < SB / 2) {
-      int p = circle_elem(lane, r, SB), q = circle_elem(SB - 1 - lane, r, SB);
-      if (p > q) { const int x = p; p = q; q = x; }
+      int p, q;
+      step_pair(full, lane, r, p, q);
       if (rot_params(L.S[cur][p][p], L.S[cur][q][q], L.S[cur][p][q], thr, eps, c, sn) &&
           t == lane)
         L.any = 1;
     }
     const double ca = __shfl(c, a), sa = __shfl(sn, a);
     const double cb = __shfl(c, b), sb = __shfl(sn, b);
-    int p0 = circle_elem(a, r, SB), q0 = circle_elem(SB - 1 - a, r, SB);
-    if (p0 > q0) { const int x = p0; p0 = q0; q0 = x; }
-    int p1 = circle_elem(b, r, SB), q1 = circle_elem(SB - 1 - b, r, SB);
-    if (p1 > q1) { const int x = p1; p1 = q1; q1 = x; }
+    int p0, q0, p1, q1;
+    step_pair(full, a, r, p0, q0);
+    step_pair(full, b, r, p1, q1);
     const double m00 = L.S[cur][p0][p1], m01 = L.S[cur][p0][q1];
     const double m10 = L.S[cur][q0][p1], m11 = L.S[cur][q0][q1];
     const double r00 = L.R[cur][p0][p1], r01 = L.R[cur][p0][q1];
@@ -149,6 +166,7 @@ __device__ void subproblem_sweep(SolveLds& L, double thr, double eps) {
     L.R[nxt][q0][q1] = r10 * sb + r11 * cb;
     __syncthreads();
   }
+  return steps & 1;
 }
 
 // Solve workgroup for pair j = (bI, bJ) of ``pn``: form its subproblem, run one sweep, store
@@ -156,18 +174,14 @@ __device__ void subproblem_sweep(SolveLds& L, double thr, double eps) {
 // A is the matrix before the round whose pairs ``pc`` and rotations Rc are given.
 __device__ void solve_pair(SolveLds& L, int pp, int np, const double* __restrict__ A,
                            const int* __restrict__ pc, int rc, const double* __restrict__ Rc,
-                           const int* __restrict__ pn, int j, double thr, double eps,
+                           const int* __restrict__ pn, int j, bool full, double thr, double eps,
                            double* __restrict__ Rn, int* __restrict__ applied) {
   const int t = threadIdx.x;
   const int nI = pn[2 * j], nJ = pn[2 * j + 1];
   double (&X)[SB][LDS_PAD] = L.S[1];
   double (&RA)[SB][LDS_PAD] = L.R[1];
-  double (&RB)[SB][LDS_PAD] = L.E;
+  double (&RB)[SB][LDS_PAD] = L.R[0];
   if (t == 0) L.any = 0;
-  for (int e = t; e < SB * SB; e += NTJ) {
-    const int i = e / SB, k = e % SB;
-    L.R[0][i][k] = (i == k) ? 1.0 : 0.0;
-  }
   if (!Rc) {
     for (int e = t; e < SB * SB; e += NTJ) {
       const int i = e / SB, k = e % SB;
@@ -239,11 +253,16 @@ __device__ void solve_pair(SolveLds& L, int pp, int np, const double* __restrict
       for (int k = 0; k < SB; ++k) sum += R1[k][HB * H[h1] + si] * X[k][sc];
       L.S[0][HB * h1 + si][HB * h2 + sc] = sum;
     }
+    __syncthreads();  // RB (in R[0]) no longer read
+  }
+  for (int e = t; e < SB * SB; e += NTJ) {
+    const int i = e / SB, k = e % SB;
+    L.R[0][i][k] = (i == k) ? 1.0 : 0.0;
   }
   __syncthreads();
-  subproblem_sweep(L, thr, eps);
+  const int res = subproblem_sweep(L, thr, eps, full);
   double* Ro = Rn + (long)j * SB * SB;
-  for (int e = t; e < SB * SB; e += NTJ) Ro[e] = L.R[1][e / SB][e % SB];
+  for (int e = t; e < SB * SB; e += NTJ) Ro[e] = L.R[res][e / SB][e % SB];
   if (t == 0 && L.any) atomicAdd(applied, 1);
 }
 
@@ -254,79 +273,134 @@ __global__ __launch_bounds__(NTJ) void jac_solve0(int pp, int np, const double* 
                                                   double* __restrict__ Rn,
                                                   int* __restrict__ applied) {
   __shared__ SolveLds L;
-  solve_pair(L, pp, np, A, nullptr, 0, nullptr, pn, blockIdx.x, *thr_dev, eps, Rn, applied);
+  solve_pair(L, pp, np, A, nullptr, 0, nullptr, pn, blockIdx.x, true, *thr_dev, eps, Rn,
+             applied);
 }
 
-// One round.  Blocks [0, np): solves of the next round's pairs pn (rotations to Rn).
-// Blocks [np, np + np*np): Aout block (pair P rows, pair Q cols) = R_P^T Ain_PQ R_Q.
-// Blocks [np + np*np, ...): V tile (rows 32 t.., cols of pair Q) <- V_tile R_Q (in place).
+// One round.  Blocks [0, np): solves of the next round's pairs pn (rotations to Rn; a full
+// subproblem sweep when the next round is the first of a sweep, a cross sweep otherwise).
+// The other blocks are update workers that take items w, w + nw, w + 2 nw, ... of
+//   items [0, np*np):            Aout block (pair P rows, pair Q cols) = R_P^T Ain_PQ R_Q,
+//   items [np*np, np*np + np*nt): V tile (rows 32 t.., cols of pair Q) <- V_tile R_Q (in place),
+// loading the operands of their next item into registers while they compute the current one.
 // The block products run on the FP64 matrix cores: wave w owns the 16 x 16 tile (w/2, w%2).
+struct Item {
+  bool isA;
+  int P, Q, tile;
+};
+
+__device__ inline Item decode_item(int item, int np) {
+  Item it;
+  it.isA = item < np * np;
+  if (it.isA) {
+    it.P = item / np;
+    it.Q = item % np;
+    it.tile = 0;
+  } else {
+    const int b2 = item - np * np;
+    it.Q = b2 % np;
+    it.tile = b2 / np;
+    it.P = 0;
+  }
+  return it;
+}
+
+// thread t loads elements t + 256 q (q < 4) of the item's three 32 x 32 operands
+__device__ inline void load_item(const Item& it, int pp, const int* __restrict__ pc,
+                                 const double* __restrict__ Ain, const double* __restrict__ V,
+                                 const double* __restrict__ Rc, double (&m)[4], double (&rq)[4],
+                                 double (&rp)[4]) {
+  const int t = threadIdx.x;
+  const int qI = pc[2 * it.Q], qJ = pc[2 * it.Q + 1];
+  const int pI = pc[2 * it.P], pJ = pc[2 * it.P + 1];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int e = t + NTJ * q, i = e / SB, j = e % SB;
+    rq[q] = Rc[(long)it.Q * SB * SB + e];
+    if (it.isA) {
+      rp[q] = Rc[(long)it.P * SB * SB + e];
+      m[q] = Ain[(long)gidx(i, pI, pJ) * pp + gidx(j, qI, qJ)];
+    } else {
+      m[q] = V[(long)(it.tile * SB + i) * pp + gidx(j, qI, qJ)];
+    }
+  }
+}
+
 __global__ __launch_bounds__(NTJ) void jac_round(int pp, int np, const double* __restrict__ Ain,
                                                  double* __restrict__ Aout,
                                                  double* __restrict__ V,
                                                  const int* __restrict__ pc, int rc,
                                                  const double* __restrict__ Rc,
-                                                 const int* __restrict__ pn,
+                                                 const int* __restrict__ pn, int full,
                                                  double* __restrict__ Rn,
                                                  const double* __restrict__ thr_dev, double eps,
                                                  int* __restrict__ applied) {
   __shared__ SolveLds L;
-  int blk = blockIdx.x;
+  const int blk = blockIdx.x;
   if (blk < np) {
-    solve_pair(L, pp, np, Ain, pc, rc, Rc, pn, blk, *thr_dev, eps, Rn, applied);
+    solve_pair(L, pp, np, Ain, pc, rc, Rc, pn, blk, full != 0, *thr_dev, eps, Rn, applied);
     return;
   }
-  blk -= np;
+  const int nw = gridDim.x - np;
+  const int nitems = np * np + np * (pp / SB);
+  int item = blk - np;
+  if (item >= nitems) return;
   double (&M)[SB][LDS_PAD] = L.S[1];
-  double (&RQ)[SB][LDS_PAD] = L.E;
+  double (&RQ)[SB][LDS_PAD] = L.S[0];
   double (&RP)[SB][LDS_PAD] = L.R[1];
-  double (&T1)[SB][LDS_PAD] = L.S[0];
-  const bool isA = blk < np * np;
-  int P, Q, tile = 0;
-  if (isA) { P = blk / np; Q = blk % np; }
-  else { const int b2 = blk - np * np; Q = b2 % np; tile = b2 / np; P = 0; }
-  const int qI = pc[2 * Q], qJ = pc[2 * Q + 1];
-  const int pI = pc[2 * P], pJ = pc[2 * P + 1];
-  const double* RQg = Rc + (long)Q * SB * SB;
-  const double* RPg = Rc + (long)P * SB * SB;
-  for (int e = threadIdx.x; e < SB * SB; e += NTJ) {
-    const int i = e / SB, j = e % SB;
-    RQ[i][j] = RQg[e];
-    if (isA) {
-      RP[i][j] = RPg[e];
-      M[i][j] = Ain[(long)gidx(i, pI, pJ) * pp + gidx(j, qI, qJ)];
-    } else {
-      M[i][j] = V[(long)(tile * SB + i) * pp + gidx(j, qI, qJ)];
-    }
-  }
-  __syncthreads();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double (&T1)[SB][LDS_PAD] = L.R[0];
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
   const int ti = wave >> 1, tj = wave & 1;
   const int lr = lane & 15, lk = lane >> 4;
-  f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+  double m[4], rq[4], rp[4];
+  Item it = decode_item(item, np);
+  load_item(it, pp, pc, Ain, V, Rc, m, rq, rp);
+  while (true) {
+    __syncthreads();  // the previous item's operands are no longer read
 #pragma unroll
-  for (int k0 = 0; k0 < SB; k0 += 4)
-    acc = mfma_f64(M[16 * ti + lr][k0 + lk], RQ[k0 + lk][16 * tj + lr], acc);
-  // D layout (FP64 16x16x4): lane l, register i -> row 4 i + l / 16, column l % 16
-  if (!isA) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int r = 16 * ti + 4 * i + lk, c = 16 * tj + lr;
-      V[(long)(tile * SB + r) * pp + gidx(c, qI, qJ)] = acc[i];
+    for (int q = 0; q < 4; ++q) {
+      const int e = t + NTJ * q, i = e / SB, j = e % SB;
+      M[i][j] = m[q];
+      RQ[i][j] = rq[q];
+      if (it.isA) RP[i][j] = rp[q];
     }
-    return;
-  }
+    __syncthreads();
+    const Item cur = it;
+    const int next = item + nw;
+    if (next < nitems) {
+      it = decode_item(next, np);
+      load_item(it, pp, pc, Ain, V, Rc, m, rq, rp);
+    }
+    const int qI = pc[2 * cur.Q], qJ = pc[2 * cur.Q + 1];
+    f64x4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int i = 0; i < 4; ++i) T1[16 * ti + 4 * i + lk][16 * tj + lr] = acc[i];
-  __syncthreads();
-  f64x4 out = {0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < SB; k0 += 4)
+      acc = mfma_f64(M[16 * ti + lr][k0 + lk], RQ[k0 + lk][16 * tj + lr], acc);
+    // D layout (FP64 16x16x4): lane l, register i -> row 4 i + l / 16, column l % 16
+    if (!cur.isA) {
 #pragma unroll
-  for (int k0 = 0; k0 < SB; k0 += 4)
-    out = mfma_f64(RP[k0 + lk][16 * ti + lr], T1[k0 + lk][16 * tj + lr], out);
+      for (int i = 0; i < 4; ++i) {
+        const int r = 16 * ti + 4 * i + lk, c = 16 * tj + lr;
+        V[(long)(cur.tile * SB + r) * pp + gidx(c, qI, qJ)] = acc[i];
+      }
+    } else {
+      const int pI = pc[2 * cur.P], pJ = pc[2 * cur.P + 1];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int r = 16 * ti + 4 * i + lk, c = 16 * tj + lr;
-    Aout[(long)gidx(r, pI, pJ) * pp + gidx(c, qI, qJ)] = out[i];
+      for (int i = 0; i < 4; ++i) T1[16 * ti + 4 * i + lk][16 * tj + lr] = acc[i];
+      __syncthreads();
+      f64x4 out = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int k0 = 0; k0 < SB; k0 += 4)
+        out = mfma_f64(RP[k0 + lk][16 * ti + lr], T1[k0 + lk][16 * tj + lr], out);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = 16 * ti + 4 * i + lk, c = 16 * tj + lr;
+        Aout[(long)gidx(r, pI, pJ) * pp + gidx(c, qI, qJ)] = out[i];
+      }
+    }
+    item = next;
+    if (item >= nitems) break;
   }
 }
 
@@ -473,6 +547,9 @@ int syev(hipStream_t s, int p, const double* H, long ldh, double* w, double* V, 
   const double total = host[1];
   int cur = 0, rc = 0;  // A in Aw[cur], rotations of the next round in Rb[rc]
   bool solved = false;
+  // update workers: about as many as fit on the chip next to the solves (4 per CU)
+  const int nitems = np * np + np * (pp / SB);
+  const int nw = std::min(nitems, std::max(256, 4 * 256 - np));
   while (sweep < max_sweeps && np > 0) {
     if (host[0] <= tol_rel * tol_rel * total) break;
     if (sweep > 0 && host[2] == 0.0) break;
@@ -485,10 +562,11 @@ int syev(hipStream_t s, int p, const double* H, long ldh, double* w, double* V, 
     if (kt) LYAP_TRY(kt->mark(s, &e0));
     for (int r = 0; r < rounds; ++r) {
       const int* pc = pairs + (size_t)r * np * 2;
-      const int* pn = pairs + (size_t)((r + 1) % rounds) * np * 2;
-      hipLaunchKernelGGL(jac_round, dim3(np + np * np + np * (pp / SB)), dim3(NTJ), 0, s, pp, np,
-                         Aw[cur], Aw[cur ^ 1], Vw, pc, r, Rb[rc], pn, Rb[rc ^ 1], thr, eps,
-                         applied);
+      const int rn = (r + 1) % rounds;
+      const int* pn = pairs + (size_t)rn * np * 2;
+      hipLaunchKernelGGL(jac_round, dim3(np + nw), dim3(NTJ), 0, s, pp, np,
+                         Aw[cur], Aw[cur ^ 1], Vw, pc, r, Rb[rc], pn, rn == 0 ? 1 : 0, Rb[rc ^ 1],
+                         thr, eps, applied);
       cur ^= 1;
       rc ^= 1;
     }

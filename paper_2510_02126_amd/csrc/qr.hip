@@ -163,15 +163,34 @@ __device__ void panel_factor(double (&a)[RPR][CPT], int r, int w, PanelLds& L) {
     }
   }
   __syncthreads();
-  // Tw[c][c] = tau_c; Tw[c][k] = -tau_k sum_{c <= c' < k} Tw[c][c'] Zs[k][c'] (row c by thread c)
-  if (t < kmax) {
-    L.Tw[t][t] = L.tau[t];
-    for (int k = t + 1; k < kmax; ++k) {
-      double s = 0.0;
-#pragma unroll
-      for (int cp = 0; cp < PB; ++cp)
-        s += (cp >= t && cp < k) ? L.Tw[t][cp] * L.Zs[k][cp] : 0.0;
-      L.Tw[t][k] = -L.tau[k] * s;
+  // Tw is the inverse of the upper triangular U with U[c][c] = 1 / tau_c and U[c][k] = v_c^T v_k
+  // = Zs[k][c] (c < k): the recurrence Tw_k = [[Tw_{k-1}, -tau_k Tw_{k-1} V^T v_k], [0, tau_k]]
+  // inverts to [[U_{k-1}, V^T v_k], [0, 1 / tau_k]].  It is inverted by doubling: with the
+  // diagonal blocks Tw11, Tw22 (s x s) of a 2s x 2s diagonal block known, its upper right block
+  // is -Tw11 U12 Tw22.  Diagonal entries are set to tau_c directly, so a reflector with tau = 0
+  // (an identity factor) gets a zero row and column, as in the recurrence; indices >= kmax
+  // stay zero.
+  if (t < kmax) L.Tw[t][t] = L.tau[t];
+  double* X = &L.part[0][0];  // s x s products of the current level, 16 s entries
+  for (int s = 1; s < PB; s *= 2) {
+    __syncthreads();
+    const int b = t / (s * s), i = (t / s) % s, j = t % s;
+    const int r0 = 2 * s * b, c0 = r0 + s;
+    const bool act = t < 16 * s;  // PB / (2 s) block pairs of s x s entries
+    if (act) {
+      double x = 0.0;  // (U12 Tw22)[i][j], Tw22 upper triangular
+      for (int k = 0; k <= j; ++k) {
+        const int c = r0 + i, kk = c0 + k;
+        const double u = (kk < kmax) ? L.Zs[kk][c] : 0.0;
+        x += u * L.Tw[kk][c0 + j];
+      }
+      X[t] = x;
+    }
+    __syncthreads();
+    if (act) {
+      double y = 0.0;  // (Tw11 X)[i][j], Tw11 upper triangular
+      for (int k = i; k < s; ++k) y += L.Tw[r0 + i][r0 + k] * X[b * s * s + k * s + j];
+      L.Tw[r0 + i][c0 + j] = -y;
     }
   }
   __syncthreads();
