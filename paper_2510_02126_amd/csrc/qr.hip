@@ -18,10 +18,11 @@
 // of Z and L).
 //
 // Panel factorisation: the r x 32 block is held in registers, 4 (or 8) rows x 8 columns per
-// thread.  Step k forms, in one reduction over rows below k, the sums s_c = sum_i A[i][c] A[i][k]
-// for all 32 columns: s_k is the squared norm below the diagonal, s_j (j > k) gives the
-// reflector's action on the trailing columns and s_c (c < k) gives V^T v_k for the Tw
-// recurrence (Tw[0:k, k] = -tau_k Tw[0:k, 0:k] V^T v_k), which is evaluated after the loop.
+// thread, and the 32 steps are unrolled.  Step k forms, in one reduction over rows below k, the
+// sums s_c = sum_i A[i][c] A[i][k] for all 32 columns: s_k is the squared norm below the
+// diagonal, s_j (j > k) gives the reflector's action on the trailing columns and s_c (c < k)
+// gives v_c^T v_k.  Those inner products and the tau_k make up the inverse of Tw
+// (diag(1 / tau) plus the strict upper triangle of V^T V), which is inverted after the loop.
 #include <algorithm>
 #include <cmath>
 
@@ -76,7 +77,10 @@ __device__ void panel_factor(double (&a)[RPR][CPT], int r, int w, PanelLds& L) {
   const int lane = t & 63, wave = t >> 6;
   const int kmax = min(r, w);
   for (int e = t; e < PB * PB; e += NTH) L.Tw[e / PB][e % PB] = 0.0;
-  for (int k = 0; k < kmax; ++k) {
+  // fully unrolled, so the pivot column's group and slot are constants of each step
+#pragma unroll
+  for (int k = 0; k < PB; ++k) {
+    if (k < kmax) {
     const int cgk = k / CPT, jk = k % CPT;
     double x[RPR];
 #pragma unroll
@@ -160,6 +164,7 @@ __device__ void panel_factor(double (&a)[RPR][CPT], int r, int w, PanelLds& L) {
         for (int jj = 0; jj < CPT; ++jj)
           a[i][jj] = (cg == cgk && jj == jk) ? v : a[i][jj] - d[jj] * v;
       }
+    }
     }
   }
   __syncthreads();
