@@ -36,7 +36,6 @@ constexpr int PB = 32;     // panel width
 constexpr int CH = 256;    // chunk rows at level 1
 constexpr int NTH = 256;   // threads per workgroup
 constexpr int MAXCH = 16;  // chunks per panel (n <= 4096)
-constexpr int SL_STACK = 128;  // row slab of the block-reflector application on the stack
 
 constexpr int CPT = 8;         // panel columns per thread
 constexpr int NCG = PB / CPT;  // column groups: thread t owns column group t % NCG
@@ -301,18 +300,16 @@ __device__ inline f64x4 mfma_f64(double a, double b, f64x4 c) {
 // [32 blockIdx.y, ...).  STACK = false: the rows of chunk blockIdx.x (panel rows
 // [b*CH, b*CH + CH) clipped to nr), V = Vg rows of that chunk, Tw = Twg[b].  STACK = true:
 // the stacked rows i < nch*PB, i.e. panel row (i / PB) * CH + i % PB, V = V2, Tw = Tw2.
-// Y = V^T X, Y <- op(Tw) Y, X <- X - V Y, all on the FP64 matrix cores; wave w owns the
-// 16 x 16 tile (w / 2, w % 2) of Y.  Rows are staged through LDS in slabs of SL rows; when
-// all rows fit in one slab it is loaded once for both passes.
-template <bool STACK, int SL>
+// Y = V^T X, Y <- op(Tw) Y, X <- X - V Y, all on the FP64 matrix cores with the operands of
+// V and X loaded from memory straight into the matrix-core lanes.  For Y each wave sums all
+// four 16 x 16 tiles over a quarter of the rows and the four partial sums are added in a
+// fixed order in LDS; for the update each wave takes every fourth 16-row tile.
+template <bool STACK>
 __global__ __launch_bounds__(NTH) void apply_wy(int nr, int nch, bool trans,
                                                 const double* __restrict__ Vsrc,
                                                 const double* __restrict__ Twsrc,
                                                 double* __restrict__ X, long ldx, int ncols) {
-  __shared__ double Vs[SL][PB + 1];
-  __shared__ double Xs[SL][PB + 1];
-  __shared__ double Ys[PB][PB + 1];
-  __shared__ double Ts[PB][PB + 1];
+  __shared__ double Yp[4][PB][PB + 1];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int lr = lane & 15, lk = lane >> 4;
   const int b = STACK ? 0 : blockIdx.x;
@@ -325,62 +322,70 @@ __global__ __launch_bounds__(NTH) void apply_wy(int nr, int nch, bool trans,
     const int g = STACK ? (i / PB) * CH + (i % PB) : b * CH + i;
     return g < nr ? g : -1;
   };
-  auto load_slab = [&](int k0) {
-    for (int e = t; e < SL * PB; e += NTH) {
-      const int i = e / PB, c = e % PB;
-      const int g = xrow(k0 + i);
-      Vs[i][c] = (k0 + i < rows) ? V[(long)(k0 + i) * PB + c] : 0.0;
-      Xs[i][c] = (g >= 0 && c0 + c < ncols) ? X[(long)g * ldx + c0 + c] : 0.0;
-    }
-  };
-  for (int e = t; e < PB * PB; e += NTH) Ts[e / PB][e % PB] = Tw[e];
-  const int ti = wave >> 1, tj = wave & 1;
-  const bool one_slab = rows <= SL;
-  f64x4 acc = {0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < rows; k0 += SL) {
-    load_slab(k0);
-    __syncthreads();
-#pragma unroll 8
-    for (int kk = 0; kk < SL; kk += 4)
-      acc = mfma_f64(Vs[kk + lk][16 * ti + lr], Xs[kk + lk][16 * tj + lr], acc);
-    if (!one_slab) __syncthreads();
+  const bool col0 = c0 + lr < ncols, col1 = c0 + 16 + lr < ncols;
+  // Y partial over rows [i0, i1) of this wave
+  const int rpw = (((rows + 3) / 4 + 3) / 4) * 4;  // a quarter of the rows, a multiple of 4
+  const int i0 = wave * rpw, i1 = min(rows, i0 + rpw);
+  f64x4 y00 = {0.0, 0.0, 0.0, 0.0}, y01 = y00, y10 = y00, y11 = y00;
+#pragma unroll 4
+  for (int k0 = i0; k0 < i1; k0 += 4) {
+    const int i = k0 + lk;
+    const int g = i < i1 ? xrow(i) : -1;
+    const double v0 = i < i1 ? V[(long)i * PB + lr] : 0.0;
+    const double v1 = i < i1 ? V[(long)i * PB + 16 + lr] : 0.0;
+    const double x0 = (g >= 0 && col0) ? X[(long)g * ldx + c0 + lr] : 0.0;
+    const double x1 = (g >= 0 && col1) ? X[(long)g * ldx + c0 + 16 + lr] : 0.0;
+    y00 = mfma_f64(v0, x0, y00);
+    y01 = mfma_f64(v0, x1, y01);
+    y10 = mfma_f64(v1, x0, y10);
+    y11 = mfma_f64(v1, x1, y11);
   }
   // D layout (FP64 16x16x4): lane l, register i -> row 4 i + l / 16, column l % 16
 #pragma unroll
-  for (int i = 0; i < 4; ++i) Ys[16 * ti + 4 * i + lk][16 * tj + lr] = acc[i];
+  for (int i = 0; i < 4; ++i) {
+    Yp[wave][4 * i + lk][lr] = y00[i];
+    Yp[wave][4 * i + lk][16 + lr] = y01[i];
+    Yp[wave][16 + 4 * i + lk][lr] = y10[i];
+    Yp[wave][16 + 4 * i + lk][16 + lr] = y11[i];
+  }
   __syncthreads();
+  for (int e = t; e < PB * PB; e += NTH) {
+    const int i = e / PB, c = e % PB;
+    Yp[0][i][c] = ((Yp[0][i][c] + Yp[1][i][c]) + Yp[2][i][c]) + Yp[3][i][c];
+  }
+  __syncthreads();
+  // Y2 = op(Tw) Y into Yp[1]: wave w owns the 16 x 16 tile (w / 2, w % 2)
+  const int ti = wave >> 1, tj = wave & 1;
   f64x4 y2 = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int k = 0; k < PB; k += 4) {
-    const double aop = trans ? Ts[k + lk][16 * ti + lr] : Ts[16 * ti + lr][k + lk];
-    y2 = mfma_f64(aop, Ys[k + lk][16 * tj + lr], y2);
+    const double aop = trans ? Tw[(k + lk) * PB + 16 * ti + lr] : Tw[(16 * ti + lr) * PB + k + lk];
+    y2 = mfma_f64(aop, Yp[0][k + lk][16 * tj + lr], y2);
   }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) Yp[1][16 * ti + 4 * i + lk][16 * tj + lr] = y2[i];
   __syncthreads();
+  // X <- X - V Y2, 16-row tiles
+  for (int r0 = 16 * wave; r0 < rows; r0 += 64) {
+    double vt[PB / 4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) Ys[16 * ti + 4 * i + lk][16 * tj + lr] = y2[i];
-  __syncthreads();
-  constexpr int WR = SL / 4;  // slab rows per wave in the update
-  for (int k0 = 0; k0 < rows; k0 += SL) {
-    if (!one_slab) {
-      load_slab(k0);
-      __syncthreads();
-    }
+    for (int q = 0; q < PB / 4; ++q)
+      vt[q] = r0 + lr < rows ? V[(long)(r0 + lr) * PB + 4 * q + lk] : 0.0;
 #pragma unroll
-    for (int rt = 0; rt < WR / 16; ++rt)
+    for (int cj = 0; cj < 2; ++cj) {
+      f64x4 u = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int cj = 0; cj < 2; ++cj) {
-        const int r0 = WR * wave + 16 * rt;
-        f64x4 u = {0.0, 0.0, 0.0, 0.0};
+      for (int q = 0; q < PB / 4; ++q) u = mfma_f64(vt[q], Yp[1][4 * q + lk][16 * cj + lr], u);
+      const bool cok = cj == 0 ? col0 : col1;
 #pragma unroll
-        for (int k = 0; k < PB; k += 4) u = mfma_f64(Vs[r0 + lr][k + lk], Ys[k + lk][16 * cj + lr], u);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int li = r0 + 4 * i + lk, c = 16 * cj + lr;
-          const int g = xrow(k0 + li);
-          if (g >= 0 && c0 + c < ncols) X[(long)g * ldx + c0 + c] = Xs[li][c] - u[i];
+      for (int i = 0; i < 4; ++i) {
+        const int g = xrow(r0 + 4 * i + lk);
+        if (g >= 0 && cok) {
+          double* px = X + (long)g * ldx + c0 + 16 * cj + lr;
+          *px = *px - u[i];
         }
       }
-    if (!one_slab) __syncthreads();
+    }
   }
 }
 
@@ -455,9 +460,9 @@ int qr(hipStream_t s, int n, int p, const double* F, long ldf, double* U, long l
     if (rest > 0) {
       double* X = P + w;  // rows [c, n), columns [c+w, p)
       const unsigned ct = (unsigned)ceil_div(rest, PB);
-      hipLaunchKernelGGL((apply_wy<false, CH>), dim3(nch, ct), dim3(NTH), 0, s, nr, nch, true,
+      hipLaunchKernelGGL((apply_wy<false>), dim3(nch, ct), dim3(NTH), 0, s, nr, nch, true,
                          pans[j].Vg, pans[j].Twg, X, (long)p, rest);
-      hipLaunchKernelGGL((apply_wy<true, SL_STACK>), dim3(1, ct), dim3(NTH), 0, s, nr, nch, true,
+      hipLaunchKernelGGL((apply_wy<true>), dim3(1, ct), dim3(NTH), 0, s, nr, nch, true,
                          pans[j].V2, pans[j].Tw2, X, (long)p, rest);
       hipLaunchKernelGGL(copy_rows, dim3(nb256((long)w * rest)), dim3(256), 0, s, w, rest, X,
                          (long)p, T + (long)c * ldt + c + w, ldt);
@@ -471,9 +476,9 @@ int qr(hipStream_t s, int n, int p, const double* F, long ldf, double* U, long l
     const int cols = kk - c;
     const unsigned ct = (unsigned)ceil_div(cols, PB);
     double* X = U + (long)c * ldu + c;
-    hipLaunchKernelGGL((apply_wy<true, SL_STACK>), dim3(1, ct), dim3(NTH), 0, s, nr, nch, false,
+    hipLaunchKernelGGL((apply_wy<true>), dim3(1, ct), dim3(NTH), 0, s, nr, nch, false,
                        pans[j].V2, pans[j].Tw2, X, ldu, cols);
-    hipLaunchKernelGGL((apply_wy<false, CH>), dim3(nch, ct), dim3(NTH), 0, s, nr, nch, false,
+    hipLaunchKernelGGL((apply_wy<false>), dim3(nch, ct), dim3(NTH), 0, s, nr, nch, false,
                        pans[j].Vg, pans[j].Twg, X, ldu, cols);
     LYAP_HIP(hipGetLastError());
   }
