@@ -51,29 +51,40 @@ __device__ inline double rsqrt_nr(double x) {
   h = 0.5 * x * y;
   return fma(y, fma(-h, y, 0.5), y);
 }
+// FP32: one Newton step on the hardware estimate
+__device__ inline float recip(float x) {
+  const float r = __builtin_amdgcn_rcpf(x);
+  return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+__device__ inline float rsqrt_nr(float x) {
+  const float y = __builtin_amdgcn_rsqf(x);
+  const float h = 0.5f * x * y;
+  return fmaf(y, fmaf(-h, y, 0.5f), y);
+}
 
 // Rotation zeroing a_pq of the 2 x 2 block [[app, apq], [apq, aqq]], or none (c = 1, s = 0)
 // when |a_pq| <= thr or |a_pq| <= eps sqrt(|a_pp a_qq|); returns whether it is applied.
 // t = tan(angle) is the smaller root of t^2 + 2 theta t - 1 = 0, c = 1 / sqrt(1 + t^2).
-__device__ inline bool rot_params(double app, double aqq, double apq, double thr, double eps,
-                                  double& c, double& s) {
-  const double a = fabs(apq);
+template <class T>
+__device__ inline bool rot_params(T app, T aqq, T apq, T thr, T eps, T& c, T& s) {
+  const T a = fabs(apq);
   if (a <= thr || a * a <= eps * eps * fabs(app * aqq)) {
-    c = 1.0;
-    s = 0.0;
+    c = T(1);
+    s = T(0);
     return false;
   }
-  const double theta = (aqq - app) * recip(2.0 * apq);
-  const double at = fabs(theta);
-  double t;
-  if (at > 1e150) {
-    t = 0.5 * recip(theta);
+  const T theta = (aqq - app) * recip(T(2) * apq);
+  const T at = fabs(theta);
+  const T big = sizeof(T) == 8 ? T(1e150) : T(1e18);  // theta^2 would overflow
+  T t;
+  if (at > big) {
+    t = T(0.5) * recip(theta);
   } else {
-    const double q = 1.0 + theta * theta;
-    const double h = q * rsqrt_nr(q);  // sqrt(1 + theta^2)
+    const T q = T(1) + theta * theta;
+    const T h = q * rsqrt_nr(q);  // sqrt(1 + theta^2)
     t = copysign(recip(at + h), theta);
   }
-  c = rsqrt_nr(1.0 + t * t);
+  c = rsqrt_nr(T(1) + t * t);
   s = t * c;
   return true;
 }
@@ -85,18 +96,34 @@ __device__ inline int circle_elem(int slot, int r, int m) {
   return 1 + (slot - 1 + r) % (m - 1);
 }
 
-__device__ inline f64x4 mfma_f64(double a, double b, f64x4 c) {
-  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
+// 16 x 16 x 4 matrix-core products.  A operand: lane l holds A[l % 16][l / 16]; B operand:
+// B[l / 16][l % 16]; result register i of lane l is row row(i, l / 16), column l % 16, which
+// differs between the FP64 and FP32 instructions.
+template <class T> struct Mf;
+template <> struct Mf<double> {
+  using V4 = f64x4;
+  static __device__ V4 mma(double a, double b, V4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ int row(int i, int lk) { return 4 * i + lk; }
+};
+template <> struct Mf<float> {
+  using V4 = f32x4;
+  static __device__ V4 mma(float a, float b, V4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ int row(int i, int lk) { return 4 * lk + i; }
+};
 
 __device__ inline int gidx(int i, int bi, int bj) { return i < HB ? bi * HB + i : bj * HB + (i - HB); }
 
 // LDS of a round workgroup (four 32 x 32 buffers, so four workgroups fit on a CU).  A solve
 // uses S[0..1] and R[0..1] for the sweep and, while it forms its subproblem, S[1] / R[1] /
 // R[0] as staging (X / RA / RB); an update workgroup uses all four for its operands.
+template <class T>
 struct SolveLds {
-  double S[2][SB][LDS_PAD];  // subproblem, double-buffered by step parity
-  double R[2][SB][LDS_PAD];  // accumulated rotation
+  T S[2][SB][LDS_PAD];  // subproblem, double-buffered by step parity
+  T R[2][SB][LDS_PAD];  // accumulated rotation
   int any;
 };
 
@@ -130,13 +157,14 @@ __device__ inline void step_pair(bool full, int k, int r, int& p, int& q) {
 // b = t % 16 columns).  Lanes 0..15 of each wave compute the 16 rotations of the step and the
 // other lanes fetch theirs by lane permutation; every thread reads the current buffer and
 // writes its block of the other one, so a step needs a single barrier.
-__device__ int subproblem_sweep(SolveLds& L, double thr, double eps, bool full) {
+template <class T>
+__device__ int subproblem_sweep(SolveLds<T>& L, T thr, T eps, bool full) {
   const int t = threadIdx.x, lane = t & 63;
   const int a = t / (SB / 2), b = t % (SB / 2);
   const int steps = full ? SB - 1 : HB;
   for (int r = 0; r < steps; ++r) {
     const int cur = r & 1, nxt = cur ^ 1;
-    double c = 1.0, sn = 0.0;
+    T c = T(1), sn = T(0);
     if (lane < SB / 2) {
       int p, q;
       step_pair(full, lane, r, p, q);
@@ -144,18 +172,18 @@ __device__ int subproblem_sweep(SolveLds& L, double thr, double eps, bool full) 
           t == lane)
         L.any = 1;
     }
-    const double ca = __shfl(c, a), sa = __shfl(sn, a);
-    const double cb = __shfl(c, b), sb = __shfl(sn, b);
+    const T ca = __shfl(c, a), sa = __shfl(sn, a);
+    const T cb = __shfl(c, b), sb = __shfl(sn, b);
     int p0, q0, p1, q1;
     step_pair(full, a, r, p0, q0);
     step_pair(full, b, r, p1, q1);
-    const double m00 = L.S[cur][p0][p1], m01 = L.S[cur][p0][q1];
-    const double m10 = L.S[cur][q0][p1], m11 = L.S[cur][q0][q1];
-    const double r00 = L.R[cur][p0][p1], r01 = L.R[cur][p0][q1];
-    const double r10 = L.R[cur][q0][p1], r11 = L.R[cur][q0][q1];
+    const T m00 = L.S[cur][p0][p1], m01 = L.S[cur][p0][q1];
+    const T m10 = L.S[cur][q0][p1], m11 = L.S[cur][q0][q1];
+    const T r00 = L.R[cur][p0][p1], r01 = L.R[cur][p0][q1];
+    const T r10 = L.R[cur][q0][p1], r11 = L.R[cur][q0][q1];
     // G_a^T M G_b and R G_b
-    const double x00 = ca * m00 - sa * m10, x01 = ca * m01 - sa * m11;
-    const double x10 = sa * m00 + ca * m10, x11 = sa * m01 + ca * m11;
+    const T x00 = ca * m00 - sa * m10, x01 = ca * m01 - sa * m11;
+    const T x10 = sa * m00 + ca * m10, x11 = sa * m01 + ca * m11;
     L.S[nxt][p0][p1] = x00 * cb - x01 * sb;
     L.S[nxt][p0][q1] = x00 * sb + x01 * cb;
     L.S[nxt][q0][p1] = x10 * cb - x11 * sb;
@@ -172,15 +200,16 @@ __device__ int subproblem_sweep(SolveLds& L, double thr, double eps, bool full) 
 // Solve workgroup for pair j = (bI, bJ) of ``pn``: form its subproblem, run one sweep, store
 // the rotation to Rn[j].  With Rc == nullptr the subproblem is read from A directly; otherwise
 // A is the matrix before the round whose pairs ``pc`` and rotations Rc are given.
-__device__ void solve_pair(SolveLds& L, int pp, int np, const double* __restrict__ A,
-                           const int* __restrict__ pc, int rc, const double* __restrict__ Rc,
-                           const int* __restrict__ pn, int j, bool full, double thr, double eps,
-                           double* __restrict__ Rn, int* __restrict__ applied) {
+template <class T>
+__device__ void solve_pair(SolveLds<T>& L, int pp, int np, const T* __restrict__ A,
+                           const int* __restrict__ pc, int rc, const T* __restrict__ Rc,
+                           const int* __restrict__ pn, int j, bool full, T thr, T eps,
+                           T* __restrict__ Rn, int* __restrict__ applied) {
   const int t = threadIdx.x;
   const int nI = pn[2 * j], nJ = pn[2 * j + 1];
-  double (&X)[SB][LDS_PAD] = L.S[1];
-  double (&RA)[SB][LDS_PAD] = L.R[1];
-  double (&RB)[SB][LDS_PAD] = L.R[0];
+  T (&X)[SB][LDS_PAD] = L.S[1];
+  T (&RA)[SB][LDS_PAD] = L.R[1];
+  T (&RB)[SB][LDS_PAD] = L.R[0];
   if (t == 0) L.any = 0;
   if (!Rc) {
     for (int e = t; e < SB * SB; e += NTJ) {
@@ -205,7 +234,7 @@ __device__ void solve_pair(SolveLds& L, int pp, int np, const double* __restrict
     }
     // all four blocks of the current matrix and both rotations, loaded at once (thread t
     // owns elements t + 256 q)
-    double xr[4][4], ra[4], rb[4];
+    T xr[4][4], ra[4], rb[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int e = t + NTJ * q, i = e / SB, k = e % SB;
@@ -234,12 +263,12 @@ __device__ void solve_pair(SolveLds& L, int pp, int np, const double* __restrict
       }
       __syncthreads();
       // Y = X R_P[h2][:, half H[h2]]  (32 x 16): thread (i = t / 8, columns 2 (t % 8) + {0, 1})
-      double (&R2)[SB][LDS_PAD] = h2 == 0 ? RA : RB;
-      double (&R1)[SB][LDS_PAD] = h1 == 0 ? RA : RB;
+      T (&R2)[SB][LDS_PAD] = h2 == 0 ? RA : RB;
+      T (&R1)[SB][LDS_PAD] = h1 == 0 ? RA : RB;
       const int yi = t / 8, yc = 2 * (t % 8);
-      double y0 = 0.0, y1 = 0.0;
+      T y0 = T(0), y1 = T(0);
       for (int k = 0; k < SB; ++k) {
-        const double x = X[yi][k];
+        const T x = X[yi][k];
         y0 += x * R2[k][HB * H[h2] + yc];
         y1 += x * R2[k][HB * H[h2] + yc + 1];
       }
@@ -249,7 +278,7 @@ __device__ void solve_pair(SolveLds& L, int pp, int np, const double* __restrict
       __syncthreads();
       // S block = R_P[h1][:, half H[h1]]^T Y  (16 x 16): thread (i = t / 16, c = t % 16)
       const int si = t / HB, sc = t % HB;
-      double sum = 0.0;
+      T sum = T(0);
       for (int k = 0; k < SB; ++k) sum += R1[k][HB * H[h1] + si] * X[k][sc];
       L.S[0][HB * h1 + si][HB * h2 + sc] = sum;
     }
@@ -257,24 +286,24 @@ __device__ void solve_pair(SolveLds& L, int pp, int np, const double* __restrict
   }
   for (int e = t; e < SB * SB; e += NTJ) {
     const int i = e / SB, k = e % SB;
-    L.R[0][i][k] = (i == k) ? 1.0 : 0.0;
+    L.R[0][i][k] = (i == k) ? T(1) : T(0);
   }
   __syncthreads();
   const int res = subproblem_sweep(L, thr, eps, full);
-  double* Ro = Rn + (long)j * SB * SB;
+  T* Ro = Rn + (long)j * SB * SB;
   for (int e = t; e < SB * SB; e += NTJ) Ro[e] = L.R[res][e / SB][e % SB];
   if (t == 0 && L.any) atomicAdd(applied, 1);
 }
 
 // First solve of the iteration (subproblems read from A).
-__global__ __launch_bounds__(NTJ) void jac_solve0(int pp, int np, const double* __restrict__ A,
+template <class T>
+__global__ __launch_bounds__(NTJ) void jac_solve0(int pp, int np, const T* __restrict__ A,
                                                   const int* __restrict__ pn,
                                                   const double* __restrict__ thr_dev, double eps,
-                                                  double* __restrict__ Rn,
-                                                  int* __restrict__ applied) {
-  __shared__ SolveLds L;
-  solve_pair(L, pp, np, A, nullptr, 0, nullptr, pn, blockIdx.x, true, *thr_dev, eps, Rn,
-             applied);
+                                                  T* __restrict__ Rn, int* __restrict__ applied) {
+  __shared__ SolveLds<T> L;
+  solve_pair<T>(L, pp, np, A, nullptr, 0, nullptr, pn, blockIdx.x, true, (T)*thr_dev, (T)eps,
+                Rn, applied);
 }
 
 // One round.  Blocks [0, np): solves of the next round's pairs pn (rotations to Rn; a full
@@ -306,10 +335,10 @@ __device__ inline Item decode_item(int item, int np) {
 }
 
 // thread t loads elements t + 256 q (q < 4) of the item's three 32 x 32 operands
+template <class T>
 __device__ inline void load_item(const Item& it, int pp, const int* __restrict__ pc,
-                                 const double* __restrict__ Ain, const double* __restrict__ V,
-                                 const double* __restrict__ Rc, double (&m)[4], double (&rq)[4],
-                                 double (&rp)[4]) {
+                                 const T* __restrict__ Ain, const T* __restrict__ V,
+                                 const T* __restrict__ Rc, T (&m)[4], T (&rq)[4], T (&rp)[4]) {
   const int t = threadIdx.x;
   const int qI = pc[2 * it.Q], qJ = pc[2 * it.Q + 1];
   const int pI = pc[2 * it.P], pJ = pc[2 * it.P + 1];
@@ -326,36 +355,38 @@ __device__ inline void load_item(const Item& it, int pp, const int* __restrict__
   }
 }
 
-__global__ __launch_bounds__(NTJ) void jac_round(int pp, int np, const double* __restrict__ Ain,
-                                                 double* __restrict__ Aout,
-                                                 double* __restrict__ V,
+template <class T>
+__global__ __launch_bounds__(NTJ) void jac_round(int pp, int np, const T* __restrict__ Ain,
+                                                 T* __restrict__ Aout, T* __restrict__ V,
                                                  const int* __restrict__ pc, int rc,
-                                                 const double* __restrict__ Rc,
+                                                 const T* __restrict__ Rc,
                                                  const int* __restrict__ pn, int full,
-                                                 double* __restrict__ Rn,
+                                                 T* __restrict__ Rn,
                                                  const double* __restrict__ thr_dev, double eps,
                                                  int* __restrict__ applied) {
-  __shared__ SolveLds L;
+  using M4 = Mf<T>;
+  __shared__ SolveLds<T> L;
   const int blk = blockIdx.x;
   if (blk < np) {
-    solve_pair(L, pp, np, Ain, pc, rc, Rc, pn, blk, full != 0, *thr_dev, eps, Rn, applied);
+    solve_pair<T>(L, pp, np, Ain, pc, rc, Rc, pn, blk, full != 0, (T)*thr_dev, (T)eps, Rn,
+                  applied);
     return;
   }
   const int nw = gridDim.x - np;
   const int nitems = np * np + np * (pp / SB);
   int item = blk - np;
   if (item >= nitems) return;
-  double (&M)[SB][LDS_PAD] = L.S[1];
-  double (&RQ)[SB][LDS_PAD] = L.S[0];
-  double (&RP)[SB][LDS_PAD] = L.R[1];
-  double (&T1)[SB][LDS_PAD] = L.R[0];
+  T (&M)[SB][LDS_PAD] = L.S[1];
+  T (&RQ)[SB][LDS_PAD] = L.S[0];
+  T (&RP)[SB][LDS_PAD] = L.R[1];
+  T (&T1)[SB][LDS_PAD] = L.R[0];
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
   const int ti = wave >> 1, tj = wave & 1;
   const int lr = lane & 15, lk = lane >> 4;
-  double m[4], rq[4], rp[4];
+  T m[4], rq[4], rp[4];
   Item it = decode_item(item, np);
-  load_item(it, pp, pc, Ain, V, Rc, m, rq, rp);
+  load_item<T>(it, pp, pc, Ain, V, Rc, m, rq, rp);
   while (true) {
     __syncthreads();  // the previous item's operands are no longer read
 #pragma unroll
@@ -370,32 +401,31 @@ __global__ __launch_bounds__(NTJ) void jac_round(int pp, int np, const double* _
     const int next = item + nw;
     if (next < nitems) {
       it = decode_item(next, np);
-      load_item(it, pp, pc, Ain, V, Rc, m, rq, rp);
+      load_item<T>(it, pp, pc, Ain, V, Rc, m, rq, rp);
     }
     const int qI = pc[2 * cur.Q], qJ = pc[2 * cur.Q + 1];
-    f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+    typename M4::V4 acc = {T(0), T(0), T(0), T(0)};
 #pragma unroll
     for (int k0 = 0; k0 < SB; k0 += 4)
-      acc = mfma_f64(M[16 * ti + lr][k0 + lk], RQ[k0 + lk][16 * tj + lr], acc);
-    // D layout (FP64 16x16x4): lane l, register i -> row 4 i + l / 16, column l % 16
+      acc = M4::mma(M[16 * ti + lr][k0 + lk], RQ[k0 + lk][16 * tj + lr], acc);
     if (!cur.isA) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int r = 16 * ti + 4 * i + lk, c = 16 * tj + lr;
+        const int r = 16 * ti + M4::row(i, lk), c = 16 * tj + lr;
         V[(long)(cur.tile * SB + r) * pp + gidx(c, qI, qJ)] = acc[i];
       }
     } else {
       const int pI = pc[2 * cur.P], pJ = pc[2 * cur.P + 1];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) T1[16 * ti + 4 * i + lk][16 * tj + lr] = acc[i];
+      for (int i = 0; i < 4; ++i) T1[16 * ti + M4::row(i, lk)][16 * tj + lr] = acc[i];
       __syncthreads();
-      f64x4 out = {0.0, 0.0, 0.0, 0.0};
+      typename M4::V4 out = {T(0), T(0), T(0), T(0)};
 #pragma unroll
       for (int k0 = 0; k0 < SB; k0 += 4)
-        out = mfma_f64(RP[k0 + lk][16 * ti + lr], T1[k0 + lk][16 * tj + lr], out);
+        out = M4::mma(RP[k0 + lk][16 * ti + lr], T1[k0 + lk][16 * tj + lr], out);
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int r = 16 * ti + 4 * i + lk, c = 16 * tj + lr;
+        const int r = 16 * ti + M4::row(i, lk), c = 16 * tj + lr;
         Aout[(long)gidx(r, pI, pJ) * pp + gidx(c, qI, qJ)] = out[i];
       }
     }
@@ -404,24 +434,26 @@ __global__ __launch_bounds__(NTJ) void jac_round(int pp, int np, const double* _
   }
 }
 
+template <class T>
 __global__ void jac_load(int p, int pp, const double* __restrict__ H, long ldh,
-                         double* __restrict__ A, double* __restrict__ V) {
+                         T* __restrict__ A, T* __restrict__ V) {
   long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (long)pp * pp) return;
   int i = (int)(idx / pp), j = (int)(idx % pp);
   double v = 0.0;
   if (i < p && j < p) v = 0.5 * (H[(long)i * ldh + j] + H[(long)j * ldh + i]);
-  A[idx] = v;
-  V[idx] = (i == j) ? 1.0 : 0.0;
+  A[idx] = (T)v;
+  V[idx] = (i == j) ? T(1) : T(0);
 }
 
 // partial sums: [0] off-diagonal squares, [1] all squares (rows strided over blocks)
-__global__ void jac_norms(int pp, const double* __restrict__ A, double* __restrict__ part) {
+template <class T>
+__global__ void jac_norms(int pp, const T* __restrict__ A, double* __restrict__ part) {
   __shared__ double r0[256], r1[256];
   double off = 0.0, all = 0.0;
   for (int i = blockIdx.x; i < pp; i += gridDim.x)
     for (int j = threadIdx.x; j < pp; j += 256) {
-      const double v = A[(long)i * pp + j];
+      const double v = (double)A[(long)i * pp + j];
       const double v2 = v * v;
       all += v2;
       if (i != j) off += v2;
@@ -461,10 +493,11 @@ __global__ void jac_norms_finish(int nparts, const double* __restrict__ part,
 
 // Sort the first p diagonal entries by descending |value| (ties by index): one workgroup, rank
 // computed by counting.
-__global__ __launch_bounds__(1024) void jac_sort(int p, int pp, const double* __restrict__ A,
+template <class T>
+__global__ __launch_bounds__(1024) void jac_sort(int p, int pp, const T* __restrict__ A,
                                                  int* __restrict__ perm, double* __restrict__ w) {
   __shared__ double dg[4096];
-  for (int i = threadIdx.x; i < p; i += 1024) dg[i] = A[(long)i * pp + i];
+  for (int i = threadIdx.x; i < p; i += 1024) dg[i] = (double)A[(long)i * pp + i];
   __syncthreads();
   for (int i = threadIdx.x; i < p; i += 1024) {
     double ai = dg[i], ki = fabs(ai);
@@ -478,12 +511,13 @@ __global__ __launch_bounds__(1024) void jac_sort(int p, int pp, const double* __
   }
 }
 
-__global__ void jac_gather(int p, int pp, const double* __restrict__ Vw, const int* __restrict__ perm,
+template <class T>
+__global__ void jac_gather(int p, int pp, const T* __restrict__ Vw, const int* __restrict__ perm,
                            double* __restrict__ V, long ldv) {
   long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (long)p * p) return;
   int i = (int)(idx / p), k = (int)(idx % p);
-  V[(long)i * ldv + k] = Vw[(long)i * pp + perm[k]];
+  V[(long)i * ldv + k] = (double)Vw[(long)i * pp + perm[k]];
 }
 
 }  // namespace
@@ -499,15 +533,16 @@ size_t syev_workspace_bytes(int p) {
   return s + 4096;
 }
 
-int syev(hipStream_t s, int p, const double* H, long ldh, double* w, double* V, long ldv,
-         Arena& ws, double tol_rel, int* sweeps_out, KernTimer* kt, bool relative) {
-  if (p <= 0) return LYAP_OK;
-  if (p > 4096) return LYAP_BADARG;
+namespace {
+
+template <class T>
+int syev_t(hipStream_t s, int p, const double* H, long ldh, double* w, double* V, long ldv,
+           Arena& ws, double tol_rel, int* sweeps_out, KernTimer* kt, bool relative) {
   const int pp = ceil_div(p, SB) * SB;
   const int nb = pp / HB, np = nb / 2, rounds = nb - 1;
-  double* Aw[2] = {ws.take<double>((size_t)pp * pp), ws.take<double>((size_t)pp * pp)};
-  double* Vw = ws.take<double>((size_t)pp * pp);
-  double* Rb[2] = {ws.take<double>((size_t)np * SB * SB), ws.take<double>((size_t)np * SB * SB)};
+  T* Aw[2] = {ws.take<T>((size_t)pp * pp), ws.take<T>((size_t)pp * pp)};
+  T* Vw = ws.take<T>((size_t)pp * pp);
+  T* Rb[2] = {ws.take<T>((size_t)np * SB * SB), ws.take<T>((size_t)np * SB * SB)};
   int* pairs = ws.take<int>((size_t)rounds * np * 2 + 2);
   double* part = ws.take<double>(2 * 256);
   double* scal = ws.take<double>(4);
@@ -530,11 +565,11 @@ int syev(hipStream_t s, int p, const double* H, long ldh, double* w, double* V, 
     }
   LYAP_HIP(hipMemcpyAsync(pairs, sched.data(), sched.size() * sizeof(int), hipMemcpyHostToDevice,
                           s));
-  hipLaunchKernelGGL(jac_load, dim3((unsigned)ceil_div(pp * pp, 256)), dim3(256), 0, s, p, pp, H,
+  hipLaunchKernelGGL((jac_load<T>), dim3((unsigned)ceil_div(pp * pp, 256)), dim3(256), 0, s, p, pp, H,
                      ldh, Aw[0], Vw);
   const int nparts = 64;
   double* thr = scal + 3;
-  hipLaunchKernelGGL(jac_norms, dim3(nparts), dim3(256), 0, s, pp, Aw[0], part);
+  hipLaunchKernelGGL((jac_norms<T>), dim3(nparts), dim3(256), 0, s, pp, Aw[0], part);
   const double thr_rel = 0.25 * tol_rel / pp;
   hipLaunchKernelGGL(jac_norms_finish, dim3(1), dim3(1), 0, s, nparts, part, scal, thr_rel, thr,
                      applied);
@@ -554,7 +589,7 @@ int syev(hipStream_t s, int p, const double* H, long ldh, double* w, double* V, 
     if (host[0] <= tol_rel * tol_rel * total) break;
     if (sweep > 0 && host[2] == 0.0) break;
     if (!solved) {
-      hipLaunchKernelGGL(jac_solve0, dim3(np), dim3(NTJ), 0, s, pp, np, Aw[cur], pairs, thr,
+      hipLaunchKernelGGL((jac_solve0<T>), dim3(np), dim3(NTJ), 0, s, pp, np, Aw[cur], pairs, thr,
                          eps, Rb[rc], applied);
       solved = true;
     }
@@ -564,7 +599,7 @@ int syev(hipStream_t s, int p, const double* H, long ldh, double* w, double* V, 
       const int* pc = pairs + (size_t)r * np * 2;
       const int rn = (r + 1) % rounds;
       const int* pn = pairs + (size_t)rn * np * 2;
-      hipLaunchKernelGGL(jac_round, dim3(np + nw), dim3(NTJ), 0, s, pp, np,
+      hipLaunchKernelGGL((jac_round<T>), dim3(np + nw), dim3(NTJ), 0, s, pp, np,
                          Aw[cur], Aw[cur ^ 1], Vw, pc, r, Rb[rc], pn, rn == 0 ? 1 : 0, Rb[rc ^ 1],
                          thr, eps, applied);
       cur ^= 1;
@@ -573,9 +608,9 @@ int syev(hipStream_t s, int p, const double* H, long ldh, double* w, double* V, 
     if (kt) {
       // block update traffic: A read and written, V read and written
       LYAP_TRY(kt->mark(s, &e1));
-      kt->add(e0, e1, 1, (double)rounds * 32.0 * pp * pp, rounds);
+      kt->add(e0, e1, 1, (double)rounds * 4.0 * sizeof(T) * pp * pp, rounds);
     }
-    hipLaunchKernelGGL(jac_norms, dim3(nparts), dim3(256), 0, s, pp, Aw[cur], part);
+    hipLaunchKernelGGL((jac_norms<T>), dim3(nparts), dim3(256), 0, s, pp, Aw[cur], part);
     hipLaunchKernelGGL(jac_norms_finish, dim3(1), dim3(1), 0, s, nparts, part, scal, thr_rel, thr,
                        applied);
     LYAP_HIP(hipGetLastError());
@@ -584,11 +619,21 @@ int syev(hipStream_t s, int p, const double* H, long ldh, double* w, double* V, 
     ++sweep;
   }
   if (sweeps_out) *sweeps_out = sweep;
-  hipLaunchKernelGGL(jac_sort, dim3(1), dim3(1024), 0, s, p, pp, Aw[cur], perm, w);
-  hipLaunchKernelGGL(jac_gather, dim3((unsigned)ceil_div(p * p, 256)), dim3(256), 0, s, p, pp, Vw,
+  hipLaunchKernelGGL((jac_sort<T>), dim3(1), dim3(1024), 0, s, p, pp, Aw[cur], perm, w);
+  hipLaunchKernelGGL((jac_gather<T>), dim3((unsigned)ceil_div(p * p, 256)), dim3(256), 0, s, p, pp, Vw,
                      perm, V, ldv);
   LYAP_HIP(hipGetLastError());
   return LYAP_OK;
+}
+
+}  // namespace
+
+int syev(hipStream_t s, int p, const double* H, long ldh, double* w, double* V, long ldv,
+         Arena& ws, double tol_rel, int* sweeps_out, KernTimer* kt, bool relative, bool single) {
+  if (p <= 0) return LYAP_OK;
+  if (p > 4096) return LYAP_BADARG;
+  if (single) return syev_t<float>(s, p, H, ldh, w, V, ldv, ws, tol_rel, sweeps_out, kt, relative);
+  return syev_t<double>(s, p, H, ldh, w, V, ldv, ws, tol_rel, sweeps_out, kt, relative);
 }
 
 }  // namespace lyap

@@ -64,9 +64,10 @@ size_t syev_workspace_bytes(int p);
 // H = V diag(w) V^T, w sorted by descending |w|.  ``sweeps_out`` (host, optional).
 // Rotations are skipped below tol ||H||_F / (4 p) and, with ``relative``, also below
 // tol sqrt(|h_pp h_qq|) (eigenvalues accurate relative to their own size rather than to
-// ||H||).
+// ||H||).  With ``single`` the rotations run in FP32 (tol must then be >= 1e-6); H, w and V
+// stay FP64.
 int syev(hipStream_t s, int p, const double* H, long ldh, double* w, double* V, long ldv,
          Arena& ws, double tol_rel, int* sweeps_out, KernTimer* kt = nullptr,
-         bool relative = true);
+         bool relative = true, bool single = false);
 
 }  // namespace lyap

@@ -208,9 +208,13 @@ int Solver::rank_trunc(Ctx& c, double* Zb, long ldb, int& cols, std::vector<doub
   c.ws->reset();
   // Inside the solver only eigenvalues above thr max|lambda| are kept and the solver works
   // at u_s: accuracy relative to ||H|| (absolute rotation threshold) is what it can use;
-  // relative accuracy for the discarded small eigenvalues would cost many extra sweeps.
+  // relative accuracy for the discarded small eigenvalues would cost many extra sweeps.  For
+  // u_s of FP16 / BF16 the rotations run in FP32 (Alg 3.2 runs at precision u_s; FP32 keeps
+  // the threshold far above its own rounding).  For u_s = FP32 they stay FP64: FP32
+  // rotations would leave noise eigenvalues at the size of the threshold itself.
+  const bool single = c.us == Prec::F16 || c.us == Prec::BF16;
   LYAP_TRY(syev(s, k, Hm, cap, wv, Vm, cap, *c.ws, std::max(10.0 * thr, 1e-15), nullptr, c.kt,
-                false));
+                false, single));
   std::vector<double> lam(k);
   LYAP_HIP(hipMemcpyAsync(lam.data(), wv, k * sizeof(double), hipMemcpyDeviceToHost, s));
   LYAP_HIP(hipStreamSynchronize(s));
