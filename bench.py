@@ -9,7 +9,8 @@ One step = one complete lyap_solve call (inversions, factor iteration, residual
 factorisations, corrections and updates) that must end with res <= 1e-13; a run whose solves
 do not reach it is reported as DNF.  Prints one JSON line.
 
-  python bench.py [--steps K] [--warmup W] [--us fp32] [--skip-cpu]
+  python bench.py [--steps K] [--warmup W] [--us fp32] [--skip-cpu] [--batched]
+  python bench.py --traffic-run   (one IR solve and a calibration copy, for HBM counters)
 """
 from __future__ import annotations
 
@@ -89,6 +90,26 @@ def _batched(lyap, torch, us):
     return out
 
 
+def _traffic_run(lyap, torch, A, L, S, us):
+    """Untimed: one IR solve, then a plain copy of known size for scaling the HBM counters
+    (a 256 MiB float64 tensor, evicted from the MALL by writing 768 MiB of other data, copied
+    once).  Run under ``rocprofv3 --pmc FETCH_SIZE`` and ``--pmc WRITE_SIZE``."""
+    _, _, info = lyap.solve(A, L, S, precisions=(us, "fp64", "fp64", "fp64"),
+                            raise_on_error=False)
+    torch.cuda.synchronize()
+    print("ir", info["status"], info["res"], "jac_round launches", info["kern_calls"][1],
+          "algorithmic bytes", info["kern_work"][1], flush=True)
+    x = torch.empty(32 * 1024 * 1024, dtype=torch.float64, device="cuda").fill_(1.0)
+    torch.cuda.synchronize()
+    big = torch.empty(96 * 1024 * 1024, dtype=torch.float64, device="cuda").fill_(2.0)
+    torch.cuda.synchronize()
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    del big
+    print("calibration copy bytes", x.numel() * 8, flush=True)
+
+
 def _measured_traffic(kernel):
     """HBM bytes per launch of ``kernel`` from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
     summary, or None when there is none or the kernel's source changed since it was taken."""
@@ -111,7 +132,7 @@ def _measured_traffic(kernel):
     return float(t.group(1))
 
 
-def _cpu_baseline(cfg, steps=3):
+def _cpu_baseline(cfg, steps=6):
     """The oracle's FP64 sign-function Newton solve (Alg 3.2) on the host cores, on a bounded
     sample: its first ``steps`` Newton steps (inversion, scaled update, factor product), scaled
     to the full solve by K / steps with the Newton count K taken from the GPU run."""
@@ -144,6 +165,8 @@ def main():
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--batched", action="store_true",
                     help="also time 256 independent equations, n in [64, 512] (batched mode)")
+    ap.add_argument("--traffic-run", action="store_true",
+                    help="one untimed IR solve and a calibration copy (for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -161,6 +184,9 @@ def main():
     L = torch.from_numpy(cfg["L"]).cuda()
     S = torch.from_numpy(cfg["S"]).cuda()
     n = A.shape[0]
+    if args.traffic_run:
+        _traffic_run(lyap, torch, A, L, S, args.us)
+        return
 
     # plain FP64 sign-function Newton solve (the baseline), then mixed-precision IR
     dt64, inf64 = _time_solves(lyap, torch, A, L, S, "fp64", args.steps, args.warmup)
@@ -205,13 +231,14 @@ def main():
 
     cpu = None
     if not args.skip_cpu:
-        t_step, threads = _cpu_baseline(cfg)
         K = inf64[-1]["inversions"]
+        steps_cpu = max(1, min(6, K))
+        t_step, threads = _cpu_baseline(cfg, steps_cpu)
         t_solve = t_step * K
         cpu = {"value": round(1.0 / t_solve, 6), "unit": "solves/s", "cores": threads,
                "kind": "oracle",
-               "sample": f"oracle FP64 sign-Newton, first 3 of K={K} Newton steps at n={n} "
-                         f"({3 * t_step:.1f} s), scaled to a full solve"}
+               "sample": f"oracle FP64 sign-Newton, first {steps_cpu} of K={K} Newton steps at "
+                         f"n={n} ({steps_cpu * t_step:.1f} s), scaled to a full solve"}
 
     line = {
         "metric": "solves/s at n=4096 to FP64-level residual: mixed-prec IR vs FP64 sign-Newton",
