@@ -58,6 +58,11 @@ size_t qr_workspace_bytes(int n, int p);
 // first.
 int qr(hipStream_t s, int n, int p, const double* F, long ldf, double* U, long ldu, double* T,
        long ldt, Arena& ws, KernTimer* kt = nullptr);
+// The same factorisation when the first c columns of F are orthonormal (block Gram-Schmidt
+// against them, Householder QR of the rest); overwrites columns c.. of F.  Falls back to
+// ``qr`` when c < 32, c >= p or p > n.
+int qr_lead(hipStream_t s, int n, int p, int c, double* F, long ldf, double* U, long ldu,
+            double* T, long ldt, Arena& ws, KernTimer* kt = nullptr);
 
 // ---- eig.hip
 size_t syev_workspace_bytes(int p);

@@ -411,6 +411,14 @@ __global__ void eye_block(int rows, int cols, double* __restrict__ dst, long ldd
   dst[(long)i * ldd + j] = i == j ? 1.0 : 0.0;
 }
 
+__global__ void add_block(int rows, int cols, const double* __restrict__ src, long lds,
+                          double* __restrict__ dst, long ldd) {
+  long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)rows * cols) return;
+  int i = (int)(idx / cols), j = (int)(idx % cols);
+  dst[(long)i * ldd + j] += src[(long)i * lds + j];
+}
+
 inline unsigned nb256(long total) { return (unsigned)((total + 255) / 256); }
 
 }  // namespace
@@ -488,6 +496,50 @@ int qr(hipStream_t s, int n, int p, const double* F, long ldf, double* U, long l
     const double k = kk;
     kt->add(e0, e1, 2, 4.0 * n * k * k - 4.0 * k * k * k / 3.0, 1);
   }
+  return LYAP_OK;
+}
+
+// Thin QR of F = [Z, Y] whose first c columns Z are orthonormal: U = [Z, Q2] and
+// T = [[I, C], [0, R2]] with C = Z^T Y from two block Gram-Schmidt passes (the second removes
+// what rounding left of range(Z) in Y) and Q2 R2 the Householder QR above of Y - Z C.  The
+// same factorisation F = U T as ``qr`` (U orthonormal, T upper triangular) with half the
+// Householder work when c = p / 2.  Y (columns c.. of F) is overwritten.
+int qr_lead(hipStream_t s, int n, int p, int c, double* F, long ldf, double* U, long ldu,
+            double* T, long ldt, Arena& ws, KernTimer* kt) {
+  if (c < PB || c >= p || p > n) return qr(s, n, p, F, ldf, U, ldu, T, ldt, ws, kt);
+  const int q = p - c;
+  double* Y = F + c;
+  double* C = T + c;  // T[0:c, c:p]
+  double* C2 = ws.take<double>((size_t)c * q);
+  const size_t kws = std::min((size_t)8 * c * q, (size_t)4 << 20);
+  double* part = ws.take<double>(kws);
+  if (!C2 || !part) return LYAP_NO_MEMORY;
+  GemmDesc g;  // C <- Z^T Y
+  g.M = c; g.N = q; g.K = n;
+  g.A = F; g.sar = 1; g.sac = ldf;
+  g.B = Y; g.sbr = ldf; g.sbc = 1;
+  g.C = C; g.ldc = ldt;
+  GemmDesc u;  // Y <- Y - Z C
+  u.M = n; u.N = q; u.K = c;
+  u.alpha = -1.0; u.beta = 1.0;
+  u.A = F; u.sar = ldf; u.sac = 1;
+  u.B = C; u.sbr = ldt; u.sbc = 1;
+  u.C = Y; u.ldc = ldf;
+  LYAP_TRY(gemm_f64(s, g, part, kws));
+  LYAP_TRY(gemm_f64(s, u));
+  g.C = C2; g.ldc = q;
+  u.B = C2; u.sbr = q;
+  LYAP_TRY(gemm_f64(s, g, part, kws));
+  LYAP_TRY(gemm_f64(s, u));
+  hipLaunchKernelGGL(add_block, dim3(nb256((long)c * q)), dim3(256), 0, s, c, q, C2, (long)q, C,
+                     ldt);
+  LYAP_HIP(hipGetLastError());
+  LYAP_TRY(qr(s, n, q, Y, ldf, U + c, ldu, T + (long)c * ldt + c, ldt, ws, kt));
+  LYAP_TRY(copy_block(s, n, c, F, ldf, U, ldu));
+  hipLaunchKernelGGL(eye_block, dim3(nb256((long)c * c)), dim3(256), 0, s, c, c, T, ldt);
+  hipLaunchKernelGGL(zero_block, dim3(nb256((long)q * c)), dim3(256), 0, s, q, c,
+                     T + (long)c * ldt, ldt);
+  LYAP_HIP(hipGetLastError());
   return LYAP_OK;
 }
 

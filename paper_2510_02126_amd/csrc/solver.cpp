@@ -95,6 +95,11 @@ struct Solver::Ctx {
   double* part;
   KernTimer* kt = nullptr;
   bool trans = false;  // adjoint equation: products with A^T and with (A_k^{-1})^T
+  // Leading columns known to be orthonormal: of Zs during a factor iteration (a truncated
+  // factor Q V_kept is), and whether the solution factor in Zc is.  The QRs of the
+  // truncation, the residual factorisation and the update then orthogonalise only the rest.
+  int orth = 0;
+  bool zc_orth = false;
 };
 
 int Solver::upload_d(Ctx& c, const std::vector<double>& d, double* dst) {
@@ -196,7 +201,7 @@ int Solver::rank_trunc(Ctx& c, double* Zb, long ldb, int& cols, std::vector<doub
   double* Vm = Vm_.as<double>();
   double* wv = wv_.as<double>();
   c.ws->reset();
-  LYAP_TRY(qr(s, n, cols, Zb, ldb, Uq, cap, Tq, cap, *c.ws, c.kt));
+  LYAP_TRY(qr_lead(s, n, cols, std::min(c.orth, cols), Zb, ldb, Uq, cap, Tq, cap, *c.ws, c.kt));
   LYAP_TRY(upload_d(c, d, dvec_.as<double>()));
   LYAP_TRY(copy_block(s, k, cols, Tq, cap, TN, cap, dvec_.as<double>()));
   GemmDesc g;
@@ -236,14 +241,16 @@ int Solver::rank_trunc(Ctx& c, double* Zb, long ldb, int& cols, std::vector<doub
     LYAP_TRY(gemm_f64(s, z));
   }
   cols = r;
+  c.orth = r;  // Q V_kept has orthonormal columns
   return LYAP_OK;
 }
 
 // ------------------------------------------------------------------ factor iteration
 // eq (3.3): Z_k = [Z_{k-1}, A_{k-1}^{-1} Z_{k-1}], D_k = (mu D, D / mu) / 2, truncating
 // whenever the column count exceeds floor(rho n); finally D <- D / 2.  The products use the
-// cached inverses with operands at the solver precision.  Result in Zs (n x cols).
-int Solver::factor_iteration(Ctx& c, const double* L0, long ld0, int m0,
+// cached inverses with operands at the solver precision.  Result in Zs (n x cols); the first
+// ``orth0`` columns of L0 are orthonormal, and c.orth tells the same of the result.
+int Solver::factor_iteration(Ctx& c, const double* L0, long ld0, int m0, int orth0,
                              const std::vector<double>& d0, bool psd, int& cols,
                              std::vector<double>& d) {
   hipStream_t s = c.s;
@@ -251,6 +258,7 @@ int Solver::factor_iteration(Ctx& c, const double* L0, long ld0, int m0,
   double* Zs = Zs_.as<double>();
   LYAP_TRY(copy_block(s, n, m0, L0, ld0, Zs, cap));
   cols = m0;
+  c.orth = std::min(orth0, m0);
   d = d0;
   const int trunc_at = (int)std::floor(c.opt.rho * n);
   for (int k = 0; k < c.K; ++k) {
@@ -337,7 +345,7 @@ int Solver::res_fac(Ctx& c, const double* Zb, long ldb, int cols, const std::vec
   }
   LYAP_TRY(copy_block(s, n, m, c.L, c.ldl, F + 2 * cols, cap));
   c.ws->reset();
-  LYAP_TRY(qr(s, n, p, F, cap, Uq, cap, Tq, cap, *c.ws, c.kt));
+  LYAP_TRY(qr_lead(s, n, p, c.zc_orth ? cols : 0, F, cap, Uq, cap, Tq, cap, *c.ws, c.kt));
   // TN = T N = [T2 D, T1 D, T3 S]
   LYAP_TRY(upload_d(c, d, dvec_.as<double>()));
   LYAP_TRY(upload_d(c, c.svec, dvec2_.as<double>()));
@@ -419,7 +427,7 @@ int Solver::sol_upt(Ctx& c, int& cols, std::vector<double>& d, int cd,
   LYAP_TRY(copy_block(s, n, cols, Zc, cap, F, cap));
   LYAP_TRY(copy_block(s, n, cd, Zs_.as<double>(), cap, F + cols, cap));
   c.ws->reset();
-  LYAP_TRY(qr(s, n, q, F, cap, Uq, cap, Tq, cap, *c.ws, c.kt));
+  LYAP_TRY(qr_lead(s, n, q, c.zc_orth ? cols : 0, F, cap, Uq, cap, Tq, cap, *c.ws, c.kt));
   std::vector<double> ups(d);
   ups.insert(ups.end(), dd.begin(), dd.end());
   LYAP_TRY(upload_d(c, ups, dvec_.as<double>()));
@@ -454,6 +462,7 @@ int Solver::sol_upt(Ctx& c, int& cols, std::vector<double>& d, int cd,
     LYAP_TRY(gemm_f64(s, z));
   }
   cols = r;
+  c.zc_orth = true;  // U Theta_t
   return LYAP_OK;
 }
 
@@ -568,7 +577,8 @@ int Solver::solve(hipStream_t s, Arena& ws, int* flags, int n, int m, const doub
   t0 = clk::now();
   int cols = 0;
   std::vector<double> d;
-  LYAP_TRY(factor_iteration(c, L, ldl, m, c.svec, c.psd, cols, d));
+  LYAP_TRY(factor_iteration(c, L, ldl, m, 0, c.svec, c.psd, cols, d));
+  c.zc_orth = cols > 0 && c.orth >= cols;
   LYAP_TRY(copy_block(s, n, cols, Zs_.as<double>(), cap, Zc_.as<double>(), cap));
   LYAP_HIP(hipStreamSynchronize(s));
   info->phase_ms[2] += ms_since(t0);
@@ -612,7 +622,7 @@ int Solver::solve(hipStream_t s, Arena& ws, int* flags, int n, int m, const doub
     t0 = clk::now();
     int cd = 0;
     std::vector<double> dd;
-    LYAP_TRY(factor_iteration(c, Zd_.as<double>(), cap, rd, sd, false, cd, dd));
+    LYAP_TRY(factor_iteration(c, Zd_.as<double>(), cap, rd, rd, sd, false, cd, dd));  // U Q_t
     LYAP_HIP(hipStreamSynchronize(s));
     info->phase_ms[2] += ms_since(t0);
     info->newton_total += c.K;

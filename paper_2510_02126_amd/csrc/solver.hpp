@@ -31,8 +31,9 @@ class Solver {
  private:
   struct Ctx;
   int a_iteration(Ctx& c);
-  int factor_iteration(Ctx& c, const double* L0, long ld0, int m0, const std::vector<double>& d0,
-                       bool psd, int& cols, std::vector<double>& d);
+  int factor_iteration(Ctx& c, const double* L0, long ld0, int m0, int orth0,
+                       const std::vector<double>& d0, bool psd, int& cols,
+                       std::vector<double>& d);
   int rank_trunc(Ctx& c, double* Zb, long ldb, int& cols, std::vector<double>& d, double thr,
                  bool psd);
   int xnorm(Ctx& c, const double* Zb, long ldb, int cols, const std::vector<double>& d,
