@@ -232,55 +232,83 @@ __device__ void solve_pair(SolveLds<T>& L, int pp, int np, const T* __restrict__
       bi[h] = pc[2 * P[h]];
       bj[h] = pc[2 * P[h] + 1];
     }
-    // all four blocks of the current matrix and both rotations, loaded at once (thread t
-    // owns elements t + 256 q)
-    T xr[4][4], ra[4], rb[4];
+    if constexpr (sizeof(T) == 8) {
+      // FP64: wave w forms block (h1, h2) = (w / 2, w % 2) on the matrix cores,
+      // S_h1h2 = R_P[h1][:, half H[h1]]^T (X R_P[h2][:, half H[h2]]) with X the 32 x 32
+      // block of A; the operands come straight from memory and Y = X R stays in registers
+      // (the FP64 result layout, row 4 i + l / 16, is the next product's B-operand layout).
+      const int lane = t & 63, wave = t >> 6, lr = lane & 15, lk = lane >> 4;
+      const int h1 = wave >> 1, h2 = wave & 1;
+      const T* R1 = Rc + (long)P[h1] * SB * SB + HB * H[h1];
+      const T* R2 = Rc + (long)P[h2] * SB * SB + HB * H[h2];
+      typename Mf<T>::V4 y0 = {T(0), T(0), T(0), T(0)}, y1 = y0, sb = y0;
+      const long r0 = (long)gidx(lr, bi[h1], bj[h1]) * pp;       // X row lr
+      const long r1 = (long)gidx(HB + lr, bi[h1], bj[h1]) * pp;  // X row 16 + lr
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int e = t + NTJ * q, i = e / SB, k = e % SB;
-      ra[q] = Rc[(long)P[0] * SB * SB + e];
-      rb[q] = Rc[(long)P[1] * SB * SB + e];
+      for (int k0 = 0; k0 < SB; k0 += 4) {
+        const int col = gidx(k0 + lk, bi[h2], bj[h2]);
+        const T rk = R2[(k0 + lk) * SB + lr];
+        y0 = Mf<T>::mma(A[r0 + col], rk, y0);
+        y1 = Mf<T>::mma(A[r1 + col], rk, y1);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        sb = Mf<T>::mma(R1[(4 * i + lk) * SB + lr], y0[i], sb);
+        sb = Mf<T>::mma(R1[(HB + 4 * i + lk) * SB + lr], y1[i], sb);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) L.S[0][HB * h1 + 4 * i + lk][HB * h2 + lr] = sb[i];
+    } else {
+      // all four blocks of the current matrix and both rotations, loaded at once (thread t
+      // owns elements t + 256 q)
+      T xr[4][4], ra[4], rb[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int e = t + NTJ * q, i = e / SB, k = e % SB;
+        ra[q] = Rc[(long)P[0] * SB * SB + e];
+        rb[q] = Rc[(long)P[1] * SB * SB + e];
+#pragma unroll
+        for (int cmb = 0; cmb < 4; ++cmb) {
+          const int h1 = cmb >> 1, h2 = cmb & 1;
+          xr[cmb][q] = A[(long)gidx(i, bi[h1], bj[h1]) * pp + gidx(k, bi[h2], bj[h2])];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int e = t + NTJ * q, i = e / SB, k = e % SB;
+        RA[i][k] = ra[q];  // R_P[0]
+        RB[i][k] = rb[q];  // R_P[1]
+      }
 #pragma unroll
       for (int cmb = 0; cmb < 4; ++cmb) {
         const int h1 = cmb >> 1, h2 = cmb & 1;
-        xr[cmb][q] = A[(long)gidx(i, bi[h1], bj[h1]) * pp + gidx(k, bi[h2], bj[h2])];
-      }
-    }
+        __syncthreads();
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int e = t + NTJ * q, i = e / SB, k = e % SB;
-      RA[i][k] = ra[q];  // R_P[0]
-      RB[i][k] = rb[q];  // R_P[1]
-    }
-#pragma unroll
-    for (int cmb = 0; cmb < 4; ++cmb) {
-      const int h1 = cmb >> 1, h2 = cmb & 1;
-      __syncthreads();
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int e = t + NTJ * q;
-        X[e / SB][e % SB] = xr[cmb][q];
+        for (int q = 0; q < 4; ++q) {
+          const int e = t + NTJ * q;
+          X[e / SB][e % SB] = xr[cmb][q];
+        }
+        __syncthreads();
+        // Y = X R_P[h2][:, half H[h2]]  (32 x 16): thread (i = t / 8, columns 2 (t % 8) + {0, 1})
+        T (&R2)[SB][LDS_PAD] = h2 == 0 ? RA : RB;
+        T (&R1)[SB][LDS_PAD] = h1 == 0 ? RA : RB;
+        const int yi = t / 8, yc = 2 * (t % 8);
+        T y0 = T(0), y1 = T(0);
+        for (int k = 0; k < SB; ++k) {
+          const T x = X[yi][k];
+          y0 += x * R2[k][HB * H[h2] + yc];
+          y1 += x * R2[k][HB * H[h2] + yc + 1];
+        }
+        __syncthreads();
+        X[yi][yc] = y0;  // X now holds Y in its first 16 columns
+        X[yi][yc + 1] = y1;
+        __syncthreads();
+        // S block = R_P[h1][:, half H[h1]]^T Y  (16 x 16): thread (i = t / 16, c = t % 16)
+        const int si = t / HB, sc = t % HB;
+        T sum = T(0);
+        for (int k = 0; k < SB; ++k) sum += R1[k][HB * H[h1] + si] * X[k][sc];
+        L.S[0][HB * h1 + si][HB * h2 + sc] = sum;
       }
-      __syncthreads();
-      // Y = X R_P[h2][:, half H[h2]]  (32 x 16): thread (i = t / 8, columns 2 (t % 8) + {0, 1})
-      T (&R2)[SB][LDS_PAD] = h2 == 0 ? RA : RB;
-      T (&R1)[SB][LDS_PAD] = h1 == 0 ? RA : RB;
-      const int yi = t / 8, yc = 2 * (t % 8);
-      T y0 = T(0), y1 = T(0);
-      for (int k = 0; k < SB; ++k) {
-        const T x = X[yi][k];
-        y0 += x * R2[k][HB * H[h2] + yc];
-        y1 += x * R2[k][HB * H[h2] + yc + 1];
-      }
-      __syncthreads();
-      X[yi][yc] = y0;  // X now holds Y in its first 16 columns
-      X[yi][yc + 1] = y1;
-      __syncthreads();
-      // S block = R_P[h1][:, half H[h1]]^T Y  (16 x 16): thread (i = t / 16, c = t % 16)
-      const int si = t / HB, sc = t % HB;
-      T sum = T(0);
-      for (int k = 0; k < SB; ++k) sum += R1[k][HB * H[h1] + si] * X[k][sc];
-      L.S[0][HB * h1 + si][HB * h2 + sc] = sum;
     }
     __syncthreads();  // RB (in R[0]) no longer read
   }
@@ -309,8 +337,9 @@ __global__ __launch_bounds__(NTJ) void jac_solve0(int pp, int np, const T* __res
 // One round.  Blocks [0, np): solves of the next round's pairs pn (rotations to Rn; a full
 // subproblem sweep when the next round is the first of a sweep, a cross sweep otherwise).
 // The other blocks are update workers that take items w, w + nw, w + 2 nw, ... of
-//   items [0, np*np):            Aout block (pair P rows, pair Q cols) = R_P^T Ain_PQ R_Q,
-//   items [np*np, np*np + np*nt): V tile (rows 32 t.., cols of pair Q) <- V_tile R_Q (in place),
+//   items [0, na), na = np (np + 1) / 2: pair blocks P <= Q, Aout block (pair P rows, pair Q
+//                 cols) = R_P^T Ain_PQ R_Q and, A being symmetric, block (Q, P) its transpose,
+//   items [na, na + np*nt): V tile (rows 32 t.., cols of pair Q) <- V_tile R_Q (in place),
 // loading the operands of their next item into registers while they compute the current one.
 // The block products run on the FP64 matrix cores: wave w owns the 16 x 16 tile (w/2, w%2).
 struct Item {
@@ -318,15 +347,24 @@ struct Item {
   int P, Q, tile;
 };
 
+// A items are the pair blocks with P <= Q in row order (row P starts at P np - P (P - 1) / 2).
+__device__ inline int upper_start(int P, int np) { return P * np - P * (P - 1) / 2; }
+
 __device__ inline Item decode_item(int item, int np) {
   Item it;
-  it.isA = item < np * np;
+  const int na = np * (np + 1) / 2;
+  it.isA = item < na;
   if (it.isA) {
-    it.P = item / np;
-    it.Q = item % np;
+    const double b = 2.0 * np + 1.0;
+    int P = (int)((b - sqrt(b * b - 8.0 * item)) * 0.5);
+    P = max(0, min(np - 1, P));
+    while (P + 1 < np && upper_start(P + 1, np) <= item) ++P;
+    while (P > 0 && upper_start(P, np) > item) --P;
+    it.P = P;
+    it.Q = P + (item - upper_start(P, np));
     it.tile = 0;
   } else {
-    const int b2 = item - np * np;
+    const int b2 = item - na;
     it.Q = b2 % np;
     it.tile = b2 / np;
     it.P = 0;
@@ -373,7 +411,7 @@ __global__ __launch_bounds__(NTJ) void jac_round(int pp, int np, const T* __rest
     return;
   }
   const int nw = gridDim.x - np;
-  const int nitems = np * np + np * (pp / SB);
+  const int nitems = np * (np + 1) / 2 + np * (pp / SB);
   int item = blk - np;
   if (item >= nitems) return;
   T (&M)[SB][LDS_PAD] = L.S[1];
@@ -427,6 +465,17 @@ __global__ __launch_bounds__(NTJ) void jac_round(int pp, int np, const T* __rest
       for (int i = 0; i < 4; ++i) {
         const int r = 16 * ti + M4::row(i, lk), c = 16 * tj + lr;
         Aout[(long)gidx(r, pI, pJ) * pp + gidx(c, qI, qJ)] = out[i];
+      }
+      if (cur.P != cur.Q) {
+        // block (Q, P) is the transpose: staged through M (free since the first product)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) M[16 * ti + M4::row(i, lk)][16 * tj + lr] = out[i];
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int e = t + NTJ * q, i = e / SB, j = e % SB;
+          Aout[(long)gidx(i, qI, qJ) * pp + gidx(j, pI, pJ)] = M[j][i];
+        }
       }
     }
     item = next;
@@ -583,7 +632,7 @@ int syev_t(hipStream_t s, int p, const double* H, long ldh, double* w, double* V
   int cur = 0, rc = 0;  // A in Aw[cur], rotations of the next round in Rb[rc]
   bool solved = false;
   // update workers: about as many as fit on the chip next to the solves (4 per CU)
-  const int nitems = np * np + np * (pp / SB);
+  const int nitems = np * (np + 1) / 2 + np * (pp / SB);
   const int nw = std::min(nitems, std::max(256, 4 * 256 - np));
   while (sweep < max_sweeps && np > 0) {
     if (host[0] <= tol_rel * tol_rel * total) break;
@@ -606,9 +655,12 @@ int syev_t(hipStream_t s, int p, const double* H, long ldh, double* w, double* V
       rc ^= 1;
     }
     if (kt) {
-      // block update traffic: A read and written, V read and written
+      // block update traffic per round: the pair blocks P <= Q of A read, all of A written,
+      // V read and written
       LYAP_TRY(kt->mark(s, &e1));
-      kt->add(e0, e1, 1, (double)rounds * 4.0 * sizeof(T) * pp * pp, rounds);
+      const double per_round =
+          ((double)np * (np + 1) / 2 * SB * SB + 3.0 * pp * pp) * sizeof(T);
+      kt->add(e0, e1, 1, rounds * per_round, rounds);
     }
     hipLaunchKernelGGL((jac_norms<T>), dim3(nparts), dim3(256), 0, s, pp, Aw[cur], part);
     hipLaunchKernelGGL(jac_norms_finish, dim3(1), dim3(1), 0, s, nparts, part, scal, thr_rel, thr,
