@@ -36,13 +36,23 @@ constexpr int SB = 2 * HB;    // subproblem size
 constexpr int LDS_PAD = SB + 1;
 
 // Reciprocal and reciprocal square root from the hardware estimates refined by Newton steps
-// (each step roughly doubles the number of correct bits of the estimate).
+// (each step roughly doubles the number of correct bits of the estimate; the FP64 estimates
+// are good to about 2^-24, one step to about 2e-15, two to full precision).
 __device__ inline double recip(double x) {
   double r = __builtin_amdgcn_rcp(x);
   double e = fma(-x, r, 1.0);
   r = fma(r, e, r);
   e = fma(-x, r, 1.0);
   return fma(r, e, r);
+}
+__device__ inline double recip1(double x) {  // one step
+  const double r = __builtin_amdgcn_rcp(x);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+__device__ inline double rsqrt1(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x * y;
+  return fma(y, fma(-h, y, 0.5), y);
 }
 __device__ inline double rsqrt_nr(double x) {
   double y = __builtin_amdgcn_rsq(x);
@@ -61,10 +71,14 @@ __device__ inline float rsqrt_nr(float x) {
   const float h = 0.5f * x * y;
   return fmaf(y, fmaf(-h, y, 0.5f), y);
 }
+__device__ inline float recip1(float x) { return recip(x); }
+__device__ inline float rsqrt1(float x) { return rsqrt_nr(x); }
 
 // Rotation zeroing a_pq of the 2 x 2 block [[app, apq], [apq, aqq]], or none (c = 1, s = 0)
 // when |a_pq| <= thr or |a_pq| <= eps sqrt(|a_pp a_qq|); returns whether it is applied.
 // t = tan(angle) is the smaller root of t^2 + 2 theta t - 1 = 0, c = 1 / sqrt(1 + t^2).
+// An error in t only leaves a slightly larger remainder of a_pq, so t takes one refinement
+// step; c and s = t c must satisfy c^2 + s^2 = 1 to working precision, so c takes two.
 template <class T>
 __device__ inline bool rot_params(T app, T aqq, T apq, T thr, T eps, T& c, T& s) {
   const T a = fabs(apq);
@@ -73,16 +87,16 @@ __device__ inline bool rot_params(T app, T aqq, T apq, T thr, T eps, T& c, T& s)
     s = T(0);
     return false;
   }
-  const T theta = (aqq - app) * recip(T(2) * apq);
+  const T theta = (aqq - app) * recip1(T(2) * apq);
   const T at = fabs(theta);
   const T big = sizeof(T) == 8 ? T(1e150) : T(1e18);  // theta^2 would overflow
   T t;
   if (at > big) {
-    t = T(0.5) * recip(theta);
+    t = T(0.5) * recip1(theta);
   } else {
     const T q = T(1) + theta * theta;
-    const T h = q * rsqrt_nr(q);  // sqrt(1 + theta^2)
-    t = copysign(recip(at + h), theta);
+    const T h = q * rsqrt1(q);  // sqrt(1 + theta^2)
+    t = copysign(recip1(at + h), theta);
   }
   c = rsqrt_nr(T(1) + t * t);
   s = t * c;
@@ -154,29 +168,25 @@ __device__ inline void step_pair(bool full, int k, int r, int& p, int& q) {
 
 // One sweep on L.S[0] (R starts as I in L.R[0]); returns the buffer holding the result (the
 // parity of the step count).  Thread t owns the 2 x 2 blocks (pair a = t / 16 rows, pair
-// b = t % 16 columns).  Lanes 0..15 of each wave compute the 16 rotations of the step and the
-// other lanes fetch theirs by lane permutation; every thread reads the current buffer and
-// writes its block of the other one, so a step needs a single barrier.
+// b = t % 16 columns) and computes the two rotations it applies itself (the same arithmetic
+// on the same entries as any other thread that needs them, so no lane exchange); every
+// thread reads the current buffer and writes its block of the other one, so a step needs a
+// single barrier.
 template <class T>
 __device__ int subproblem_sweep(SolveLds<T>& L, T thr, T eps, bool full) {
-  const int t = threadIdx.x, lane = t & 63;
+  const int t = threadIdx.x;
   const int a = t / (SB / 2), b = t % (SB / 2);
   const int steps = full ? SB - 1 : HB;
   for (int r = 0; r < steps; ++r) {
     const int cur = r & 1, nxt = cur ^ 1;
-    T c = T(1), sn = T(0);
-    if (lane < SB / 2) {
-      int p, q;
-      step_pair(full, lane, r, p, q);
-      if (rot_params(L.S[cur][p][p], L.S[cur][q][q], L.S[cur][p][q], thr, eps, c, sn) &&
-          t == lane)
-        L.any = 1;
-    }
-    const T ca = __shfl(c, a), sa = __shfl(sn, a);
-    const T cb = __shfl(c, b), sb = __shfl(sn, b);
     int p0, q0, p1, q1;
     step_pair(full, a, r, p0, q0);
     step_pair(full, b, r, p1, q1);
+    T ca, sa, cb, sb;
+    if (rot_params(L.S[cur][p0][p0], L.S[cur][q0][q0], L.S[cur][p0][q0], thr, eps, ca, sa) &&
+        b == 0)
+      L.any = 1;
+    rot_params(L.S[cur][p1][p1], L.S[cur][q1][q1], L.S[cur][p1][q1], thr, eps, cb, sb);
     const T m00 = L.S[cur][p0][p1], m01 = L.S[cur][p0][q1];
     const T m10 = L.S[cur][q0][p1], m11 = L.S[cur][q0][q1];
     const T r00 = L.R[cur][p0][p1], r01 = L.R[cur][p0][q1];
