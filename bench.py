@@ -204,7 +204,7 @@ def main():
     fams = {
         0: ("inversion (Gauss-Jordan leaves + MFMA block updates, 2n^3 flops)", "mfma",
             "TFLOP/s", 1e12, PEAK_TFLOPS["fp32" if args.us == "fp32" else args.us]),
-        1: ("jac_round (Jacobi round: block rotation update of A and V, ~28 pp^2 bytes)",
+        1: ("jac_round (Jacobi round: block rotation update of A and V, ~24 pp^2 bytes)",
             "hbm", "GB/s", 1e9, PEAK_HBM_GBS),
         2: ("thin QR (Householder TSQR panels + compact-WY MFMA updates)", "mfma", "TFLOP/s",
             1e12, PEAK_TFLOPS["fp64"]),

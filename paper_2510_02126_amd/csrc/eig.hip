@@ -131,6 +131,12 @@ template <> struct Mf<float> {
 
 __device__ inline int gidx(int i, int bi, int bj) { return i < HB ? bi * HB + i : bj * HB + (i - HB); }
 
+// A is kept as its upper triangle of 16 x 16 blocks (both triangles inside diagonal blocks):
+// entry (r, c) lives at (r, c) when block(r) <= block(c), otherwise at (c, r).
+__device__ inline long sidx(int r, int c, int pp) {
+  return (r / HB <= c / HB) ? (long)r * pp + c : (long)c * pp + r;
+}
+
 // LDS of a round workgroup (four 32 x 32 buffers, so four workgroups fit on a CU).  A solve
 // uses S[0..1] and R[0..1] for the sweep and, while it forms its subproblem, S[1] / R[1] /
 // R[0] as staging (X / RA / RB); an update workgroup uses all four for its operands.
@@ -224,7 +230,7 @@ __device__ void solve_pair(SolveLds<T>& L, int pp, int np, const T* __restrict__
   if (!Rc) {
     for (int e = t; e < SB * SB; e += NTJ) {
       const int i = e / SB, k = e % SB;
-      L.S[0][i][k] = A[(long)gidx(i, nI, nJ) * pp + gidx(k, nI, nJ)];
+      L.S[0][i][k] = A[sidx(gidx(i, nI, nJ), gidx(k, nI, nJ), pp)];
     }
   } else {
     // block b of the new pair sits in current pair P(b) at half h(b): its slot in round rc
@@ -252,14 +258,14 @@ __device__ void solve_pair(SolveLds<T>& L, int pp, int np, const T* __restrict__
       const T* R1 = Rc + (long)P[h1] * SB * SB + HB * H[h1];
       const T* R2 = Rc + (long)P[h2] * SB * SB + HB * H[h2];
       typename Mf<T>::V4 y0 = {T(0), T(0), T(0), T(0)}, y1 = y0, sb = y0;
-      const long r0 = (long)gidx(lr, bi[h1], bj[h1]) * pp;       // X row lr
-      const long r1 = (long)gidx(HB + lr, bi[h1], bj[h1]) * pp;  // X row 16 + lr
+      const int r0 = gidx(lr, bi[h1], bj[h1]);       // X row lr
+      const int r1 = gidx(HB + lr, bi[h1], bj[h1]);  // X row 16 + lr
 #pragma unroll
       for (int k0 = 0; k0 < SB; k0 += 4) {
         const int col = gidx(k0 + lk, bi[h2], bj[h2]);
         const T rk = R2[(k0 + lk) * SB + lr];
-        y0 = Mf<T>::mma(A[r0 + col], rk, y0);
-        y1 = Mf<T>::mma(A[r1 + col], rk, y1);
+        y0 = Mf<T>::mma(A[sidx(r0, col, pp)], rk, y0);
+        y1 = Mf<T>::mma(A[sidx(r1, col, pp)], rk, y1);
       }
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
@@ -280,7 +286,7 @@ __device__ void solve_pair(SolveLds<T>& L, int pp, int np, const T* __restrict__
 #pragma unroll
         for (int cmb = 0; cmb < 4; ++cmb) {
           const int h1 = cmb >> 1, h2 = cmb & 1;
-          xr[cmb][q] = A[(long)gidx(i, bi[h1], bj[h1]) * pp + gidx(k, bi[h2], bj[h2])];
+          xr[cmb][q] = A[sidx(gidx(i, bi[h1], bj[h1]), gidx(k, bi[h2], bj[h2]), pp)];
         }
       }
 #pragma unroll
@@ -348,7 +354,7 @@ __global__ __launch_bounds__(NTJ) void jac_solve0(int pp, int np, const T* __res
 // subproblem sweep when the next round is the first of a sweep, a cross sweep otherwise).
 // The other blocks are update workers that take items w, w + nw, w + 2 nw, ... of
 //   items [0, na), na = np (np + 1) / 2: pair blocks P <= Q, Aout block (pair P rows, pair Q
-//                 cols) = R_P^T Ain_PQ R_Q and, A being symmetric, block (Q, P) its transpose,
+//                 cols) = R_P^T Ain_PQ R_Q, stored into the upper block triangle,
 //   items [na, na + np*nt): V tile (rows 32 t.., cols of pair Q) <- V_tile R_Q (in place),
 // loading the operands of their next item into registers while they compute the current one.
 // The block products run on the FP64 matrix cores: wave w owns the 16 x 16 tile (w/2, w%2).
@@ -396,7 +402,7 @@ __device__ inline void load_item(const Item& it, int pp, const int* __restrict__
     rq[q] = Rc[(long)it.Q * SB * SB + e];
     if (it.isA) {
       rp[q] = Rc[(long)it.P * SB * SB + e];
-      m[q] = Ain[(long)gidx(i, pI, pJ) * pp + gidx(j, qI, qJ)];
+      m[q] = Ain[sidx(gidx(i, pI, pJ), gidx(j, qI, qJ), pp)];
     } else {
       m[q] = V[(long)(it.tile * SB + i) * pp + gidx(j, qI, qJ)];
     }
@@ -471,20 +477,24 @@ __global__ __launch_bounds__(NTJ) void jac_round(int pp, int np, const T* __rest
 #pragma unroll
       for (int k0 = 0; k0 < SB; k0 += 4)
         out = M4::mma(RP[k0 + lk][16 * ti + lr], T1[k0 + lk][16 * tj + lr], out);
+      // staged through M (free since the first product) so that each stored 16 x 16 block
+      // is written row by row: block (h1, h2) of the result goes to (x, y) = (its row block,
+      // its column block) when x <= y and transposed to (y, x) otherwise; for P == Q the
+      // block (1, 0) is the transpose of (0, 1) and is not written
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int r = 16 * ti + M4::row(i, lk), c = 16 * tj + lr;
-        Aout[(long)gidx(r, pI, pJ) * pp + gidx(c, qI, qJ)] = out[i];
-      }
-      if (cur.P != cur.Q) {
-        // block (Q, P) is the transpose: staged through M (free since the first product)
+      for (int i = 0; i < 4; ++i) M[16 * ti + M4::row(i, lk)][16 * tj + lr] = out[i];
+      __syncthreads();
 #pragma unroll
-        for (int i = 0; i < 4; ++i) M[16 * ti + M4::row(i, lk)][16 * tj + lr] = out[i];
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int e = t + NTJ * q, i = e / SB, j = e % SB;
-          Aout[(long)gidx(i, qI, qJ) * pp + gidx(j, pI, pJ)] = M[j][i];
+      for (int h = 0; h < 4; ++h) {
+        const int h1 = h >> 1, h2 = h & 1;
+        if (cur.P == cur.Q && h1 == 1 && h2 == 0) continue;
+        const int x = h1 ? pJ : pI, y = h2 ? qJ : qI;
+        if (x <= y) {
+          const int a = t / HB, b = t % HB;
+          Aout[(long)(HB * x + a) * pp + HB * y + b] = M[HB * h1 + a][HB * h2 + b];
+        } else {
+          const int a = t % HB, b = t / HB;
+          Aout[(long)(HB * y + b) * pp + HB * x + a] = M[HB * h1 + a][HB * h2 + b];
         }
       }
     }
@@ -506,14 +516,16 @@ __global__ void jac_load(int p, int pp, const double* __restrict__ H, long ldh,
 }
 
 // partial sums: [0] off-diagonal squares, [1] all squares (rows strided over blocks)
+// (entries of the stored upper block triangle; an off-diagonal block counts twice)
 template <class T>
 __global__ void jac_norms(int pp, const T* __restrict__ A, double* __restrict__ part) {
   __shared__ double r0[256], r1[256];
   double off = 0.0, all = 0.0;
   for (int i = blockIdx.x; i < pp; i += gridDim.x)
     for (int j = threadIdx.x; j < pp; j += 256) {
+      if (i / HB > j / HB) continue;
       const double v = (double)A[(long)i * pp + j];
-      const double v2 = v * v;
+      const double v2 = (i / HB == j / HB) ? v * v : 2.0 * v * v;
       all += v2;
       if (i != j) off += v2;
     }
@@ -665,11 +677,10 @@ int syev_t(hipStream_t s, int p, const double* H, long ldh, double* w, double* V
       rc ^= 1;
     }
     if (kt) {
-      // block update traffic per round: the pair blocks P <= Q of A read, all of A written,
+      // block update traffic per round: the stored pair blocks P <= Q of A read and written,
       // V read and written
       LYAP_TRY(kt->mark(s, &e1));
-      const double per_round =
-          ((double)np * (np + 1) / 2 * SB * SB + 3.0 * pp * pp) * sizeof(T);
+      const double per_round = ((double)np * (np + 1) * SB * SB + 2.0 * pp * pp) * sizeof(T);
       kt->add(e0, e1, 1, rounds * per_round, rounds);
     }
     hipLaunchKernelGGL((jac_norms<T>), dim3(nparts), dim3(256), 0, s, pp, Aw[cur], part);
