@@ -547,30 +547,46 @@ __global__ void jac_norms(int pp, const T* __restrict__ A, double* __restrict__ 
 
 // out[0] = ||offdiag||_F^2, out[1] = ||A||_F^2, out[2] = number of subproblems that applied a
 // rotation since the last call (the counter is reset); *thr_dev = thr_rel ||A||_F.
+// One workgroup of 256 threads, fixed summation order.
 __global__ void jac_norms_finish(int nparts, const double* __restrict__ part,
                                  double* __restrict__ out, double thr_rel,
                                  double* __restrict__ thr_dev, int* __restrict__ applied) {
+  __shared__ double r0[256], r1[256];
   double off = 0.0, all = 0.0;
-  for (int i = 0; i < nparts; ++i) {
+  for (int i = threadIdx.x; i < nparts; i += 256) {
     off += part[2 * i];
     all += part[2 * i + 1];
   }
-  out[0] = off;
-  out[1] = all;
-  out[2] = (double)*applied;
-  *applied = 0;
-  *thr_dev = thr_rel * sqrt(all);
+  r0[threadIdx.x] = off;
+  r1[threadIdx.x] = all;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) {
+      r0[threadIdx.x] += r0[threadIdx.x + h];
+      r1[threadIdx.x] += r1[threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = r0[0];
+    out[1] = r1[0];
+    out[2] = (double)*applied;
+    *applied = 0;
+    *thr_dev = thr_rel * sqrt(r1[0]);
+  }
 }
 
-// Sort the first p diagonal entries by descending |value| (ties by index): one workgroup, rank
-// computed by counting.
+// Sort the first p diagonal entries by descending |value| (ties by index): the rank of entry i
+// is computed by counting; workgroup x ranks entries [256 x, 256 x + 256).
 template <class T>
-__global__ __launch_bounds__(1024) void jac_sort(int p, int pp, const T* __restrict__ A,
-                                                 int* __restrict__ perm, double* __restrict__ w) {
+__global__ __launch_bounds__(256) void jac_sort(int p, int pp, const T* __restrict__ A,
+                                                int* __restrict__ perm, double* __restrict__ w) {
   __shared__ double dg[4096];
-  for (int i = threadIdx.x; i < p; i += 1024) dg[i] = (double)A[(long)i * pp + i];
+  for (int i = threadIdx.x; i < p; i += 256) dg[i] = (double)A[(long)i * pp + i];
   __syncthreads();
-  for (int i = threadIdx.x; i < p; i += 1024) {
+  {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= p) return;
     double ai = dg[i], ki = fabs(ai);
     int rank = 0;
     for (int j = 0; j < p; ++j) {
@@ -615,7 +631,7 @@ int syev_t(hipStream_t s, int p, const double* H, long ldh, double* w, double* V
   T* Vw = ws.take<T>((size_t)pp * pp);
   T* Rb[2] = {ws.take<T>((size_t)np * SB * SB), ws.take<T>((size_t)np * SB * SB)};
   int* pairs = ws.take<int>((size_t)rounds * np * 2 + 2);
-  double* part = ws.take<double>(2 * 256);
+  double* part = ws.take<double>(2 * 256);  // nparts pairs
   double* scal = ws.take<double>(4);
   int* perm = ws.take<int>(pp);
   int* applied = ws.take<int>(1);
@@ -638,11 +654,11 @@ int syev_t(hipStream_t s, int p, const double* H, long ldh, double* w, double* V
                           s));
   hipLaunchKernelGGL((jac_load<T>), dim3((unsigned)ceil_div(pp * pp, 256)), dim3(256), 0, s, p, pp, H,
                      ldh, Aw[0], Vw);
-  const int nparts = 64;
+  const int nparts = 256;
   double* thr = scal + 3;
   hipLaunchKernelGGL((jac_norms<T>), dim3(nparts), dim3(256), 0, s, pp, Aw[0], part);
   const double thr_rel = 0.25 * tol_rel / pp;
-  hipLaunchKernelGGL(jac_norms_finish, dim3(1), dim3(1), 0, s, nparts, part, scal, thr_rel, thr,
+  hipLaunchKernelGGL(jac_norms_finish, dim3(1), dim3(256), 0, s, nparts, part, scal, thr_rel, thr,
                      applied);
   LYAP_HIP(hipGetLastError());
   double host[3] = {0, 0, 0};
@@ -684,7 +700,7 @@ int syev_t(hipStream_t s, int p, const double* H, long ldh, double* w, double* V
       kt->add(e0, e1, 1, rounds * per_round, rounds);
     }
     hipLaunchKernelGGL((jac_norms<T>), dim3(nparts), dim3(256), 0, s, pp, Aw[cur], part);
-    hipLaunchKernelGGL(jac_norms_finish, dim3(1), dim3(1), 0, s, nparts, part, scal, thr_rel, thr,
+    hipLaunchKernelGGL(jac_norms_finish, dim3(1), dim3(256), 0, s, nparts, part, scal, thr_rel, thr,
                        applied);
     LYAP_HIP(hipGetLastError());
     LYAP_HIP(hipMemcpyAsync(host, scal, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -692,7 +708,8 @@ int syev_t(hipStream_t s, int p, const double* H, long ldh, double* w, double* V
     ++sweep;
   }
   if (sweeps_out) *sweeps_out = sweep;
-  hipLaunchKernelGGL((jac_sort<T>), dim3(1), dim3(1024), 0, s, p, pp, Aw[cur], perm, w);
+  hipLaunchKernelGGL((jac_sort<T>), dim3((unsigned)ceil_div(p, 256)), dim3(256), 0, s, p, pp,
+                     Aw[cur], perm, w);
   hipLaunchKernelGGL((jac_gather<T>), dim3((unsigned)ceil_div(p * p, 256)), dim3(256), 0, s, p, pp, Vw,
                      perm, V, ldv);
   LYAP_HIP(hipGetLastError());

@@ -40,8 +40,9 @@ constexpr int MAXCH = 16;  // chunks per panel (n <= 4096)
 constexpr int CPT = 8;         // panel columns per thread
 constexpr int NCG = PB / CPT;  // column groups: thread t owns column group t % NCG
 
+template <int NT>
 struct PanelLds {
-  double part[NTH / 16][PB];  // partial sums per 16-lane row of each wave
+  double part[NT / 16][PB];  // partial sums per 16-lane row of each wave
   double prow[PB];            // row k
   double dvec[PB];            // tau (A[k][j] + v_k^T A[k+1:, j]) for j > k, else 0
   double sc[2];               // beta, scale
@@ -60,7 +61,7 @@ __device__ inline double dpp_d(double x) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
-// Householder QR of an r x w block (r <= 64 RPR, w <= PB).  Thread t = NCG g + cg holds rows
+// Householder QR of an r x w block (r <= NT RPR / 4, w <= PB).  Thread t = NCG g + cg holds rows
 // g RPR + i (i < RPR) at columns CPT cg + jj (jj < CPT) in a[i][jj].  On return the rows hold
 // R on and above the diagonal and the reflectors v below it (unit diagonal implied); L.Tw holds
 // Tw (zero outside the kmax x kmax upper triangle).
@@ -70,12 +71,12 @@ __device__ inline double dpp_d(double x) {
 // and across rows and waves in LDS by 32 threads, which then form the reflector (s_k is the
 // squared norm below the diagonal), the update coefficients of the trailing columns and
 // z = V^T v_k for the Tw recurrence.
-template <int RPR>
-__device__ void panel_factor(double (&a)[RPR][CPT], int r, int w, PanelLds& L) {
+template <int RPR, int NT>
+__device__ void panel_factor(double (&a)[RPR][CPT], int r, int w, PanelLds<NT>& L) {
   const int t = threadIdx.x, cg = t % NCG, g = t / NCG;
   const int lane = t & 63, wave = t >> 6;
   const int kmax = min(r, w);
-  for (int e = t; e < PB * PB; e += NTH) L.Tw[e / PB][e % PB] = 0.0;
+  for (int e = t; e < PB * PB; e += NT) L.Tw[e / PB][e % PB] = 0.0;
   // fully unrolled, so the pivot column's group and slot are constants of each step
 #pragma unroll
   for (int k = 0; k < PB; ++k) {
@@ -122,7 +123,7 @@ __device__ void panel_factor(double (&a)[RPR][CPT], int r, int w, PanelLds& L) {
     if (t < PB) {
       double sc = 0.0;
 #pragma unroll
-      for (int q = 0; q < NTH / 16; ++q) sc += L.part[q][t];
+      for (int q = 0; q < NT / 16; ++q) sc += L.part[q][t];
       const double sigma = __shfl(sc, k, PB);
       const double alpha = L.prow[k];
       double beta, tau, scale;
@@ -261,12 +262,12 @@ __global__ __launch_bounds__(NTH) void tsqr_local(int nr, int w, const double* _
                                                   long ldp, double* __restrict__ Vg,
                                                   double* __restrict__ Twg,
                                                   double* __restrict__ Rstack) {
-  __shared__ PanelLds L;
+  __shared__ PanelLds<NTH> L;
   constexpr int RPR = CH / (NTH / NCG);
   const int b = blockIdx.x, r0 = b * CH, rows = min(CH, nr - r0), t = threadIdx.x;
   double a[RPR][CPT];
   panel_load<RPR>(a, P + (long)r0 * ldp, ldp, rows, w);
-  panel_factor<RPR>(a, rows, w, L);
+  panel_factor<RPR, NTH>(a, rows, w, L);
   const int kmax = min(rows, w);
   panel_store_r<RPR>(a, Rstack + (long)b * PB * PB, PB, kmax, w, true);
   double* Tw = Twg + (long)b * PB * PB;
@@ -274,21 +275,23 @@ __global__ __launch_bounds__(NTH) void tsqr_local(int nr, int w, const double* _
   panel_store_v<RPR>(a, Vg + (long)r0 * PB, rows, kmax);
 }
 
-// Level 2: QR of the stacked R factors (nch*PB x w) by one workgroup; R (w x w) goes to T,
-// the reflectors to V2 (nch*PB x PB) and the WY factor to Tw2.
-__global__ __launch_bounds__(NTH) void tsqr_stack(int nch, int w, const double* __restrict__ Rstack,
+// Level 2: QR of the stacked R factors (nch*PB x w) by one workgroup of NTS threads (4 rows
+// per thread, as at level 1); R (w x w) goes to T, the reflectors to V2 (nch*PB x PB) and the
+// WY factor to Tw2.
+constexpr int NTS = 512;
+__global__ __launch_bounds__(NTS) void tsqr_stack(int nch, int w, const double* __restrict__ Rstack,
                                                   double* __restrict__ T, long ldt,
                                                   double* __restrict__ V2,
                                                   double* __restrict__ Tw2) {
-  __shared__ PanelLds L;
-  constexpr int RPR = MAXCH * PB / (NTH / NCG);
+  __shared__ PanelLds<NTS> L;
+  constexpr int RPR = MAXCH * PB / (NTS / NCG);
   const int r = nch * PB, t = threadIdx.x;
   double a[RPR][CPT];
   panel_load<RPR>(a, Rstack, PB, r, w);
-  panel_factor<RPR>(a, r, w, L);
+  panel_factor<RPR, NTS>(a, r, w, L);
   const int kmax = min(r, w);
   panel_store_r<RPR>(a, T, ldt, kmax, w, false);
-  for (int e = t; e < PB * PB; e += NTH) Tw2[e] = L.Tw[e / PB][e % PB];
+  for (int e = t; e < PB * PB; e += NTS) Tw2[e] = L.Tw[e / PB][e % PB];
   panel_store_v<RPR>(a, V2, r, kmax);
 }
 
@@ -462,7 +465,7 @@ int qr(hipStream_t s, int n, int p, const double* F, long ldf, double* U, long l
     double* P = W + (long)c * p + c;  // rows [c, n), columns [c, c+w)
     hipLaunchKernelGGL(tsqr_local, dim3(nch), dim3(NTH), 0, s, nr, w, P, (long)p, pans[j].Vg,
                        pans[j].Twg, Rstack);
-    hipLaunchKernelGGL(tsqr_stack, dim3(1), dim3(NTH), 0, s, nch, w, Rstack,
+    hipLaunchKernelGGL(tsqr_stack, dim3(1), dim3(NTS), 0, s, nch, w, Rstack,
                        T + (long)c * ldt + c, ldt, pans[j].V2, pans[j].Tw2);
     const int rest = p - c - w;
     if (rest > 0) {
