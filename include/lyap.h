@@ -68,6 +68,15 @@ typedef struct {
   double theta;      /* stagnation ratio of eq (4.2); 0.9                                 */
   int refine;        /* 1: iterative refinement (Alg 2.2); 0: one solve + residual check  */
   int psd;           /* -1 auto (S == NULL or S >= 0), 0 off, 1 on: PSD projection        */
+  int form;          /* 0: LDL^T type (Alg 2.2, default).  1: Cholesky type (Alg 2.1,
+                        Fragments 2.1 / 2.2), only for W = L L^T (S must be NULL): the
+                        residual is split into R = L+ L+^T - L- L-^T, the two correction
+                        equations are solved separately (sharing the inverse sequence) and
+                        the update keeps [Z, Z+, Z-] with signature (+, +, -) projected onto
+                        the PSD cone; Z is returned as the Cholesky-type factor
+                        (X ~ Z Z^T) and D is filled with ones.  The in-solver
+                        truncation keeps singular values above sqrt(u_s) sigma_1 of the
+                        factor (SVD reading of RankTruncChol).                              */
 } lyap_options;
 
 /* Per-solve diagnostics (Table 4.1 columns plus timings). */

@@ -151,7 +151,8 @@ def _solve(fn_name, A, L, S, precisions, tol, refine, z_cap, raise_on_error, opt
 def solve(A, L, S=None, precisions=("fp16", "fp64", "fp64", "fp64"), tol=1e-13, refine=True,
           z_cap=None, raise_on_error=True, **opts):
     """Alg 2.2 (LDL^T-type mixed-precision IR) on the GPU for A X + X A^T + L S L^T = 0.
-    Returns (Z, D, info) with X ~ Z diag(D) Z^T."""
+    Returns (Z, D, info) with X ~ Z diag(D) Z^T.  ``form=1`` (with S = None) runs the
+    Cholesky type, Alg 2.1, and returns the Cholesky-type factor (X ~ Z Z^T, D = 1)."""
     return _solve("lyap_solve", A, L, S, precisions, tol, refine, z_cap, raise_on_error, opts)
 
 

@@ -39,7 +39,7 @@ class Options(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("i_max", ctypes.c_int), ("k_max", ctypes.c_int),
                 ("rho", ctypes.c_double), ("eta_r", ctypes.c_double), ("eta_s", ctypes.c_double),
                 ("delta_off", ctypes.c_double), ("theta", ctypes.c_double),
-                ("refine", ctypes.c_int), ("psd", ctypes.c_int)]
+                ("refine", ctypes.c_int), ("psd", ctypes.c_int), ("form", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):

@@ -129,7 +129,8 @@ static int solve_on(Solver& solver, Arena& ws, int* flags, hipStream_t stream, i
   if (opt) o = *opt;
   else lyap_default_options(&o);
   if (!(o.tol >= 0) || o.i_max < 0 || o.i_max > 63 || o.k_max < 1 || o.k_max > 64 ||
-      !(o.rho > 0) || !(o.eta_r >= 0) || !(o.theta > 0))
+      !(o.rho > 0) || !(o.eta_r >= 0) || !(o.theta > 0) || (o.form != 0 && o.form != 1) ||
+      (o.form == 1 && S != nullptr))
     return LYAP_BADARG;
   lyap_info local;
   lyap_info* inf = info ? info : &local;
@@ -183,6 +184,7 @@ void lyap_default_options(lyap_options* o) {
   o->theta = 0.9;
   o->refine = 1;
   o->psd = -1;
+  o->form = 0;
 }
 
 int lyap_create(lyap_handle* h, int device) {

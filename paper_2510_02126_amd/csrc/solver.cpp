@@ -100,6 +100,7 @@ struct Solver::Ctx {
   // truncation, the residual factorisation and the update then orthogonalise only the rest.
   int orth = 0;
   bool zc_orth = false;
+  bool chol = false;  // Cholesky-type IR (Alg 2.1)
 };
 
 int Solver::upload_d(Ctx& c, const std::vector<double>& d, double* dst) {
@@ -407,8 +408,10 @@ int Solver::res_factor(Ctx& c, int& rd, std::vector<double>& sd) {
 // ------------------------------------------------------------------ solution update
 // Fragment 2.4: G = [Z, Z^D] = V Gamma, K = Gamma blkdiag(D, D^D) Gamma^T = Theta Sigma Theta^T,
 // keep sigma >= eta_s max|sigma| (|sigma| when the PSD projection is off);
-// Z <- V Theta_t (into Zc), D <- Sigma_t.  The correction Z^D is read from Zs.
-int Solver::sol_upt(Ctx& c, int& cols, std::vector<double>& d, int cd,
+// Z <- V Theta_t (into Zc), D <- Sigma_t.  The correction Z^D (cd columns) is read from Zcor.
+// Fragment 2.2 (Cholesky type) is the same with Z^D = [Z+, Z-], D^D = (D+, -D-) and the PSD
+// projection: G = [Z, Z+, Z-] scaled by the square roots of the weights gives its K.
+int Solver::sol_upt(Ctx& c, int& cols, std::vector<double>& d, const double* Zcor, int cd,
                     const std::vector<double>& dd, double eta_s, bool psd) {
   hipStream_t s = c.s;
   const int n = c.n, cap = c.cap;
@@ -425,7 +428,7 @@ int Solver::sol_upt(Ctx& c, int& cols, std::vector<double>& d, int cd,
   double* Vm = Vm_.as<double>();
   double* wv = wv_.as<double>();
   LYAP_TRY(copy_block(s, n, cols, Zc, cap, F, cap));
-  LYAP_TRY(copy_block(s, n, cd, Zs_.as<double>(), cap, F + cols, cap));
+  LYAP_TRY(copy_block(s, n, cd, Zcor, cap, F + cols, cap));
   c.ws->reset();
   LYAP_TRY(qr_lead(s, n, q, c.zc_orth ? cols : 0, F, cap, Uq, cap, Tq, cap, *c.ws, c.kt));
   std::vector<double> ups(d);
@@ -498,8 +501,11 @@ int Solver::solve(hipStream_t s, Arena& ws, int* flags, int n, int m, const doub
   }
   bool all_nonneg = true;
   for (double v : c.svec) all_nonneg = all_nonneg && v >= 0.0;
-  c.psd = opt.psd < 0 ? all_nonneg : (opt.psd != 0);
-  c.cap = 2 * n + 2 * m + 64;
+  c.chol = opt.form == 1;
+  c.psd = c.chol || (opt.psd < 0 ? all_nonneg : (opt.psd != 0));
+  // column capacity of the tall buffers: [Z, AZ, L] and [Z, Z^D]; the Cholesky type keeps two
+  // corrections, [Z, Z+, Z-]
+  c.cap = (c.chol ? 3 : 2) * n + 2 * m + 64;
   const int cap = c.cap;
   const size_t nn = (size_t)n * n, ncap = (size_t)n * cap;
   const size_t RP = 256;
@@ -618,26 +624,70 @@ int Solver::solve(hipStream_t s, Arena& ws, int* flags, int n, int m, const doub
     t0 = clk::now();
     LYAP_TRY(res_factor(c, rd, sd));
     info->phase_ms[4] += ms_since(t0);
-    // correction equation at the solver precision, reusing the cached inverses
+    // correction equation(s) at the solver precision, reusing the cached inverses
     t0 = clk::now();
     int cd = 0;
     std::vector<double> dd;
-    LYAP_TRY(factor_iteration(c, Zd_.as<double>(), cap, rd, rd, sd, false, cd, dd));  // U Q_t
+    const double* Zcor = Zs_.as<double>();
+    if (!c.chol) {
+      LYAP_TRY(factor_iteration(c, Zd_.as<double>(), cap, rd, rd, sd, false, cd, dd));  // U Q_t
+    } else {
+      // Fragment 2.1: R = L+ L+^T - L- L-^T with L+- = U Q_+- |Lambda_+-|^(1/2), here as
+      // (U Q_+-, |lambda|); the two correction equations (Alg 2.1) share the inverse sequence
+      // and are truncated independently.  U Q_t is gathered into F (positive part first),
+      // and the corrections Z+ and Z- are collected in Zd.
+      std::vector<int> order;
+      std::vector<double> dp, dm;
+      for (int i = 0; i < rd; ++i)
+        if (sd[i] > 0.0) { order.push_back(i); dp.push_back(sd[i]); }
+      const int rp = (int)order.size();
+      for (int i = 0; i < rd; ++i)
+        if (sd[i] < 0.0) { order.push_back(i); dm.push_back(-sd[i]); }
+      const int rm = (int)order.size() - rp;
+      double* Fb = F_.as<double>();
+      double* Zpm = Zd_.as<double>();
+      if (!order.empty()) {
+        LYAP_HIP(hipMemcpyAsync(idx_.p, order.data(), order.size() * sizeof(int),
+                                hipMemcpyHostToDevice, s));
+        LYAP_TRY(gather_cols(s, n, (int)order.size(), Zd_.as<double>(), cap, idx_.as<int>(), Fb,
+                             cap));
+      }
+      int cp = 0, cm = 0;
+      std::vector<double> ddp, ddm;
+      LYAP_TRY(factor_iteration(c, Fb, cap, rp, rp, dp, true, cp, ddp));
+      LYAP_TRY(copy_block(s, n, cp, Zs_.as<double>(), cap, Zpm, cap));
+      LYAP_TRY(factor_iteration(c, Fb + rp, cap, rm, rm, dm, true, cm, ddm));
+      if (cp + cm > cap) return LYAP_CAPACITY;
+      LYAP_TRY(copy_block(s, n, cm, Zs_.as<double>(), cap, Zpm + cp, cap));
+      cd = cp + cm;
+      dd = ddp;
+      for (double x : ddm) dd.push_back(-x);
+      Zcor = Zpm;
+    }
     LYAP_HIP(hipStreamSynchronize(s));
     info->phase_ms[2] += ms_since(t0);
     info->newton_total += c.K;
     info->refinements += 1;
-    // projected solution update (Fragment 2.4)
+    // projected solution update (Fragment 2.4; Fragment 2.2 for the Cholesky type)
     t0 = clk::now();
-    LYAP_TRY(sol_upt(c, cols, d, cd, dd, eta_s, c.psd));
+    LYAP_TRY(sol_upt(c, cols, d, Zcor, cd, dd, eta_s, c.psd));
     info->phase_ms[5] += ms_since(t0);
   }
   info->rank = cols;
   *rank = cols;
   if (cols > z_cap) return LYAP_CAPACITY;
-  LYAP_TRY(copy_block(s, n, cols, Zc_.as<double>(), cap, Z, ldz));
-  if (cols > 0)
-    LYAP_HIP(hipMemcpyAsync(D, d.data(), cols * sizeof(double), hipMemcpyHostToDevice, s));
+  if (!c.chol) {
+    LYAP_TRY(copy_block(s, n, cols, Zc_.as<double>(), cap, Z, ldz));
+    if (cols > 0)
+      LYAP_HIP(hipMemcpyAsync(D, d.data(), cols * sizeof(double), hipMemcpyHostToDevice, s));
+  } else if (cols > 0) {
+    // Cholesky-type factor Z diag(d)^(1/2) (d >= 0 after the PSD projection), D = 1
+    std::vector<double> sq(cols), ones(cols, 1.0);
+    for (int i = 0; i < cols; ++i) sq[i] = std::sqrt(std::max(d[i], 0.0));
+    LYAP_TRY(upload_d(c, sq, dvec_.as<double>()));
+    LYAP_TRY(copy_block(s, n, cols, Zc_.as<double>(), cap, Z, ldz, dvec_.as<double>()));
+    LYAP_HIP(hipMemcpyAsync(D, ones.data(), cols * sizeof(double), hipMemcpyHostToDevice, s));
+  }
   LYAP_HIP(hipStreamSynchronize(s));
   if (kt_.collect() == LYAP_OK) {
     for (int f = 0; f < KernTimer::NF; ++f) {

@@ -41,8 +41,8 @@ class Solver {
   int res_fac(Ctx& c, const double* Zb, long ldb, int cols, const std::vector<double>& d,
               bool want_factor, double& normR, int& rd, std::vector<double>& sd);
   int res_factor(Ctx& c, int& rd, std::vector<double>& sd);
-  int sol_upt(Ctx& c, int& cols, std::vector<double>& d, int cd, const std::vector<double>& dd,
-              double eta_s, bool psd);
+  int sol_upt(Ctx& c, int& cols, std::vector<double>& d, const double* Zcor, int cd,
+              const std::vector<double>& dd, double eta_s, bool psd);
   int upload_d(Ctx& c, const std::vector<double>& d, double* dst);
 
   // persistent buffers (grown to the largest problem seen)
