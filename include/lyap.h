@@ -123,18 +123,20 @@ const char* lyap_strerror(int code);
 const char* lyap_version(void);
 
 /*
- * lyap_solve -- Alg 2.2 (LDL^T-type mixed-precision IR) with Alg 3.2 as the solver.
+ * lyap_solve -- Alg 2.2 (LDL^T-type mixed-precision IR) with Alg 3.2 as the solver, or with
+ * opt->form == 1 Alg 2.1 (Cholesky type, W = L L^T only).
  *
- *  n, m      order of A and number of columns of L (1 <= m <= n).
+ *  n, m      order of A (n <= 4096) and number of columns of L (1 <= m <= n).
  *  A         n x n FP64, row-major, leading dimension lda >= n; A must be Hurwitz.
  *  L         n x m FP64, row-major, ldl >= m.
  *  S         m FP64 values: the diagonal of S (W = L diag(S) L^T), or NULL for W = L L^T.
  *  prec      precisions {u_s, u, u_r, u_c}; u, u_r, u_c must be LYAP_F64.
  *  opt       options or NULL for the defaults.
  *  Z         n x z_cap FP64 output, row-major, ldz >= z_cap; columns 0..rank-1 receive
- *            orthonormal factor columns.
- *  D         z_cap FP64 output: the diagonal of D (X ~ Z diag(D) Z^T).  For a Cholesky-type
- *            equation (S == NULL) D > 0 and Z diag(sqrt D) is a Cholesky-type factor.
+ *            orthonormal factor columns (form 0) or the Cholesky-type factor (form 1).
+ *  D         z_cap FP64 output: the diagonal of D (X ~ Z diag(D) Z^T).  For W = L L^T
+ *            (S == NULL) D > 0 and Z diag(sqrt D) is a Cholesky-type factor; with form 1,
+ *            D = 1.
  *  rank      host int: the number of columns written.
  *  info      host lyap_info or NULL.
  * Returns LYAP_OK when res <= tol.  LYAP_NOT_CONVERGED / LYAP_STAGNATED still write the
