@@ -1,5 +1,6 @@
-// Symmetric spectral decomposition H = V diag(w) V^T in FP64 (the spectral decompositions of
-// Fragments 2.1-2.4 and of RankTruncLdlt in Alg 3.2): two-sided cyclic block Jacobi.
+// Symmetric spectral decomposition H = V diag(w) V^T (the spectral decompositions of
+// Fragments 2.1-2.4 and of RankTruncLdlt in Alg 3.2): two-sided cyclic block Jacobi, in FP64
+// (or FP32 rotations on request; H, w and V stay FP64).
 //
 // The matrix (padded to a multiple of 32 with zero rows/columns, which stay decoupled) is cut
 // into blocks of 16 indices.  A sweep visits every pair of blocks once in a round-robin
@@ -12,9 +13,12 @@
 // blocks (16 steps instead of 31), so each index pair of the matrix is rotated once per sweep.
 //
 // One kernel per round, with A ping-ponged between two buffers: its first workgroups solve the
-// subproblems of round r + 1 while the others apply round r.  The subproblem of a round-(r+1)
-// pair is formed directly from the matrix before round r and round r's rotations (each of its
-// four 16 x 16 blocks is a slice of R_P^T A_PQ R_Q), so the solves do not wait for the update.
+// subproblems of round r + 1 while the others (persistent workers) apply round r.  The
+// subproblem of a round-(r+1) pair is formed directly from the matrix before round r and round
+// r's rotations (each of its four 16 x 16 blocks is a slice of R_P^T A_PQ R_Q), so the solves
+// do not wait for the update.  A is kept as its upper triangle of 16 x 16 blocks (a block
+// below the diagonal is read as the transpose of its mirror), so a round updates the pair
+// blocks P <= Q only.
 //
 // Rotations are skipped when |a_pq| is below an absolute floor (tol ||A||_F / (4 pp)) or, when
 // the caller asks for eigenvalues accurate relative to their own size, below
