@@ -238,6 +238,17 @@ int lyap_gemm(lyap_handle h, void* stream, int dtype, int transa, int transb, in
               double beta, double* C, int ldc);
 
 /*
+ * lyap_qr_lead -- the same thin QR F = U T (n >= p) when the first c columns Z of F are
+ * orthonormal to working precision, as the truncated and updated factors of the solver are
+ * (RankTruncLdlt in Alg 3.2, Fragments 2.3 / 2.4): C = Z^T Y and Y <- Y - Z C twice (block
+ * Gram-Schmidt with reorthogonalisation), then the Householder QR of lyap_qr of the projected
+ * Y = Q2 R2, so U = [Z, Q2] and T = [[I, C], [0, R2]].  Same layouts and errors as lyap_qr;
+ * 0 <= c <= p (c = 0 or c < 32 gives lyap_qr's factorisation).  F is not modified.  If Z is
+ * not orthonormal the result is not a QR factorisation of F.
+ */
+int lyap_qr_lead(lyap_handle h, void* stream, int n, int p, int c, const double* F, int ldf,
+                 double* U, int ldu, double* T, int ldt);
+/*
  * lyap_qr -- thin QR F = U T of the n x p FP64 matrix F, as used by the residual
  * factorisation and solution update (Fragments 2.1-2.4) and RankTruncLdlt (Alg 3.2):
  * right-looking blocked Householder QR whose panels are factored by a two-level

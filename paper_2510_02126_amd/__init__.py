@@ -90,13 +90,20 @@ def gemm(A, B, C=None, alpha=1.0, beta=0.0, transa=False, transb=False, dtype="f
     return C
 
 
-def qr(F: torch.Tensor):
+def qr(F: torch.Tensor, lead: int = 0):
+    """Thin QR F = U T (library kernels).  ``lead`` > 0 states that the first ``lead``
+    columns of F are orthonormal (lyap_qr_lead)."""
     dev = _dev(F)
     F, ldf = _rowmajor(F)
     n, p = F.shape
     k = min(n, p)
     U = torch.empty((n, k), dtype=torch.float64, device=F.device)
     T = torch.empty((k, p), dtype=torch.float64, device=F.device)
+    if lead > 0:
+        code = _lib.lib().lyap_qr_lead(_lib.handle(dev), _stream(dev), n, p, int(lead), _ptr(F),
+                                       ldf, _ptr(U), k, _ptr(T), p)
+        _lib.check(code, "lyap_qr_lead")
+        return U, T
     code = _lib.lib().lyap_qr(_lib.handle(dev), _stream(dev), n, p, _ptr(F), ldf, _ptr(U), k,
                               _ptr(T), p)
     _lib.check(code, "lyap_qr")

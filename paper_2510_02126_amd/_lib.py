@@ -95,6 +95,7 @@ _SIGS = {
     "lyap_inverse": (I, [P, P, I, I, I, P, I, P, I]),
     "lyap_gemm": (I, [P, P, I, I, I, I, I, I, D, P, I, P, I, D, P, I]),
     "lyap_qr": (I, [P, P, I, I, P, I, P, I, P, I]),
+    "lyap_qr_lead": (I, [P, P, I, I, I, P, I, P, I, P, I]),
     "lyap_syev": (I, [P, P, I, P, I, P, P, I]),
 }
 

@@ -282,6 +282,25 @@ int lyap_qr(lyap_handle h, void* stream, int n, int p, const double* F, int ldf,
   return LYAP_OK;
 }
 
+int lyap_qr_lead(lyap_handle h, void* stream, int n, int p, int c, const double* F, int ldf,
+                 double* U, int ldu, double* T, int ldt) {
+  if (!h || n < 0 || p < 0 || n > 4096 || p > n || c < 0 || c > p ||
+      (p > 0 && (!F || !U || !T || ldf < p || ldu < p || ldt < p)))
+    return LYAP_BADARG;
+  if (p == 0) return LYAP_OK;
+  hipStream_t s = (hipStream_t)stream;
+  const size_t q = (size_t)(p - c);
+  LYAP_TRY(h->ws.reserve(qr_workspace_bytes(n, p) + (size_t)n * p * 8 + (size_t)c * q * 8 +
+                         ((size_t)4 << 23) + (2 << 20)));
+  h->ws.reset();
+  double* W = h->ws.take<double>((size_t)n * p);
+  if (!W) return LYAP_NO_MEMORY;
+  LYAP_TRY(copy_block(s, n, p, F, ldf, W, p));
+  LYAP_TRY(qr_lead(s, n, p, c, W, p, U, ldu, T, ldt, h->ws));
+  LYAP_HIP(hipStreamSynchronize(s));
+  return LYAP_OK;
+}
+
 int lyap_syev(lyap_handle h, void* stream, int p, const double* H, int ldh, double* w, double* V,
               int ldv) {
   if (!h || p < 0 || (p > 0 && (!H || !w || !V || ldh < p || ldv < p))) return LYAP_BADARG;

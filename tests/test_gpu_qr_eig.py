@@ -33,6 +33,33 @@ def test_qr_full_rank(lyap, n, p):
     assert np.allclose(np.tril(T, -1), 0.0)
 
 
+@pytest.mark.parametrize("n,c,q", [(1000, 300, 400), (2048, 512, 512), (4096, 96, 33),
+                                   (500, 40, 1)])
+def test_qr_orthonormal_lead(lyap, n, c, q):
+    # F = [Z, Y] with Z orthonormal and Y partly in the span of Z (the structure of a
+    # truncated factor extended by A^{-1} Z): lyap_qr_lead keeps Z as the first columns of U
+    # and I as the leading block of T; U T = F and U^T U = I to working precision, and T^T T
+    # equals that of the plain Householder QR (both are F^T F).
+    print(f"qr with orthonormal lead n={n} c={c} q={q}", flush=True)
+    rng = np.random.default_rng(n + c + q)
+    Z, _ = np.linalg.qr(rng.standard_normal((n, c)))
+    Y = rng.standard_normal((n, q)) * np.logspace(0, -8, q)[None, :]
+    k = min(q, c) // 2
+    Y[:, :k] = Z[:, :k] @ rng.standard_normal((k, k)) + 1e-12 * rng.standard_normal((n, k))
+    F = np.hstack([Z, Y])
+    U, T = (x.cpu().numpy() for x in lyap.qr(_cuda(F), lead=c))
+    u = 2.0 ** -53
+    p = c + q
+    assert np.array_equal(U[:, :c], Z)
+    assert np.array_equal(T[:c, :c], np.eye(c))
+    assert np.allclose(np.tril(T, -1), 0.0)
+    assert np.linalg.norm(U @ T - F) <= 50 * u * np.sqrt(n * p) * np.linalg.norm(F)
+    assert np.linalg.norm(U.T @ U - np.eye(p)) <= 50 * u * np.sqrt(n * p)
+    U0, T0 = (x.cpu().numpy() for x in lyap.qr(_cuda(F)))
+    G = F.T @ F
+    assert np.linalg.norm(T.T @ T - T0.T @ T0) <= 100 * u * np.sqrt(n * p) * np.linalg.norm(G)
+
+
 def test_qr_rank_deficient(lyap):
     # F = [Z, A Z, L]-like: the middle block is (nearly) in the span of the others
     print("qr rank-deficient n=2048 p=136", flush=True)
