@@ -3,14 +3,17 @@
 // (or FP32 rotations on request; H, w and V stay FP64).
 //
 // The matrix (padded to a multiple of 32 with zero rows/columns, which stay decoupled) is cut
-// into blocks of 16 indices.  A sweep visits every pair of blocks once in a round-robin
-// tournament (nb - 1 rounds of nb / 2 disjoint pairs).  Round r computes, for each of its
-// pairs, a 32 x 32 orthogonal R_p from Jacobi rotations of the pair's subproblem in LDS, and
-// then A <- G^T A G, V <- V G with G the block-diagonal (in pair order) of the R_p: block
-// (p, q) of A becomes R_p^T A_pq R_q (FP64 matrix cores).  In the first round of a sweep the
-// subproblems get a full cyclic sweep (every pair of their 32 indices, so every pair inside a
-// block is rotated once per sweep); later rounds rotate only the 16 x 16 pairs across the two
-// blocks (16 steps instead of 31), so each index pair of the matrix is rotated once per sweep.
+// into nb blocks of 16 indices.  A sweep visits every pair of blocks once in nb rounds of
+// nb / 2 disjoint pairs, in the modulus ordering: round t takes the pairs (i, j), i < j, with
+// i + j = t mod nb.  That sequence is the row-cyclic ordering of the block pairs with only
+// disjoint pairs exchanged, so it performs the same rotations as row-cyclic Jacobi, which on
+// the graded matrices met here needs far fewer sweeps than a round-robin tournament.  Round t
+// computes, for each of its pairs, a 32 x 32 orthogonal R_p from Jacobi rotations of the
+// pair's subproblem in LDS, and then A <- G^T A G, V <- V G with G the block-diagonal (in pair
+// order) of the R_p: block (p, q) of A becomes R_p^T A_pq R_q (FP64 matrix cores).  In the
+// first two rounds of a sweep (between them every block takes part) the subproblems get a
+// full cyclic sweep (every pair of their 32 indices, including the pairs inside a block);
+// later rounds rotate only the 16 x 16 pairs across the two blocks (16 steps instead of 31).
 //
 // One kernel per round, with A ping-ponged between two buffers: its first workgroups solve the
 // subproblems of round r + 1 while the others (persistent workers) apply round r.  The
@@ -155,12 +158,6 @@ struct SolveLds {
 // matrix-core tiles of the A and V update).
 constexpr int NTJ = 256;
 
-// Slot of element e in round r of the circle tournament on m slots (inverse of circle_elem).
-__device__ inline int circle_slot(int e, int r, int m) {
-  if (e == 0) return 0;
-  return 1 + ((e - 1 - r) % (m - 1) + (m - 1)) % (m - 1);
-}
-
 // Index pair k of step r of a subproblem sweep (p < q).  A full sweep (SB - 1 steps of the
 // circle tournament on SB indices) rotates every pair of the subproblem once; a cross sweep
 // (HB steps, pair k of step r = (k, HB + (k + r) mod HB)) rotates only the pairs with one
@@ -219,13 +216,21 @@ __device__ int subproblem_sweep(SolveLds<T>& L, T thr, T eps, bool full) {
 
 // Solve workgroup for pair j = (bI, bJ) of ``pn``: form its subproblem, run one sweep, store
 // the rotation to Rn[j].  With Rc == nullptr the subproblem is read from A directly; otherwise
-// A is the matrix before the round whose pairs ``pc`` and rotations Rc are given.
+// A is the matrix before the round whose pairs ``pc``, block map ``mc`` (block b sits in pair
+// mc[b] / 2 at half mc[b] % 2) and rotations Rc are given.  The pair j == pseudo (the two
+// blocks idle in a round) gets the identity.
 template <class T>
 __device__ void solve_pair(SolveLds<T>& L, int pp, int np, const T* __restrict__ A,
-                           const int* __restrict__ pc, int rc, const T* __restrict__ Rc,
-                           const int* __restrict__ pn, int j, bool full, T thr, T eps,
-                           T* __restrict__ Rn, int* __restrict__ applied) {
+                           const int* __restrict__ pc, const int* __restrict__ mc,
+                           const T* __restrict__ Rc, const int* __restrict__ pn, int j,
+                           int pseudo, bool full, T thr, T eps, T* __restrict__ Rn,
+                           int* __restrict__ applied) {
   const int t = threadIdx.x;
+  if (j == pseudo) {
+    T* Ro = Rn + (long)j * SB * SB;
+    for (int e = t; e < SB * SB; e += NTJ) Ro[e] = (e / SB == e % SB) ? T(1) : T(0);
+    return;
+  }
   const int nI = pn[2 * j], nJ = pn[2 * j + 1];
   T (&X)[SB][LDS_PAD] = L.S[1];
   T (&RA)[SB][LDS_PAD] = L.R[1];
@@ -237,15 +242,12 @@ __device__ void solve_pair(SolveLds<T>& L, int pp, int np, const T* __restrict__
       L.S[0][i][k] = A[sidx(gidx(i, nI, nJ), gidx(k, nI, nJ), pp)];
     }
   } else {
-    // block b of the new pair sits in current pair P(b) at half h(b): its slot in round rc
-    // of the block tournament gives the pair, the stored (min, max) order the half
-    const int nbk = 2 * np;
+    // block b of the new pair sits in current pair P(b) at half H(b)
     int P[2], H[2];
     for (int h = 0; h < 2; ++h) {
-      const int blk = h == 0 ? nI : nJ;
-      const int slot = circle_slot(blk, rc, nbk);
-      P[h] = slot < np ? slot : nbk - 1 - slot;
-      H[h] = pc[2 * P[h]] == blk ? 0 : 1;
+      const int e = mc[h == 0 ? nI : nJ];
+      P[h] = e >> 1;
+      H[h] = e & 1;
     }
     int bi[2], bj[2];
     for (int h = 0; h < 2; ++h) {
@@ -346,16 +348,17 @@ __device__ void solve_pair(SolveLds<T>& L, int pp, int np, const T* __restrict__
 // First solve of the iteration (subproblems read from A).
 template <class T>
 __global__ __launch_bounds__(NTJ) void jac_solve0(int pp, int np, const T* __restrict__ A,
-                                                  const int* __restrict__ pn,
+                                                  const int* __restrict__ pn, int pseudo,
                                                   const double* __restrict__ thr_dev, double eps,
                                                   T* __restrict__ Rn, int* __restrict__ applied) {
   __shared__ SolveLds<T> L;
-  solve_pair<T>(L, pp, np, A, nullptr, 0, nullptr, pn, blockIdx.x, true, (T)*thr_dev, (T)eps,
-                Rn, applied);
+  solve_pair<T>(L, pp, np, A, nullptr, nullptr, nullptr, pn, blockIdx.x, pseudo, true,
+                (T)*thr_dev, (T)eps, Rn, applied);
 }
 
 // One round.  Blocks [0, np): solves of the next round's pairs pn (rotations to Rn; a full
-// subproblem sweep when the next round is the first of a sweep, a cross sweep otherwise).
+// subproblem sweep when the next round is one of the first two of a sweep, a cross sweep
+// otherwise).
 // The other blocks are update workers that take items w, w + nw, w + 2 nw, ... of
 //   items [0, na), na = np (np + 1) / 2: pair blocks P <= Q, Aout block (pair P rows, pair Q
 //                 cols) = R_P^T Ain_PQ R_Q, stored into the upper block triangle,
@@ -416,9 +419,10 @@ __device__ inline void load_item(const Item& it, int pp, const int* __restrict__
 template <class T>
 __global__ __launch_bounds__(NTJ) void jac_round(int pp, int np, const T* __restrict__ Ain,
                                                  T* __restrict__ Aout, T* __restrict__ V,
-                                                 const int* __restrict__ pc, int rc,
+                                                 const int* __restrict__ pc,
+                                                 const int* __restrict__ mc,
                                                  const T* __restrict__ Rc,
-                                                 const int* __restrict__ pn, int full,
+                                                 const int* __restrict__ pn, int pseudo, int full,
                                                  T* __restrict__ Rn,
                                                  const double* __restrict__ thr_dev, double eps,
                                                  int* __restrict__ applied) {
@@ -426,8 +430,8 @@ __global__ __launch_bounds__(NTJ) void jac_round(int pp, int np, const T* __rest
   __shared__ SolveLds<T> L;
   const int blk = blockIdx.x;
   if (blk < np) {
-    solve_pair<T>(L, pp, np, Ain, pc, rc, Rc, pn, blk, full != 0, (T)*thr_dev, (T)eps, Rn,
-                  applied);
+    solve_pair<T>(L, pp, np, Ain, pc, mc, Rc, pn, blk, pseudo, full != 0, (T)*thr_dev, (T)eps,
+                  Rn, applied);
     return;
   }
   const int nw = gridDim.x - np;
@@ -619,7 +623,7 @@ size_t syev_workspace_bytes(int p) {
   size_t s = 0;
   s += 3 * align_up(pp * pp * 8, 256);
   s += 2 * align_up(np * SB * SB * 8, 256);
-  s += align_up((nb - 1) * np * 2 * 4 + 8, 256);
+  s += align_up(nb * np * 2 * 4 + 8, 256) + align_up(nb * nb * 4 + 8, 256);
   s += align_up(2 * 256 * 8, 256) + align_up(4 * 8, 256) + align_up(pp * 4, 256) + 256;
   return s + 4096;
 }
@@ -630,32 +634,50 @@ template <class T>
 int syev_t(hipStream_t s, int p, const double* H, long ldh, double* w, double* V, long ldv,
            Arena& ws, double tol_rel, int* sweeps_out, KernTimer* kt, bool relative) {
   const int pp = ceil_div(p, SB) * SB;
-  const int nb = pp / HB, np = nb / 2, rounds = nb - 1;
+  const int nb = pp / HB, np = nb / 2, rounds = nb;
   T* Aw[2] = {ws.take<T>((size_t)pp * pp), ws.take<T>((size_t)pp * pp)};
   T* Vw = ws.take<T>((size_t)pp * pp);
   T* Rb[2] = {ws.take<T>((size_t)np * SB * SB), ws.take<T>((size_t)np * SB * SB)};
   int* pairs = ws.take<int>((size_t)rounds * np * 2 + 2);
+  int* bmap = ws.take<int>((size_t)rounds * nb + 2);
   double* part = ws.take<double>(2 * 256);  // nparts pairs
   double* scal = ws.take<double>(4);
   int* perm = ws.take<int>(pp);
   int* applied = ws.take<int>(1);
-  if (!Aw[0] || !Aw[1] || !Vw || !Rb[0] || !Rb[1] || !pairs || !part || !scal || !perm ||
-      !applied)
+  if (!Aw[0] || !Aw[1] || !Vw || !Rb[0] || !Rb[1] || !pairs || !bmap || !part || !scal ||
+      !perm || !applied)
     return LYAP_NO_MEMORY;
   if (tol_rel <= 0.0) tol_rel = 1e-15;
   const double eps = relative ? tol_rel : 0.0;
-  // round-robin schedule of block pairs (host-computed, uploaded once)
-  std::vector<int> sched((size_t)rounds * np * 2);
-  for (int r = 0; r < rounds; ++r)
-    for (int k = 0; k < np; ++k) {
-      int a = (k == 0) ? 0 : 1 + (k - 1 + r) % (nb - 1);
-      int kb = nb - 1 - k;
-      int b = (kb == 0) ? 0 : 1 + (kb - 1 + r) % (nb - 1);
-      sched[((size_t)r * np + k) * 2] = std::min(a, b);
-      sched[((size_t)r * np + k) * 2 + 1] = std::max(a, b);
+  // Block pair schedule (modulus ordering): round t rotates the block pairs (i, j), i < j,
+  // with i + j = t mod nb, listed by i.  Every pair appears once in the nb rounds of a sweep,
+  // and the sequence of rounds, sweep after sweep, is the row-cyclic sequence of pairs with
+  // only disjoint (commuting) pairs reordered, so it converges like the row-cyclic ordering.
+  // Even rounds leave blocks t / 2 and t / 2 + nb / 2 idle: they form the last pair of the
+  // round with the identity as rotation.  bmap[t][b] = 2 k + h for block b at half h of
+  // pair k of round t.
+  std::vector<int> sched((size_t)rounds * np * 2), bm((size_t)rounds * nb);
+  for (int r = 0; r < rounds; ++r) {
+    int k = 0;
+    for (int i = 0; i < nb; ++i) {
+      const int j = (r - i + nb) % nb;
+      if (j <= i) continue;
+      sched[((size_t)r * np + k) * 2] = i;
+      sched[((size_t)r * np + k) * 2 + 1] = j;
+      ++k;
     }
+    if (r % 2 == 0) {
+      sched[((size_t)r * np + k) * 2] = r / 2;
+      sched[((size_t)r * np + k) * 2 + 1] = r / 2 + np;
+      ++k;
+    }
+    if (k != np) return LYAP_BADARG;  // not reached: every round holds np pairs
+    for (k = 0; k < np; ++k)
+      for (int h = 0; h < 2; ++h) bm[(size_t)r * nb + sched[((size_t)r * np + k) * 2 + h]] = 2 * k + h;
+  }
   LYAP_HIP(hipMemcpyAsync(pairs, sched.data(), sched.size() * sizeof(int), hipMemcpyHostToDevice,
                           s));
+  LYAP_HIP(hipMemcpyAsync(bmap, bm.data(), bm.size() * sizeof(int), hipMemcpyHostToDevice, s));
   hipLaunchKernelGGL((jac_load<T>), dim3((unsigned)ceil_div(pp * pp, 256)), dim3(256), 0, s, p, pp, H,
                      ldh, Aw[0], Vw);
   const int nparts = 256;
@@ -680,8 +702,8 @@ int syev_t(hipStream_t s, int p, const double* H, long ldh, double* w, double* V
     if (host[0] <= tol_rel * tol_rel * total) break;
     if (sweep > 0 && host[2] == 0.0) break;
     if (!solved) {
-      hipLaunchKernelGGL((jac_solve0<T>), dim3(np), dim3(NTJ), 0, s, pp, np, Aw[cur], pairs, thr,
-                         eps, Rb[rc], applied);
+      hipLaunchKernelGGL((jac_solve0<T>), dim3(np), dim3(NTJ), 0, s, pp, np, Aw[cur], pairs,
+                         np - 1, thr, eps, Rb[rc], applied);
       solved = true;
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -691,8 +713,9 @@ int syev_t(hipStream_t s, int p, const double* H, long ldh, double* w, double* V
       const int rn = (r + 1) % rounds;
       const int* pn = pairs + (size_t)rn * np * 2;
       hipLaunchKernelGGL((jac_round<T>), dim3(np + nw), dim3(NTJ), 0, s, pp, np,
-                         Aw[cur], Aw[cur ^ 1], Vw, pc, r, Rb[rc], pn, rn == 0 ? 1 : 0, Rb[rc ^ 1],
-                         thr, eps, applied);
+                         Aw[cur], Aw[cur ^ 1], Vw, pc, bmap + (size_t)r * nb, Rb[rc], pn,
+                         rn % 2 == 0 ? np - 1 : -1, rn <= 1 ? 1 : 0, Rb[rc ^ 1], thr, eps,
+                         applied);
       cur ^= 1;
       rc ^= 1;
     }
