@@ -1,0 +1,69 @@
+"""Parity at the full size of the n = 4096 workload (lyapgen.config("large"): A = Q T Q^T with
+kappa ~ 1e3, W = L S L^T indefinite, m = 8), in the configuration bench.py times: the
+fp32-inner mixed-precision IR solve and the FP64 sign-function Newton solve.
+
+  * The relative residual of eq (4.1), recomputed on the host in float64 by the oracle from
+    the returned factors, is <= 1e-13 and agrees with the one the library reports.
+  * Sampled entries, the Frobenius norm and the trace of X = Z diag(D) Z^T match the exact
+    solution (the oracle's Schur-form solve; tests/golden/large_x_samples.json, written by
+    tests/golden/make_large_samples.py).  Tolerance: X_hat - X = L^{-1}(R) with
+    ||R||_F = res (||W||_F + 2 ||A||_F ||X_hat||_F) and res <= 1e-13.  Here ||A||_F ~ 19 and
+    ||L^{-1}||_2 ~ 1 / (2 min |lambda(A)|) = 500 up to the non-normality of T (its inverse
+    stays within 1.2x of the normal matrix's), so ||X_hat - X||_F / ||X||_F <= about 2.5e-9;
+    entries are held to 1e-8 ||X||_F."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import lyapgen
+from oracle import residual as R
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                      "large_x_samples.json")
+
+
+@pytest.fixture(scope="module")
+def lyap():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2510_02126_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def large():
+    cfg = lyapgen.config("large")
+    with open(GOLDEN) as f:
+        gold = json.load(f)
+    return cfg, gold
+
+
+@pytest.mark.parametrize("prec", [("fp32", "fp64", "fp64", "fp64"), ("fp64",) * 4],
+                         ids=["ir_fp32_inner", "fp64_sign_newton"])
+def test_large_workload_parity(lyap, large, prec):
+    cfg, gold = large
+    A, L, S = cfg["A"], cfg["L"], cfg["S"]
+    print(f"large workload n=4096 m=8 precisions={prec}", flush=True)
+    Ad, Ld, Sd = (torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in (A, L, S))
+    Z, D, info = lyap.solve(Ad, Ld, Sd, precisions=prec)
+    Z, D = Z.cpu().numpy(), D.cpu().numpy()
+    res = R.relres(A, L, S, Z, D)
+    ii, jj = np.array(gold["i"]), np.array(gold["j"])
+    xs = np.einsum("kc,c,kc->k", Z[ii], D, Z[jj])
+    fro = float(np.sqrt(np.sum((Z.T @ Z * D[:, None] * D[None, :]) * (Z.T @ Z))))
+    tr = float(np.sum(D * np.sum(Z * Z, axis=0)))
+    err = np.max(np.abs(xs - np.array(gold["x"]))) / gold["fro"]
+    print(f"  status={info['status']} res host={res:.2e} lib={info['res']:.2e} "
+          f"rank={info['rank']} refinements={info['refinements']} max sample err/||X||="
+          f"{err:.2e} fro rel={abs(fro - gold['fro']) / gold['fro']:.2e}", flush=True)
+    assert info["status"] == "OK"
+    assert res <= 1e-13
+    assert info["res"] == pytest.approx(res, rel=0.05, abs=1e-16)
+    assert err <= 1e-8
+    assert fro == pytest.approx(gold["fro"], rel=1e-8)
+    assert tr == pytest.approx(gold["trace"], abs=1e-8 * gold["fro"] * np.sqrt(gold["n"]))
