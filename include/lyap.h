@@ -269,6 +269,20 @@ int lyap_qr(lyap_handle h, void* stream, int n, int p, const double* F, int ldf,
 int lyap_syev(lyap_handle h, void* stream, int p, const double* H, int ldh, double* w,
               double* V, int ldv);
 
+/*
+ * lyap_jacobi_schedule -- the block-pair schedule lyap_syev sweeps with (host only, no GPU
+ * call, no handle): the spectral decompositions of Fragments 2.1-2.4 and Alg 3.2 are
+ * computed by cyclic Jacobi, whose pair ordering this fixes.  The matrix is cut into nb
+ * blocks (nb even, 2 <= nb <= 256); a sweep is nb rounds of nb/2 disjoint pairs, round t
+ * holding the pairs (i, j), i < j, with i + j = t mod nb in increasing i, and in even rounds
+ * last the pseudo-pair (t/2, t/2 + nb/2) of the two blocks the round leaves idle (rotated by
+ * the identity).  pairs (caller-owned, nb * nb ints): pairs[(t * nb/2 + k) * 2 + h] is block
+ * h of pair k of round t.  bmap (caller-owned, nb * nb ints): bmap[t * nb + b] = 2 k + h for
+ * block b at half h of pair k of round t.  Returns LYAP_BADARG for an odd or out-of-range nb
+ * or a NULL pointer.
+ */
+int lyap_jacobi_schedule(int nb, int* pairs, int* bmap);
+
 #ifdef __cplusplus
 }
 #endif

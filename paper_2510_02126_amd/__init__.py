@@ -122,6 +122,19 @@ def syev(H: torch.Tensor):
     return w, V
 
 
+def jacobi_schedule(nb: int):
+    """The block-pair schedule of the Jacobi sweeps (host only): ``pairs`` (nb, nb/2, 2) with
+    pairs[t, k] the blocks of pair k in round t, and ``bmap`` (nb, nb) with
+    bmap[t, b] = 2 k + h for block b at half h of pair k of round t."""
+    import numpy as np
+
+    pairs = np.zeros(max(nb, 0) * max(nb, 0), dtype=np.int32)
+    bmap = np.zeros(max(nb, 0) * max(nb, 0), dtype=np.int32)
+    code = _lib.lib().lyap_jacobi_schedule(int(nb), pairs.ctypes.data, bmap.ctypes.data)
+    _lib.check(code, "lyap_jacobi_schedule")
+    return pairs.reshape(nb, nb // 2, 2), bmap.reshape(nb, nb)
+
+
 def _solve(fn_name, A, L, S, precisions, tol, refine, z_cap, raise_on_error, opts):
     dev = _dev(A, L, S)
     n = A.shape[0]

@@ -97,6 +97,7 @@ _SIGS = {
     "lyap_qr": (I, [P, P, I, I, P, I, P, I, P, I]),
     "lyap_qr_lead": (I, [P, P, I, I, I, P, I, P, I, P, I]),
     "lyap_syev": (I, [P, P, I, P, I, P, P, I]),
+    "lyap_jacobi_schedule": (I, [I, P, P]),
 }
 
 

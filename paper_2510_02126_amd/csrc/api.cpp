@@ -301,6 +301,11 @@ int lyap_qr_lead(lyap_handle h, void* stream, int n, int p, int c, const double*
   return LYAP_OK;
 }
 
+int lyap_jacobi_schedule(int nb, int* pairs, int* bmap) {
+  if (nb < 2 || nb > 256 || nb % 2 != 0 || !pairs || !bmap) return LYAP_BADARG;
+  return jacobi_schedule(nb, pairs, bmap);
+}
+
 int lyap_syev(lyap_handle h, void* stream, int p, const double* H, int ldh, double* w, double* V,
               int ldv) {
   if (!h || p < 0 || (p > 0 && (!H || !w || !V || ldh < p || ldv < p))) return LYAP_BADARG;

@@ -617,6 +617,38 @@ __global__ void jac_gather(int p, int pp, const T* __restrict__ Vw, const int* _
 
 }  // namespace
 
+// Block pair schedule (modulus ordering): round t rotates the block pairs (i, j), i < j,
+// with i + j = t mod nb, listed by i.  Every pair appears once in the nb rounds of a sweep,
+// and the sequence of rounds, sweep after sweep, is the row-cyclic sequence of pairs with
+// only disjoint (commuting) pairs reordered, so it converges like the row-cyclic ordering.
+// Even rounds leave blocks t / 2 and t / 2 + nb / 2 idle: they form the last pair of the
+// round with the identity as rotation.  bmap[t][b] = 2 k + h for block b at half h of
+// pair k of round t.
+int jacobi_schedule(int nb, int* pairs, int* bmap) {
+  if (nb < 2 || nb % 2 != 0 || !pairs || !bmap) return LYAP_BADARG;
+  const int np = nb / 2;
+  for (int r = 0; r < nb; ++r) {
+    int* pr = pairs + (size_t)r * np * 2;
+    int k = 0;
+    for (int i = 0; i < nb; ++i) {
+      const int j = (r - i + nb) % nb;
+      if (j <= i) continue;
+      pr[2 * k] = i;
+      pr[2 * k + 1] = j;
+      ++k;
+    }
+    if (r % 2 == 0) {
+      pr[2 * k] = r / 2;
+      pr[2 * k + 1] = r / 2 + np;
+      ++k;
+    }
+    if (k != np) return LYAP_BADARG;  // not reached: every round holds np pairs
+    for (k = 0; k < np; ++k)
+      for (int h = 0; h < 2; ++h) bmap[(size_t)r * nb + pr[2 * k + h]] = 2 * k + h;
+  }
+  return LYAP_OK;
+}
+
 size_t syev_workspace_bytes(int p) {
   size_t pp = (size_t)ceil_div(p, SB) * SB;
   size_t nb = pp / HB, np = nb / 2;
@@ -649,32 +681,8 @@ int syev_t(hipStream_t s, int p, const double* H, long ldh, double* w, double* V
     return LYAP_NO_MEMORY;
   if (tol_rel <= 0.0) tol_rel = 1e-15;
   const double eps = relative ? tol_rel : 0.0;
-  // Block pair schedule (modulus ordering): round t rotates the block pairs (i, j), i < j,
-  // with i + j = t mod nb, listed by i.  Every pair appears once in the nb rounds of a sweep,
-  // and the sequence of rounds, sweep after sweep, is the row-cyclic sequence of pairs with
-  // only disjoint (commuting) pairs reordered, so it converges like the row-cyclic ordering.
-  // Even rounds leave blocks t / 2 and t / 2 + nb / 2 idle: they form the last pair of the
-  // round with the identity as rotation.  bmap[t][b] = 2 k + h for block b at half h of
-  // pair k of round t.
   std::vector<int> sched((size_t)rounds * np * 2), bm((size_t)rounds * nb);
-  for (int r = 0; r < rounds; ++r) {
-    int k = 0;
-    for (int i = 0; i < nb; ++i) {
-      const int j = (r - i + nb) % nb;
-      if (j <= i) continue;
-      sched[((size_t)r * np + k) * 2] = i;
-      sched[((size_t)r * np + k) * 2 + 1] = j;
-      ++k;
-    }
-    if (r % 2 == 0) {
-      sched[((size_t)r * np + k) * 2] = r / 2;
-      sched[((size_t)r * np + k) * 2 + 1] = r / 2 + np;
-      ++k;
-    }
-    if (k != np) return LYAP_BADARG;  // not reached: every round holds np pairs
-    for (k = 0; k < np; ++k)
-      for (int h = 0; h < 2; ++h) bm[(size_t)r * nb + sched[((size_t)r * np + k) * 2 + h]] = 2 * k + h;
-  }
+  LYAP_TRY(jacobi_schedule(nb, sched.data(), bm.data()));
   LYAP_HIP(hipMemcpyAsync(pairs, sched.data(), sched.size() * sizeof(int), hipMemcpyHostToDevice,
                           s));
   LYAP_HIP(hipMemcpyAsync(bmap, bm.data(), bm.size() * sizeof(int), hipMemcpyHostToDevice, s));

@@ -66,6 +66,10 @@ int qr_lead(hipStream_t s, int n, int p, int c, double* F, long ldf, double* U, 
 
 // ---- eig.hip
 size_t syev_workspace_bytes(int p);
+// The block-pair schedule of the Jacobi sweeps for nb (even) blocks: pairs[(t np + k) 2 + h]
+// is block h of pair k of round t (np = nb / 2 pairs, nb rounds), bmap[t nb + b] = 2 k + h.
+// Host only.
+int jacobi_schedule(int nb, int* pairs, int* bmap);
 // H = V diag(w) V^T, w sorted by descending |w|.  ``sweeps_out`` (host, optional).
 // Rotations are skipped below tol ||H||_F / (4 p) and, with ``relative``, also below
 // tol sqrt(|h_pp h_qq|) (eigenvalues accurate relative to their own size rather than to
