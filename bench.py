@@ -169,8 +169,8 @@ def main():
                     help="one untimed IR solve and a calibration copy (for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(see DESIGN.md for how the solve would shard).", file=sys.stderr)
+        print("bench.py measures one GPU: the solver has no multi-GPU path; --gpus must be 1.",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -50,7 +50,7 @@ enum {
 typedef enum { LYAP_F64 = 0, LYAP_F32 = 1, LYAP_F16 = 2, LYAP_BF16 = 3 } lyap_dtype;
 
 /* Precisions of Alg 2.1/2.2: solver u_s, working u, residual factorisation u_r and solution
- * update u_c, with u_s >= u >= u_r, u_c.  This build supports u = u_r = u_c = F64 and any
+ * update u_c, with u_s >= u >= u_r, u_c.  The library supports u = u_r = u_c = F64 and any
  * u_s (F64 gives the plain FP64 sign-function Newton solve). */
 typedef struct {
   int u_s, u, u_r, u_c; /* lyap_dtype values */
