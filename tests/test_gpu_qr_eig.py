@@ -76,8 +76,10 @@ def test_qr_rank_deficient(lyap):
     assert np.linalg.norm(U.T @ U - np.eye(F.shape[1])) <= 1e-12
 
 
-@pytest.mark.parametrize("p", [1, 5, 32, 37, 100, 256, 518])
+@pytest.mark.parametrize("p", [1, 5, 32, 37, 100, 256, 518, 2100, 4096])
 def test_syev_indefinite(lyap, p):
+    # graded indefinite spectra as in the truncations (2100: ragged, 66 blocks of 32 with
+    # padding; 4096: the largest size the entry point takes)
     print(f"syev p={p}", flush=True)
     rng = np.random.default_rng(p)
     Q = np.linalg.qr(rng.standard_normal((p, p)))[0]
@@ -94,6 +96,13 @@ def test_syev_indefinite(lyap, p):
     # Jacobi accumulates the block rotations into V: allow 1000 u p (about 6e-11 at p = 518)
     assert np.linalg.norm(V.T @ V - np.eye(p)) <= 1000 * u * p
     assert np.linalg.norm((V * w) @ V.T - H) <= 100 * u * p * nrm
+
+
+def test_syev_rejects_oversize(lyap):
+    print("syev p=4097 (rejected)", flush=True)
+    with pytest.raises(lyap.LyapError) as e:
+        lyap.syev(torch.zeros((4097, 4097), dtype=torch.float64, device="cuda"))
+    assert e.value.status == "BADARG"
 
 
 def test_syev_clustered_and_zero(lyap):
