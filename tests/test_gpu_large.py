@@ -1,6 +1,7 @@
 """Parity at the full size of the n = 4096 workload (lyapgen.config("large"): A = Q T Q^T with
-kappa ~ 1e3, W = L S L^T indefinite, m = 8), in the configuration bench.py times: the
-fp32-inner mixed-precision IR solve and the FP64 sign-function Newton solve.
+kappa ~ 1e3, W = L S L^T indefinite, m = 8), in the configuration bench.py times (the
+fp32-inner mixed-precision IR solve and the FP64 sign-function Newton solve) and with the
+fp16 and bf16 inner solvers.
 
   * The relative residual of eq (4.1), recomputed on the host in float64 by the oracle from
     the returned factors, is <= 1e-13 and agrees with the one the library reports.
@@ -43,8 +44,11 @@ def large():
     return cfg, gold
 
 
-@pytest.mark.parametrize("prec", [("fp32", "fp64", "fp64", "fp64"), ("fp64",) * 4],
-                         ids=["ir_fp32_inner", "fp64_sign_newton"])
+@pytest.mark.parametrize("prec", [("fp32", "fp64", "fp64", "fp64"), ("fp64",) * 4,
+                                  ("fp16", "fp64", "fp64", "fp64"),
+                                  ("bf16", "fp64", "fp64", "fp64")],
+                         ids=["ir_fp32_inner", "fp64_sign_newton", "ir_fp16_inner",
+                              "ir_bf16_inner"])
 def test_large_workload_parity(lyap, large, prec):
     cfg, gold = large
     A, L, S = cfg["A"], cfg["L"], cfg["S"]
