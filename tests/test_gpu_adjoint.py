@@ -90,11 +90,12 @@ def test_trace_loss_gradients_match_oracle(lyap, prec, with_s):
         assert np.linalg.norm(g - want) <= 1e-9 * np.linalg.norm(want)
 
 
-def test_trace_loss_gradient_n2048_central_differences(lyap):
-    print("trace loss grad n=2048 fp32-inner IR vs central differences", flush=True)
+@pytest.mark.parametrize("us", ["fp32", "fp16"])
+def test_trace_loss_gradient_n2048_central_differences(lyap, us):
+    print(f"trace loss grad n=2048 {us}-inner IR vs central differences", flush=True)
     cfg = lyapgen.config("grad")
     A, L, C = cfg["A"], cfg["L"], cfg["C"]
-    prec = ("fp32", "fp64", "fp64", "fp64")
+    prec = (us, "fp64", "fp64", "fp64")
     At = _cuda(A).requires_grad_(True)
     Lt = _cuda(L).requires_grad_(True)
     loss = lyap.lyapunov_trace_loss(At, Lt, None, _cuda(C), prec)
