@@ -11,6 +11,7 @@ do not reach it is reported as DNF.  Prints one JSON line.
 
   python bench.py [--steps K] [--warmup W] [--us fp32] [--skip-cpu] [--batched]
   python bench.py --traffic-run   (one IR solve and a calibration copy, for HBM counters)
+  python bench.py --mfma-run [--us fp64]   (one solve and calibration products, for MFMA counters)
 """
 from __future__ import annotations
 
@@ -110,6 +111,23 @@ def _traffic_run(lyap, torch, A, L, S, us):
     print("calibration copy bytes", x.numel() * 8, flush=True)
 
 
+def _mfma_run(lyap, torch, A, L, S, us):
+    """Untimed: one solve at inner precision ``us``, then one FP64 and one FP32 product of
+    4096^3 (torch.matmul, 137.4 GFLOP each) whose MFMA op counters give the counters' unit.
+    Run under ``rocprofv3 --pmc SQ_INSTS_VALU_MFMA_MOPS_F64 SQ_INSTS_VALU_MFMA_MOPS_F32 ...
+    --kernel-trace``."""
+    _, _, info = lyap.solve(A, L, S, precisions=(us, "fp64", "fp64", "fp64"),
+                            raise_on_error=False)
+    torch.cuda.synchronize()
+    print("solve", us, info["status"], info["res"], "inversion flops", info["kern_work"][0],
+          "inversions", info["kern_calls"][0], flush=True)
+    for dt in (torch.float64, torch.float32):
+        a = torch.ones((4096, 4096), dtype=dt, device="cuda")
+        c = torch.matmul(a, a)
+        torch.cuda.synchronize()
+        print("calibration matmul", dt, "flops", 2 * 4096 ** 3, float(c[0, 0]), flush=True)
+
+
 def _measured_traffic(kernel):
     """HBM bytes per launch of ``kernel`` from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
     summary, or None when there is none or the kernel's source changed since it was taken."""
@@ -167,6 +185,8 @@ def main():
                     help="also time 256 independent equations, n in [64, 512] (batched mode)")
     ap.add_argument("--traffic-run", action="store_true",
                     help="one untimed IR solve and a calibration copy (for HBM counters)")
+    ap.add_argument("--mfma-run", action="store_true",
+                    help="one untimed solve and calibration products (for MFMA counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the solver has no multi-GPU path; --gpus must be 1.",
@@ -186,6 +206,9 @@ def main():
     n = A.shape[0]
     if args.traffic_run:
         _traffic_run(lyap, torch, A, L, S, args.us)
+        return
+    if args.mfma_run:
+        _mfma_run(lyap, torch, A, L, S, args.us)
         return
 
     # plain FP64 sign-function Newton solve (the baseline), then mixed-precision IR
