@@ -82,11 +82,19 @@ __global__ void k_sumsq_partial(int rows, int cols, const double* __restrict__ A
   __shared__ double red[RB];
   double acc = 0.0;
   if (cols >= RB / 4) {
-    // rows strided over blocks, columns over threads (coalesced, no index division)
+    // rows strided over blocks, columns over threads (coalesced, no index division); four
+    // independent accumulators keep several loads in flight per thread
+    double acc4[4] = {0.0, 0.0, 0.0, 0.0};
     for (int i = blockIdx.x; i < rows; i += gridDim.x) {
       const double* a = A + (long)i * lda;
-      for (int j = threadIdx.x; j < cols; j += RB) acc += a[j] * a[j];
+      int j = threadIdx.x;
+      for (; j + 3 * RB < cols; j += 4 * RB) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc4[u] += a[j + u * RB] * a[j + u * RB];
+      }
+      for (; j < cols; j += RB) acc4[0] += a[j] * a[j];
     }
+    acc = (acc4[0] + acc4[1]) + (acc4[2] + acc4[3]);
   } else {
     long total = (long)rows * cols;
     for (long e = (long)blockIdx.x * RB + threadIdx.x; e < total; e += (long)gridDim.x * RB) {
@@ -274,8 +282,10 @@ int cast_store(hipStream_t s, Store st, int rows, int cols, const double* src, l
 
 int sumsq(hipStream_t s, int rows, int cols, const double* A, long lda, double* out,
           double* partial) {
-  hipLaunchKernelGGL(k_sumsq_partial, dim3(RPARTS), dim3(RB), 0, s, rows, cols, A, lda, partial);
-  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(RB), 0, s, RPARTS, partial, out);
+  // a large matrix takes four workgroups per CU so that enough loads are in flight
+  const int nparts = rows >= 4 * RPARTS ? 4 * RPARTS : RPARTS;
+  hipLaunchKernelGGL(k_sumsq_partial, dim3(nparts), dim3(RB), 0, s, rows, cols, A, lda, partial);
+  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(RB), 0, s, nparts, partial, out);
   LYAP_HIP(hipGetLastError());
   return LYAP_OK;
 }

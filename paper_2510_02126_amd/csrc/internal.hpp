@@ -26,7 +26,7 @@ int cast_store(hipStream_t s, Store st, int rows, int cols, const double* src, l
                void* dst);
 // sum of squares of a rows x cols FP64 block into out[0] (deterministic two-stage).
 int sumsq(hipStream_t s, int rows, int cols, const double* A, long lda, double* out,
-          double* partial /* >= 256 doubles */);
+          double* partial /* >= 256 doubles, >= 1024 when rows >= 1024 */);
 // Newton update: Anew = 0.5 (mu A + Ainv / mu), mu = mu_dev[0]; accumulates into out4:
 // out4[0] = ||Anew - A||_F^2, out4[1] = ||Anew||_F^2, out4[2] = ||Anew + I||_1.
 // colsum must hold n doubles, partial >= 3*256 doubles.

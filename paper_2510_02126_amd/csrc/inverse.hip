@@ -44,21 +44,32 @@ template <> struct LeafWidth<double> { static constexpr int v = 8; };
 template <> struct LeafWidth<float> { static constexpr int v = 8; };
 
 // ---------------------------------------------------------------- prescale and copy
-// Block b scans rows b, b + gridDim.x, ...; NaN anywhere poisons the partial.
+// Block b scans rows b, b + gridDim.x, ...; NaN anywhere poisons the partial.  Four
+// independent maxima keep several loads in flight per thread.
 __global__ void absmax_partial(int n, const double* __restrict__ A, long lda,
                                double* __restrict__ part) {
   __shared__ double red[256];
   __shared__ int rnan[256];
-  double m = 0.0;
+  double m4[4] = {0.0, 0.0, 0.0, 0.0};
   int nan = 0;
   for (int i = blockIdx.x; i < n; i += gridDim.x) {
     const double* a = A + (long)i * lda;
-    for (int j = threadIdx.x; j < n; j += 256) {
+    int j = threadIdx.x;
+    for (; j + 3 * 256 < n; j += 4 * 256) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double v = fabs(a[j + u * 256]);
+        if (v != v) nan = 1;
+        else m4[u] = fmax(m4[u], v);
+      }
+    }
+    for (; j < n; j += 256) {
       const double v = fabs(a[j]);
       if (v != v) nan = 1;
-      else m = fmax(m, v);
+      else m4[0] = fmax(m4[0], v);
     }
   }
+  const double m = fmax(fmax(m4[0], m4[1]), fmax(m4[2], m4[3]));
   red[threadIdx.x] = m;
   rnan[threadIdx.x] = nan;
   __syncthreads();
@@ -72,20 +83,37 @@ __global__ void absmax_partial(int n, const double* __restrict__ A, long lda,
   if (threadIdx.x == 0) part[blockIdx.x] = rnan[0] ? NAN : red[0];
 }
 
-// Reduce the partial maxima and derive e with 2^(e-1) <= max < 2^e (0 when max == 0).
-__global__ void absmax_exponent(int nparts, const double* __restrict__ part, int* __restrict__ e,
-                                int* __restrict__ bad) {
+// Reduce the partial maxima (one workgroup of 256) and derive e with 2^(e-1) <= max < 2^e
+// (0 when max == 0).
+__global__ __launch_bounds__(256) void absmax_exponent(int nparts, const double* __restrict__ part,
+                                                       int* __restrict__ e,
+                                                       int* __restrict__ bad) {
+  __shared__ double red[256];
+  __shared__ int rnan[256];
   double m = 0.0;
-  bool nan = false;
-  for (int i = 0; i < nparts; ++i) {
-    double v = part[i];
-    if (v != v) nan = true;
+  int nan = 0;
+  for (int i = threadIdx.x; i < nparts; i += 256) {
+    const double v = part[i];
+    if (v != v) nan = 1;
     else m = fmax(m, v);
   }
-  int ex = 0;
-  if (m > 0.0 && !isinf(m)) frexp(m, &ex);
-  *e = ex;
-  if (nan || isinf(m)) *bad = 1;
+  red[threadIdx.x] = m;
+  rnan[threadIdx.x] = nan;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+      rnan[threadIdx.x] |= rnan[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double mx = red[0];
+    int ex = 0;
+    if (mx > 0.0 && !isinf(mx)) frexp(mx, &ex);
+    *e = ex;
+    if (rnan[0] || isinf(mx)) *bad = 1;
+  }
 }
 
 // WT[j][i] = (T)(2^-e A[i][j]) through a TT x TT LDS tile; blocks of the first tile row also
@@ -502,13 +530,13 @@ int invert_t(hipStream_t s, Prec op, int n, const double* A, long lda, double* o
   int* used = ws.take<int>(n);
   int* piv = ws.take<int>(n);
   int* ex = ws.take<int>(1);
-  int nparts = 256;
+  const int nparts = n >= 1024 ? 1024 : 256;  // four workgroups per CU for a large matrix
   double* part = ws.take<double>(nparts);
   if (!WT || !RT || !Dinv || !used || !piv || !ex || !part) return LYAP_NO_MEMORY;
   const bool scale = !std::is_same<T, double>::value;
   const dim3 tiles((unsigned)ceil_div(n, TT), (unsigned)ceil_div(n, TT));
   hipLaunchKernelGGL(absmax_partial, dim3(nparts), dim3(256), 0, s, n, A, lda, part);
-  hipLaunchKernelGGL(absmax_exponent, dim3(1), dim3(1), 0, s, nparts, part, ex, flags_dev + 1);
+  hipLaunchKernelGGL(absmax_exponent, dim3(1), dim3(256), 0, s, nparts, part, ex, flags_dev + 1);
   hipLaunchKernelGGL((load_transposed<T>), tiles, dim3(256), 0, s, n, A, lda, ex, scale, WT, used);
   LYAP_HIP(hipGetLastError());
   Inv<T> inv{s, n, WT, RT, Dinv, used, piv, flags_dev + 0, op, pivot};
@@ -525,7 +553,7 @@ size_t inverse_workspace_bytes(Prec op, int n) {
   size_t el = op == Prec::F64 ? 8 : 4;
   size_t half = (size_t)((n + 1) / 2 + WN);
   return (size_t)n * n * el + half * half * el + (size_t)WN * WN * el + 4 * (size_t)n * 4 +
-         256 * 8 + 10 * 256;
+         1024 * 8 + 10 * 256;
 }
 
 // flags_dev[0] = singular pivot seen, flags_dev[1] = non-finite input/output (device ints,
