@@ -306,7 +306,9 @@ __device__ inline f64x4 mfma_f64(double a, double b, f64x4 c) {
 // Y = V^T X, Y <- op(Tw) Y, X <- X - V Y, all on the FP64 matrix cores with the operands of
 // V and X loaded from memory straight into the matrix-core lanes.  For Y each wave sums all
 // four 16 x 16 tiles over a quarter of the rows and the four partial sums are added in a
-// fixed order in LDS; for the update each wave takes every fourth 16-row tile.
+// fixed order in LDS; the update then covers the same quarter of the rows, whose X entries
+// each lane still holds in registers from the first product (lane (r, k) of step m loaded row
+// 4 m + k of the quarter, which is where the update's result lands), so X is read once.
 template <bool STACK>
 __global__ __launch_bounds__(NTH) void apply_wy(int nr, int nch, bool trans,
                                                 const double* __restrict__ Vsrc,
@@ -327,21 +329,28 @@ __global__ __launch_bounds__(NTH) void apply_wy(int nr, int nch, bool trans,
   };
   const bool col0 = c0 + lr < ncols, col1 = c0 + 16 + lr < ncols;
   // Y partial over rows [i0, i1) of this wave
+  constexpr int MX = (STACK ? MAXCH * PB : CH) / 16;  // most 4-row steps of a quarter
   const int rpw = (((rows + 3) / 4 + 3) / 4) * 4;  // a quarter of the rows, a multiple of 4
   const int i0 = wave * rpw, i1 = min(rows, i0 + rpw);
   f64x4 y00 = {0.0, 0.0, 0.0, 0.0}, y01 = y00, y10 = y00, y11 = y00;
-#pragma unroll 4
-  for (int k0 = i0; k0 < i1; k0 += 4) {
-    const int i = k0 + lk;
-    const int g = i < i1 ? xrow(i) : -1;
-    const double v0 = i < i1 ? V[(long)i * PB + lr] : 0.0;
-    const double v1 = i < i1 ? V[(long)i * PB + 16 + lr] : 0.0;
-    const double x0 = (g >= 0 && col0) ? X[(long)g * ldx + c0 + lr] : 0.0;
-    const double x1 = (g >= 0 && col1) ? X[(long)g * ldx + c0 + 16 + lr] : 0.0;
-    y00 = mfma_f64(v0, x0, y00);
-    y01 = mfma_f64(v0, x1, y01);
-    y10 = mfma_f64(v1, x0, y10);
-    y11 = mfma_f64(v1, x1, y11);
+  double xs0[MX], xs1[MX];  // X entries of this lane's rows, kept for the update
+#pragma unroll
+  for (int m = 0; m < MX; ++m) {
+    const int k0 = i0 + 4 * m;
+    xs0[m] = 0.0;
+    xs1[m] = 0.0;
+    if (k0 < i1) {  // uniform across the wave
+      const int i = k0 + lk;
+      const int g = i < i1 ? xrow(i) : -1;
+      const double v0 = i < i1 ? V[(long)i * PB + lr] : 0.0;
+      const double v1 = i < i1 ? V[(long)i * PB + 16 + lr] : 0.0;
+      xs0[m] = (g >= 0 && col0) ? X[(long)g * ldx + c0 + lr] : 0.0;
+      xs1[m] = (g >= 0 && col1) ? X[(long)g * ldx + c0 + 16 + lr] : 0.0;
+      y00 = mfma_f64(v0, xs0[m], y00);
+      y01 = mfma_f64(v0, xs1[m], y01);
+      y10 = mfma_f64(v1, xs0[m], y10);
+      y11 = mfma_f64(v1, xs1[m], y11);
+    }
   }
   // D layout (FP64 16x16x4): lane l, register i -> row 4 i + l / 16, column l % 16
 #pragma unroll
@@ -368,24 +377,29 @@ __global__ __launch_bounds__(NTH) void apply_wy(int nr, int nch, bool trans,
 #pragma unroll
   for (int i = 0; i < 4; ++i) Yp[1][16 * ti + 4 * i + lk][16 * tj + lr] = y2[i];
   __syncthreads();
-  // X <- X - V Y2, 16-row tiles
-  for (int r0 = 16 * wave; r0 < rows; r0 += 64) {
-    double vt[PB / 4];
+  // X <- X - V Y2 on this wave's rows [i0, i1), 16-row tiles; result row r0 + 4 i + k of
+  // lane (r, k) is row 4 (4 t + i) + k of the quarter, held in xs*[4 t + i]
 #pragma unroll
-    for (int q = 0; q < PB / 4; ++q)
-      vt[q] = r0 + lr < rows ? V[(long)(r0 + lr) * PB + 4 * q + lk] : 0.0;
+  for (int tt = 0; tt < MX / 4; ++tt) {
+    const int r0 = i0 + 16 * tt;
+    if (r0 < i1) {  // uniform across the wave
+      double vt[PB / 4];
 #pragma unroll
-    for (int cj = 0; cj < 2; ++cj) {
-      f64x4 u = {0.0, 0.0, 0.0, 0.0};
+      for (int q = 0; q < PB / 4; ++q)
+        vt[q] = r0 + lr < rows ? V[(long)(r0 + lr) * PB + 4 * q + lk] : 0.0;
 #pragma unroll
-      for (int q = 0; q < PB / 4; ++q) u = mfma_f64(vt[q], Yp[1][4 * q + lk][16 * cj + lr], u);
-      const bool cok = cj == 0 ? col0 : col1;
+      for (int cj = 0; cj < 2; ++cj) {
+        f64x4 u = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int g = xrow(r0 + 4 * i + lk);
-        if (g >= 0 && cok) {
-          double* px = X + (long)g * ldx + c0 + 16 * cj + lr;
-          *px = *px - u[i];
+        for (int q = 0; q < PB / 4; ++q)
+          u = mfma_f64(vt[q], Yp[1][4 * q + lk][16 * cj + lr], u);
+        const bool cok = cj == 0 ? col0 : col1;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int row = r0 + 4 * i + lk;
+          const int g = row < i1 ? xrow(row) : -1;
+          if (g >= 0 && cok)
+            X[(long)g * ldx + c0 + 16 * cj + lr] = (cj == 0 ? xs0[4 * tt + i] : xs1[4 * tt + i]) - u[i];
         }
       }
     }
