@@ -208,11 +208,15 @@ __device__ inline void wave_argmax(T& best, int& brow) {
   brow = r;
 }
 
+// With gv > 0 the leaf also does the gather of the block update that follows it,
+// W[piv[c0..c0+wc), gc..gc+gv) -> RT (gv x wc) with those entries of W set to zero: they lie
+// in columns the leaf does not touch, at rows it has just chosen as pivots.
 template <class T, int RPT, int WC>
 __global__ __launch_bounds__(LEAF_THREADS) void gj_leaf(int n, T* __restrict__ WT, int c0, int wc,
                                                          int* __restrict__ used,
                                                          int* __restrict__ piv,
-                                                         int* __restrict__ sing) {
+                                                         int* __restrict__ sing, int gc, int gv,
+                                                         T* __restrict__ RT) {
   constexpr int NW = LEAF_THREADS / 64;
   __shared__ T crow[2][NW][WC];  // per-wave candidate rows, double-buffered by column parity
   __shared__ T cval[2][NW];
@@ -295,6 +299,12 @@ __global__ __launch_bounds__(LEAF_THREADS) void gj_leaf(int n, T* __restrict__ W
   }
   __syncthreads();  // lpiv complete
   if (t < wc) piv[c0 + t] = lpiv[t];
+  if (t < gv * wc) {
+    const int j = t / wc, k = t % wc;
+    T* src = WT + (long)(gc + j) * n + lpiv[k];
+    RT[t] = *src;
+    *src = (T)0;
+  }
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
     const int row = t + LEAF_THREADS * r;
@@ -463,7 +473,8 @@ template <class T> struct Inv {
 
   int leaf_width() const { return pivot ? LeafWidth<T>::v : WN; }
 
-  int leaf(int c0, int wc) {
+  // gc / gv: columns of the update that follows, whose gather the pivoted leaf does itself
+  int leaf(int c0, int wc, int gc = 0, int gv = 0) {
     if (!pivot) {
       hipLaunchKernelGGL((nop_diag<T>), dim3(1), dim3(256), 0, s, n, WT, c0, wc, Dinv, used, piv,
                          sing);
@@ -476,7 +487,7 @@ template <class T> struct Inv {
     const int rpt = ceil_div(n, LEAF_THREADS);
 #define LEAF(RPT)                                                                          \
   hipLaunchKernelGGL((gj_leaf<T, RPT, WC>), dim3(1), dim3(LEAF_THREADS), 0, s, n, WT, c0, wc, \
-                     used, piv, sing)
+                     used, piv, sing, gc, gv, RT)
     if (rpt <= 1) LEAF(1);
     else if (rpt <= 2) LEAF(2);
     else if (rpt <= 4) LEAF(4);
@@ -487,13 +498,16 @@ template <class T> struct Inv {
     return LYAP_OK;
   }
 
-  // WT[c:d, :] += RT WT[a:b, :] with RT (d-c) x (b-a) gathered from the pivot rows.
-  int update(int a, int b, int c, int d) {
+  // WT[c:d, :] += RT WT[a:b, :] with RT (d-c) x (b-a) gathered from the pivot rows (here, or
+  // by the leaf just before when ``gathered``).
+  int update(int a, int b, int c, int d, bool gathered = false) {
     int w = b - a, v = d - c;
     long total = (long)w * v;
-    hipLaunchKernelGGL((gather_zero<T>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
-                       n, WT, piv, a, w, c, v, RT);
-    LYAP_HIP(hipGetLastError());
+    if (!gathered) {
+      hipLaunchKernelGGL((gather_zero<T>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
+                         s, n, WT, piv, a, w, c, v, RT);
+      LYAP_HIP(hipGetLastError());
+    }
     GemmDesc g;
     g.M = v; g.N = n; g.K = w;
     g.alpha = 1.0; g.beta = 1.0;
@@ -511,6 +525,14 @@ template <class T> struct Inv {
     int half = ceil_div(ceil_div(w, 2), lw) * lw;
     int mid = c0 + half;
     if (mid >= c1) mid = c1 - lw;
+    if (pivot && mid - c0 <= lw && c1 - mid <= lw) {
+      // two pivoted leaves: each does the gather of the update after it
+      LYAP_TRY(leaf(c0, mid - c0, mid, c1 - mid));
+      LYAP_TRY(update(c0, mid, mid, c1, true));
+      LYAP_TRY(leaf(mid, c1 - mid, c0, mid - c0));
+      LYAP_TRY(update(mid, c1, c0, mid, true));
+      return LYAP_OK;
+    }
     LYAP_TRY(rec(c0, mid));
     LYAP_TRY(update(c0, mid, mid, c1));
     LYAP_TRY(rec(mid, c1));
