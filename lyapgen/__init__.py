@@ -13,8 +13,8 @@ unstated seed and the SLICOT collection, neither of which is reproduced here):
   diag(T) = -logspace(lo, 0, n), strict upper entries N(0, (s/sqrt n)^2) with s = 0.1
   (s = 0.003 for the n = 4096 workload, see _cfg_large).  The Schur form is returned so
   the oracle can solve on it directly.
-* ``paper_family``   -- the synthetic family of the paper's Section 4.1: a symmetric
-  orthogonal sine matrix V (the "orthog" type-1 matrix) and A = -V diag(logspace(0,q,n)) V^T,
+* ``paper_family``   -- the synthetic family of the paper's Section 4.1: symmetric A with a
+  log-spaced spectrum from -1 to -10^q in the eigenbasis of the symmetric sine matrix,
   L ~ N(0, 1) with m = 3 columns.
 * ``batch_family``   -- many independent random_shift instances of uneven n and m.
 """
@@ -79,13 +79,15 @@ def sine_orthogonal(n: int) -> np.ndarray:
 
 
 def paper_family(n: int, q: float, m: int = 3, seed: int = 0):
-    """Section 4.1 synthetic family: A = -V diag(logspace(0, q, n)) V^T (symmetric,
-    kappa(L) ~ 10^q), L ~ N(0,1) n x m.  Returns (A, L)."""
-    v = sine_orthogonal(n)
-    a = -(v * np.logspace(0.0, q, n)[None, :]) @ v.T
-    a = 0.5 * (a + a.T)
-    rng = np.random.default_rng(seed)
-    l = rng.standard_normal((n, m))
+    """Section 4.1 family: a symmetric negative definite A with condition number 10^q, its
+    eigenvalues -1 .. -10^q spaced evenly in log scale and its eigenvectors the columns of
+    the symmetric orthogonal sine matrix, so kappa_F of the Lyapunov operator is about 10^q;
+    L has m independent N(0, 1) columns.  Returns (A, L)."""
+    lam = -(10.0 ** np.linspace(0.0, q, n))       # spectrum of A
+    basis = sine_orthogonal(n)                     # orthonormal eigenvectors (columns)
+    a = (basis * lam[None, :]) @ basis.T           # sum_k lam_k v_k v_k^T
+    a = 0.5 * (a + a.T)                            # exactly symmetric in floating point
+    l = np.random.default_rng(seed).standard_normal((n, m))
     return a, l
 
 

@@ -9,6 +9,13 @@ the elementwise "chop" model the paper used to simulate bf16 (Section 4).
 fp16 uses NumPy's IEEE binary16 conversion.  bf16 (8 significand bits, binary32's
 exponent range) is rounded by ``round_to_format``, written here from the format's
 definition; the pins test it against independent library conversions.
+
+Range (fp16's x_max = 65504, Table 1.1): values held at a reduced solver precision are
+stored as a power of two times a value of the format (``fl_scaled``): the scale is chosen
+per array (or per column) so that the largest magnitude lies in [1/2, 1), which is exact in
+binary arithmetic and keeps large iterates, inverses and products out of overflow.  This is
+the reading taken for the paper's silence on fp16 range (its half precision was bf16, which
+has binary32's range); products take their operands this way and accumulate in binary32.
 """
 from __future__ import annotations
 
@@ -77,12 +84,56 @@ def fl(x, fmt: str) -> np.ndarray:
     raise ValueError(f"unknown format {fmt!r}")
 
 
+def pow2_exponent(amax) -> np.ndarray:
+    """e with 2^(e-1) <= amax < 2^e (elementwise; 0 where amax is 0 or not finite)."""
+    amax = np.asarray(amax, np.float64)
+    ok = np.isfinite(amax) & (amax > 0)
+    _, e = np.frexp(np.where(ok, amax, 1.0))
+    return np.where(ok, e, 0).astype(np.int64)
+
+
+def _scale_exponents(x, axis):
+    """Per-array (axis None) or per-column (axis 0) exponents of the largest magnitude."""
+    if x.size == 0:
+        return np.zeros(() if axis is None else x.shape[1], np.int64)
+    if axis is None:
+        return pow2_exponent(np.max(np.abs(x)))
+    return pow2_exponent(np.max(np.abs(x), axis=0))
+
+
+def fl_scaled(x, fmt: str, axis=None) -> np.ndarray:
+    """Round to ``fmt`` with a power-of-two scale: 2^e fl(2^-e x), where 2^-e maps the largest
+    magnitude of the array (axis None) or of each column (axis 0) into [1/2, 1).  The same as
+    ``fl`` inside the format's range apart from where gradual underflow starts; never
+    overflows for finite x.  fp64 and fp32 are rounded plainly (their range is not at issue
+    here).  Non-finite arrays are rounded plainly so that inf / NaN propagate."""
+    x = np.asarray(x, dtype=np.float64)
+    if fmt in ("fp64", "fp32") or x.size == 0 or not np.all(np.isfinite(x)):
+        return fl(x, fmt)
+    e = _scale_exponents(x, axis)
+    return np.ldexp(fl(np.ldexp(x, -e), fmt), e)
+
+
 def matmul(a, b, fmt: str) -> np.ndarray:
     """Product at precision ``fmt``: operands rounded to ``fmt``; for the reduced formats
     the products are accumulated in binary32 and the result is rounded to ``fmt`` (operands
-    at the solver precision, binary32 accumulation); fp64 is a plain float64 product."""
+    at the solver precision, binary32 accumulation); fp64 is a plain float64 product.
+    For fp16 / bf16 the left operand is taken with one power-of-two scale and the right one
+    with one per column (``fl_scaled``); the exact scales are applied to the binary32 sums."""
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
     if fmt == "fp64":
-        return np.asarray(a, np.float64) @ np.asarray(b, np.float64)
-    a32 = fl(a, fmt).astype(np.float32)
-    b32 = fl(b, fmt).astype(np.float32)
-    return fl((a32 @ b32).astype(np.float64), fmt)
+        return a @ b
+    if fmt == "fp32":
+        a32 = fl(a, fmt).astype(np.float32)
+        b32 = fl(b, fmt).astype(np.float32)
+        return fl((a32 @ b32).astype(np.float64), fmt)
+    if not (np.all(np.isfinite(a)) and np.all(np.isfinite(b))):
+        with np.errstate(invalid="ignore", over="ignore"):
+            return fl(fl(a, fmt) @ fl(b, fmt), fmt)
+    ea = _scale_exponents(a, None)
+    eb = _scale_exponents(b, 0) if b.ndim == 2 else _scale_exponents(b[:, None], 0)[0]
+    a32 = fl(np.ldexp(a, -ea), fmt).astype(np.float32)
+    b32 = fl(np.ldexp(b, -eb), fmt).astype(np.float32)
+    prod = np.ldexp((a32 @ b32).astype(np.float64), ea + eb)
+    return fl_scaled(prod, fmt, axis=0 if prod.ndim == 2 else None)

@@ -38,7 +38,7 @@ from dataclasses import dataclass, field
 import numpy as np
 import scipy.linalg as sla
 
-from .precision import fl, unit_roundoff
+from .precision import fl, fl_scaled, unit_roundoff
 from .signnewton import a_sequence, sign_newton_chol, sign_newton_ldlt
 
 
@@ -158,6 +158,16 @@ def _prep_S(L, S):
     return np.asarray(L, np.float64) @ Qs, s, bool(np.all(s >= 0))
 
 
+def stagnated(res_hist, theta: float = 0.9) -> bool:
+    """The early stop of eq (4.2): with theta_i = res_i / res_{i-1}, refinement is stopped once
+    theta_i > theta for two consecutive steps, i.e. the last two ratios of ``res_hist`` (the
+    residuals res_0, res_1, ... of the iterates so far) both exceed ``theta``."""
+    h = list(res_hist)
+    if len(h) < 3:
+        return False
+    return h[-1] > theta * h[-2] and h[-2] > theta * h[-3]
+
+
 def _pow2_exponent(x: float) -> int:
     """e with 2^(e-1) <= x < 2^e (x > 0)."""
     return math.frexp(x)[1]
@@ -195,8 +205,7 @@ def ir_ldlt(A, L, S=None, prec=("fp32", "fp64", "fp64", "fp64"), tol: float = 1e
         if not refine:
             info.status = "NOT_CONVERGED"
             break
-        h = info.res_hist
-        if len(h) >= 3 and h[-1] / h[-2] > theta and h[-2] / h[-3] > theta:
+        if stagnated(info.res_hist, theta):
             info.status = "STAGNATED"
             break
         if i == i_max:
@@ -205,7 +214,7 @@ def ir_ldlt(A, L, S=None, prec=("fp32", "fp64", "fp64", "fp64"), tol: float = 1e
         # scale the correction's right-hand side by a power of two (linearity)
         e = _pow2_exponent(float(np.max(np.abs(sd))))
         sd_s = fl(np.ldexp(sd, -e), us)
-        Zd, Yd, _, _ = sign_newton_ldlt(A, fl(Ld, us), sd_s, us, psd=False, rho=rho, seq=seq)
+        Zd, Yd, _, _ = sign_newton_ldlt(A, fl_scaled(Ld, us, axis=0), sd_s, us, psd=False, rho=rho, seq=seq)
         Zd, Yd = fl(Zd, u), np.ldexp(fl(Yd, u), e)
         info.newton_total += seq.K
         info.refinements += 1
@@ -245,8 +254,7 @@ def ir_chol(A, L, prec=("fp32", "fp64", "fp64", "fp64"), tol: float = 1e-13,
         if not refine:
             info.status = "NOT_CONVERGED"
             break
-        h = info.res_hist
-        if len(h) >= 3 and h[-1] / h[-2] > theta and h[-2] / h[-3] > theta:
+        if stagnated(info.res_hist, theta):
             info.status = "STAGNATED"
             break
         if i == i_max:
@@ -260,7 +268,7 @@ def ir_chol(A, L, prec=("fp32", "fp64", "fp64", "fp64"), tol: float = 1e-13,
             if Lx.shape[1] == 0:
                 outs.append(np.zeros((A.shape[0], 0)))
                 continue
-            Zx, _, _ = sign_newton_chol(A, fl(np.ldexp(Lx, -e), us), us, rho=rho, seq=seq)
+            Zx, _, _ = sign_newton_chol(A, fl_scaled(np.ldexp(Lx, -e), us, axis=0), us, rho=rho, seq=seq)
             outs.append(np.ldexp(fl(Zx, u), e))
         info.newton_total += seq.K
         info.refinements += 1

@@ -25,7 +25,12 @@ are stored rounded to the format after every matrix-level operation, products ac
 in binary32, and the inverse is computed by Gauss-Jordan elimination with partial pivoting
 in which every stored intermediate is rounded (the elementwise "chop" model the paper used).
 Before each inversion A_k is scaled by a power of two so its largest entry lies in [1/2, 1)
-(exact in binary arithmetic) to keep fp16 in range.  Inside the solver "u" means u_s.
+(exact in binary arithmetic) to keep fp16 in range, and every other value held at fp16 /
+bf16 (iterates A_k, factors Z, the diagonal Y, QR and spectral factors, product operands)
+is stored the same way, as a power of two times a value of the format (``fl_scaled``,
+per column for tall factors and for Y, whose diagonal entries are separate scalars), so
+that no stored value overflows x_max of Table 1.1.
+Inside the solver "u" means u_s.
 
 The A-iteration and the factor iteration are computed one after the other rather than
 interleaved as printed in Alg 3.1/3.2; nothing in the factor iteration feeds back into
@@ -39,7 +44,7 @@ from dataclasses import dataclass, field
 import numpy as np
 import scipy.linalg as sla
 
-from .precision import fl, matmul, unit_roundoff
+from .precision import fl, fl_scaled, matmul, unit_roundoff
 
 
 class NotStableError(RuntimeError):
@@ -98,16 +103,22 @@ def inverse_at(A, fmt: str) -> np.ndarray:
 def thin_qr(M, fmt: str):
     """Householder thin QR (LAPACK) at precision ``fmt``."""
     dt = _lapack_dtype(fmt)
-    q, r = np.linalg.qr(fl(M, fmt).astype(dt), mode="reduced")
-    return fl(q.astype(np.float64), fmt), fl(r.astype(np.float64), fmt)
+    q, r = np.linalg.qr(fl_scaled(M, fmt, axis=0).astype(dt), mode="reduced")
+    return fl_scaled(q.astype(np.float64), fmt), fl_scaled(r.astype(np.float64), fmt)
 
 
 def sym_eig(M, fmt: str):
     """Symmetric spectral decomposition (LAPACK) at precision ``fmt``; ascending."""
     dt = _lapack_dtype(fmt)
-    Ms = fl(0.5 * (M + M.T), fmt).astype(dt)
-    w, v = np.linalg.eigh(Ms)
-    return fl(w.astype(np.float64), fmt), fl(v.astype(np.float64), fmt)
+    Ms = fl_scaled(0.5 * (M + M.T), fmt)
+    if not np.all(np.isfinite(Ms)):
+        raise NonFiniteError("non-finite matrix in the spectral decomposition")
+    # eigh of 2^-e Ms (exact scaling) so that the binary32 LAPACK call sees values in range
+    e = int(np.frexp(np.max(np.abs(Ms)))[1]) if Ms.size and np.any(Ms) else 0
+    w, v = np.linalg.eigh(np.ldexp(Ms, -e).astype(dt))
+    w = np.ldexp(w.astype(np.float64), e)
+    # eigenvalues are separate scalars: each keeps its own power-of-two scale
+    return fl_scaled(w[None, :], fmt, axis=0)[0], fl_scaled(v.astype(np.float64), fmt)
 
 
 # --------------------------------------------------------------------- dense iteration
@@ -150,7 +161,7 @@ def a_sequence(A, fmt: str = "fp64", k_max: int = 50, delta_off: float = 1e-2,
     tau = 10.0 * math.sqrt(n * u) if tau_N is None else tau_N
     I = np.eye(n)
     seq = ASequence(fmt=fmt)
-    Ak = fl(A, fmt)
+    Ak = fl_scaled(A, fmt)
     scaling = True
     countdown = None
     delta_prev = None
@@ -165,7 +176,7 @@ def a_sequence(A, fmt: str = "fp64", k_max: int = 50, delta_off: float = 1e-2,
             mu = math.sqrt(np.linalg.norm(Ainv, "fro") / np.linalg.norm(Ak, "fro"))
         else:
             mu = 1.0
-        Anew = fl(0.5 * (mu * Ak + Ainv / mu), fmt)
+        Anew = fl_scaled(0.5 * (mu * Ak + Ainv / mu), fmt)
         delta = float(np.linalg.norm(Anew - Ak, "fro") / np.linalg.norm(Anew, "fro"))
         onenorm = float(np.linalg.norm(Anew + I, 1))
         seq.inverses.append(Ainv)
@@ -197,7 +208,7 @@ def rank_trunc_chol(Z, fmt: str) -> np.ndarray:
     block such that ||S||_2 <= sqrt(u) ||Z||_2; returns P [T C]^T."""
     u = unit_roundoff(fmt)
     dt = _lapack_dtype(fmt)
-    Zt = fl(Z, fmt).T.astype(dt)
+    Zt = fl_scaled(Z, fmt, axis=0).T.astype(dt)
     _, R, perm = sla.qr(Zt, mode="economic", pivoting=True)
     R = R.astype(np.float64)
     c = R.shape[0]
@@ -215,7 +226,7 @@ def rank_trunc_chol(Z, fmt: str) -> np.ndarray:
     r = max(lo, 1)
     Znew = np.zeros((Z.shape[0], r))
     Znew[perm, :] = R[:r, :].T
-    return fl(Znew, fmt)
+    return fl_scaled(Znew, fmt, axis=0)
 
 
 def rank_trunc_ldlt(Z, Y, fmt: str, psd: bool):
@@ -225,6 +236,8 @@ def rank_trunc_ldlt(Z, Y, fmt: str, psd: bool):
     Q, R = thin_qr(Z, fmt)
     M = matmul(matmul(R, Y, fmt), R.T, fmt)
     lam, V = sym_eig(M, fmt)
+    if not np.all(np.isfinite(lam)):
+        raise NonFiniteError("non-finite eigenvalue in RankTruncLdlt")
     thr = u * float(np.max(np.abs(lam)))          # 1-norm of a diagonal matrix
     keep = lam > thr if psd else np.abs(lam) > thr
     return matmul(Q, V[:, keep], fmt), np.diag(lam[keep])
@@ -247,16 +260,17 @@ def sign_newton_chol(A, L, fmt: str = "fp64", rho: float = 0.1, k_max: int = 50,
     if seq is None:
         seq = a_sequence(A, fmt, k_max)
     cap = math.floor(rho * n)
-    Z = fl(L, fmt)
+    Z = fl_scaled(L, fmt, axis=0)
     cols, ntr = [], 0
     for Ainv, mu in zip(seq.inverses, seq.mus):
         AZ = matmul(Ainv, Z, fmt)
-        Z = fl(np.hstack([math.sqrt(mu / 2.0) * Z, AZ / math.sqrt(2.0 * mu)]), fmt)
+        Z = fl_scaled(np.hstack([math.sqrt(mu / 2.0) * Z, AZ / math.sqrt(2.0 * mu)]), fmt,
+                      axis=0)
         if Z.shape[1] > cap:
             Z = rank_trunc_chol(Z, fmt)
             ntr += 1
         cols.append(Z.shape[1])
-    Z = fl(Z / math.sqrt(2.0), fmt)
+    Z = fl_scaled(Z / math.sqrt(2.0), fmt, axis=0)
     return Z, seq, SolverInfo(seq.K, list(seq.mus), cols, ntr)
 
 
@@ -269,18 +283,18 @@ def sign_newton_ldlt(A, L, S, fmt: str = "fp64", psd: bool = True, rho: float = 
     if seq is None:
         seq = a_sequence(A, fmt, k_max)
     cap = math.floor(rho * n)
-    Z = fl(L, fmt)
+    Z = fl_scaled(L, fmt, axis=0)
     S = np.asarray(S, np.float64)
-    Y = fl(np.diag(S) if S.ndim == 1 else S, fmt)
+    Y = fl_scaled(np.diag(S) if S.ndim == 1 else S, fmt, axis=0)
     cols, ntr = [], 0
     for Ainv, mu in zip(seq.inverses, seq.mus):
         Z = np.hstack([Z, matmul(Ainv, Z, fmt)])
-        Y = fl(0.5 * sla.block_diag(mu * Y, Y / mu), fmt)
+        Y = fl_scaled(0.5 * sla.block_diag(mu * Y, Y / mu), fmt, axis=0)
         if Z.shape[1] > cap:
             Z, Y = rank_trunc_ldlt(Z, Y, fmt, psd)
             ntr += 1
         cols.append(Z.shape[1])
-    Y = fl(Y / 2.0, fmt)
+    Y = fl_scaled(Y / 2.0, fmt, axis=0)
     return Z, Y, seq, SolverInfo(seq.K, list(seq.mus), cols, ntr)
 
 
