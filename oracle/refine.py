@@ -39,7 +39,7 @@ import numpy as np
 import scipy.linalg as sla
 
 from .precision import fl, fl_scaled, unit_roundoff
-from .signnewton import a_sequence, sign_newton_chol, sign_newton_ldlt
+from .signnewton import NonFiniteError, NotStableError, a_sequence, sign_newton_chol, sign_newton_ldlt
 
 
 def _qr(M, fmt):
@@ -134,6 +134,8 @@ class IRInfo:
     refinements: int = 0           # correction solves performed
     rank: int = 0
     mus: list = field(default_factory=list)
+    u_s_final: str = ""            # solver precision of the last stage (escalation)
+    escalations: int = 0
 
     @property
     def res(self) -> float:
@@ -173,13 +175,24 @@ def _pow2_exponent(x: float) -> int:
     return math.frexp(x)[1]
 
 
+def _next_up(fmt: str) -> str:
+    """The next solver precision up in unit roundoff (Table 1.1): bf16, fp16, fp32, fp64."""
+    return {"bf16": "fp16", "fp16": "fp32", "fp32": "fp64"}.get(fmt, "fp64")
+
+
 def ir_ldlt(A, L, S=None, prec=("fp32", "fp64", "fp64", "fp64"), tol: float = 1e-13,
             i_max: int = 50, k_max: int = 50, rho: float = 0.1, eta_r: float = 1e-4,
             eta_s: float | None = None, psd: bool | None = None, theta: float = 0.9,
-            refine: bool = True):
+            refine: bool = True, scaling: str = "frobenius", Z0=None, d0=None,
+            escalate: bool = False):
     """Alg 2.2 with Alg 3.2 as the solver.  ``prec`` = (u_s, u, u_r, u_c).  With
     ``refine=False`` only the first solve is made and its residual evaluated (plain
-    sign-function Newton).  Returns (Z, d, info) with X ~ Z diag(d) Z^T."""
+    sign-function Newton).  ``Z0``, ``d0``: start the refinement from X_0 = Z0 diag(d0) Z0^T
+    instead of a first solve (the first line of Alg 2.2 accepts any starting factor); the
+    inverse sequence is then formed only if a correction is needed.  ``escalate``: a stage
+    that stagnates (eq 4.2), runs out of steps or overflows at u_s continues at the next
+    precision up (Table 1.1 order, not beyond u), from the current iterate when it is valid.
+    Returns (Z, d, info) with X ~ Z diag(d) Z^T."""
     us, u, ur, uc = prec
     A = np.asarray(A, np.float64)
     L, s, psd_auto = _prep_S(L, S)
@@ -188,37 +201,83 @@ def ir_ldlt(A, L, S=None, prec=("fp32", "fp64", "fp64", "fp64"), tol: float = 1e
         eta_s = 10.0 * unit_roundoff(u)
     Sm = np.diag(s)
     info = IRInfo()
-    seq = a_sequence(A, us, k_max)
-    info.inversions = seq.K
-    info.mus = list(seq.mus)
-    Z, Y, _, _ = sign_newton_ldlt(A, L, Sm, us, psd=psd, rho=rho, seq=seq)
-    Z, Y = fl(Z, u), fl(Y, u)
-    info.newton_total = info.newton_max = seq.K
+    info.u_s_final = us
+    info.escalations = 0
     normA = float(np.linalg.norm(A, "fro"))
     normW = _norm_ldlt(L, Sm)
-    for i in range(1, i_max + 1):
-        Ld, sd, normR = res_fac_ldlt(A, L, Sm, Z, Y, eta_r, ur)
-        res = normR / (normW + 2.0 * _norm_ldlt(Z, Y) * normA)
-        info.res_hist.append(res)
-        if res <= tol:
+    seq = None
+    steps_left = i_max
+    if Z0 is not None:
+        Z, Y = fl(np.asarray(Z0, np.float64), u), fl(np.diag(np.asarray(d0, np.float64)), u)
+        fresh = False
+    else:
+        Z = Y = None
+        fresh = True
+    while True:
+        status = "OK"
+        try:
+            if fresh:
+                seq = a_sequence(A, us, k_max, scaling_kind=scaling)
+                info.inversions += seq.K
+                info.mus = list(seq.mus)
+                Z, Y, _, _ = sign_newton_ldlt(A, L, Sm, us, psd=psd, rho=rho, seq=seq)
+                Z, Y = fl(Z, u), fl(Y, u)
+                info.newton_total += seq.K
+                info.newton_max = max(info.newton_max, seq.K)
+            hist = []
+            budget = steps_left
+            for i in range(1, budget + 1):
+                Ld, sd, normR = res_fac_ldlt(A, L, Sm, Z, Y, eta_r, ur)
+                res = normR / (normW + 2.0 * _norm_ldlt(Z, Y) * normA)
+                info.res_hist.append(res)
+                hist.append(res)
+                if not np.isfinite(res):
+                    raise NonFiniteError("non-finite residual")
+                if res <= tol:
+                    break
+                if not refine:
+                    status = "NOT_CONVERGED"
+                    break
+                if stagnated(hist, theta):
+                    status = "STAGNATED"
+                    break
+                if i == budget:
+                    status = "NOT_CONVERGED"
+                    break
+                if seq is None:
+                    seq = a_sequence(A, us, k_max, scaling_kind=scaling)
+                    info.inversions += seq.K
+                    info.mus = list(seq.mus)
+                # scale the correction's right-hand side by a power of two (linearity)
+                e = _pow2_exponent(float(np.max(np.abs(sd))))
+                sd_s = fl(np.ldexp(sd, -e), us)
+                Zd, Yd, _, _ = sign_newton_ldlt(A, fl_scaled(Ld, us, axis=0), sd_s, us, psd=False,
+                                                rho=rho, seq=seq)
+                Zd, Yd = fl(Zd, u), np.ldexp(fl(Yd, u), e)
+                info.newton_total += seq.K
+                info.newton_max = max(info.newton_max, seq.K)
+                info.refinements += 1
+                steps_left -= 1
+                Z, Y = sol_upt_ldlt(Z, Y, Zd, Yd, eta_s, uc, psd)
+        except NonFiniteError:
+            status = "NONFINITE"
+        except NotStableError:
+            status = "NOT_STABLE"
+        except np.linalg.LinAlgError:
+            status = "SINGULAR"
+        info.status = status
+        if not (escalate and refine and status != "OK"
+                and unit_roundoff(us) > unit_roundoff(u)):
             break
-        if not refine:
-            info.status = "NOT_CONVERGED"
-            break
-        if stagnated(info.res_hist, theta):
-            info.status = "STAGNATED"
-            break
-        if i == i_max:
-            info.status = "NOT_CONVERGED"
-            break
-        # scale the correction's right-hand side by a power of two (linearity)
-        e = _pow2_exponent(float(np.max(np.abs(sd))))
-        sd_s = fl(np.ldexp(sd, -e), us)
-        Zd, Yd, _, _ = sign_newton_ldlt(A, fl_scaled(Ld, us, axis=0), sd_s, us, psd=False, rho=rho, seq=seq)
-        Zd, Yd = fl(Zd, u), np.ldexp(fl(Yd, u), e)
-        info.newton_total += seq.K
-        info.refinements += 1
-        Z, Y = sol_upt_ldlt(Z, Y, Zd, Yd, eta_s, uc, psd)
+        valid = status in ("STAGNATED", "NOT_CONVERGED") and Z is not None
+        us = _next_up(us)
+        info.u_s_final = us
+        info.escalations += 1
+        seq = None
+        steps_left = max(1, steps_left)
+        fresh = not valid
+    if Z is None:
+        Z, Y = np.zeros((A.shape[0], 0)), np.zeros((0, 0))
     info.rank = Z.shape[1]
     d = np.diag(Y).copy() if Y.ndim == 2 else Y
     return Z, d, info

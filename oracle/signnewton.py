@@ -5,7 +5,9 @@ Follows Section 3 of the paper:
 * ``dense_iteration``  -- eq (3.1): A_k = (mu A_{k-1} + mu^{-1} A_{k-1}^{-1})/2 and
   W_k = (mu W_{k-1} + mu^{-1} A_{k-1}^{-1} W_{k-1} A_{k-1}^{-T})/2; A_k -> -I, W_k -> 2X.
 * ``a_sequence``       -- the A-iteration alone with Frobenius scaling
-  mu = sqrt(||A^{-1}||_F / ||A||_F), scaling switched off for good once
+  mu = sqrt(||A^{-1}||_F / ||A||_F) (or, as alternatives Section 3 lists, the
+  determinantal |det A|^{-1/n}, the 2-norm sqrt(||A^{-1}||_2 / ||A||_2) or the spectral
+  sqrt(rho(A^{-1}) / rho(A)) scaling; ``scaling_mu``), scaling switched off for good once
   delta_k = ||A_k - A_{k-1}||_F / ||A_k||_F < 1e-2, and the stopping rule (3.4):
   ||A_k + I||_1 <= tau_N = 10 sqrt(n u), or (scaling already off and
   delta_k > delta_{k-1}/2), then two more iterations counting the one that met the test
@@ -152,8 +154,32 @@ class ASequence:
         return len(self.inverses)
 
 
+SCALINGS = ("frobenius", "det", "2norm", "spectral")
+
+
+def scaling_mu(Ak, Ainv, kind: str = "frobenius") -> float:
+    """The scaling parameter mu of a Newton step (Section 3, the list of scalings after eq
+    (3.1)): Frobenius sqrt(||A^-1||_F / ||A||_F); determinantal |det A|^(-1/n) (from the LU
+    factorisation's log-determinant); 2-norm sqrt(||A^-1||_2 / ||A||_2) (singular values);
+    spectral sqrt(rho(A^-1) / rho(A)) (eigenvalues).  All in float64 from the computed
+    A_k and inverse."""
+    n = Ak.shape[0]
+    if kind == "frobenius":
+        return math.sqrt(np.linalg.norm(Ainv, "fro") / np.linalg.norm(Ak, "fro"))
+    if kind == "det":
+        _sign, logdet = np.linalg.slogdet(Ak)
+        return math.exp(-logdet / n)
+    if kind == "2norm":
+        return math.sqrt(np.linalg.norm(Ainv, 2) / np.linalg.norm(Ak, 2))
+    if kind == "spectral":
+        rho = float(np.max(np.abs(np.linalg.eigvals(Ak))))
+        rho_inv = float(np.max(np.abs(np.linalg.eigvals(Ainv))))
+        return math.sqrt(rho_inv / rho)
+    raise ValueError(f"unknown scaling {kind}")
+
+
 def a_sequence(A, fmt: str = "fp64", k_max: int = 50, delta_off: float = 1e-2,
-               tau_N: float | None = None) -> ASequence:
+               tau_N: float | None = None, scaling_kind: str = "frobenius") -> ASequence:
     """Scaled Newton A-iteration with the stopping rule (3.4) and the Section 4 policy."""
     A = np.asarray(A, np.float64)
     n = A.shape[0]
@@ -172,10 +198,9 @@ def a_sequence(A, fmt: str = "fp64", k_max: int = 50, delta_off: float = 1e-2,
             raise np.linalg.LinAlgError(f"singular A_k at k={_k}") from exc
         if not np.all(np.isfinite(Ainv)):
             raise NonFiniteError(f"non-finite inverse at k={_k}")
-        if scaling:
-            mu = math.sqrt(np.linalg.norm(Ainv, "fro") / np.linalg.norm(Ak, "fro"))
-        else:
-            mu = 1.0
+        mu = scaling_mu(Ak, Ainv, scaling_kind) if scaling else 1.0
+        if not (np.isfinite(mu) and mu > 0.0):
+            raise NonFiniteError(f"scaling parameter out of range at k={_k}")
         Anew = fl_scaled(0.5 * (mu * Ak + Ainv / mu), fmt)
         delta = float(np.linalg.norm(Anew - Ak, "fro") / np.linalg.norm(Anew, "fro"))
         onenorm = float(np.linalg.norm(Anew + I, 1))

@@ -126,11 +126,8 @@ def test_ir_working_precision_fp32_limits_residual():
 def test_ir_bf16_beyond_condition_bound_does_not_converge():
     # Table 3.1: bf16 needs kappa_F(L) below about 1e3; far beyond it IR cannot reach 1e-13.
     # Either the bf16 A-iteration itself never meets its stopping test, or refinement stalls.
-    from oracle.signnewton import NonFiniteError, NotStableError
     A, L = lyapgen.paper_family(60, 6.0, seed=3)
-    try:
-        Z, d, info = IR.ir_ldlt(A, L, None, prec=("bf16", "fp64", "fp64", "fp64"), tol=1e-13)
-    except (NotStableError, NonFiniteError):
-        return
-    assert info.status in ("STAGNATED", "NOT_CONVERGED")
-    assert info.res > 1e-13
+    Z, d, info = IR.ir_ldlt(A, L, None, prec=("bf16", "fp64", "fp64", "fp64"), tol=1e-13)
+    assert info.status in ("STAGNATED", "NOT_CONVERGED", "NOT_STABLE", "NONFINITE")
+    if info.res_hist:
+        assert info.res > 1e-13
