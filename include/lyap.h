@@ -1,7 +1,7 @@
 /*
  * lyap.h -- C ABI of the MI355X (gfx950) low-rank Lyapunov solver.
  *
- * Solves A X + X A^T + W = 0 with A Hurwitz and W = L L^T or W = L S L^T (S diagonal,
+ * Solves A X + X A^T + W = 0 with A Hurwitz and W = L L^T or W = L S L^T (S symmetric,
  * possibly indefinite) by the factored, scaled sign-function Newton iteration
  * (Section 3, eq (3.2)/(3.3), Alg 3.1/3.2) wrapped in mixed-precision iterative
  * refinement (Section 2, Alg 2.1/2.2, Fragments 2.1-2.4), returning X ~ Z diag(D) Z^T.
@@ -15,8 +15,12 @@
  *    is stream-ordered and returns after its results are valid (host-synchronous), since
  *    ranks and stopping decisions are taken on the host from a few device scalars.
  *  - Ownership: the caller owns all input and output buffers; the library never frees or
- *    keeps caller memory.  The handle owns a device workspace (grown on demand with
- *    hipMalloc, released by lyap_destroy) and the cached sequence of inverses.
+ *    keeps caller memory.  Every solve works in a device workspace of
+ *    lyap_workspace_size() bytes: either the caller's (``ws``, ``ws_bytes``; the call then
+ *    allocates no device memory) or, with ws == NULL, one the handle allocates with hipMalloc
+ *    on first use, grows when a larger problem needs it and frees in lyap_destroy.  The
+ *    workspace also keeps the cached sequence of inverses of the last solve made in it, which
+ *    adjoint solves and warm-started refinement replay (see lyap_options.reuse).
  *  - Errors: every entry point returns an int status (LYAP_OK = 0 or one of the codes
  *    below); nothing throws across the ABI.  On error the outputs are unspecified unless
  *    the code's description says otherwise.
@@ -42,7 +46,9 @@ enum {
   LYAP_CAPACITY = 6,      /* the factor needs more than z_cap columns; *rank = needed       */
   LYAP_BADARG = 7,        /* invalid size, pointer, precision order or option               */
   LYAP_HIP_ERROR = 8,     /* a HIP runtime call failed                                      */
-  LYAP_NO_MEMORY = 9      /* workspace allocation failed                                    */
+  LYAP_NO_MEMORY = 9,     /* the handle could not allocate its workspace                    */
+  LYAP_WORKSPACE = 10     /* the caller's workspace is smaller than lyap_workspace_size()
+                             or not 256-byte aligned                                        */
 };
 
 /* Arithmetic formats of Table 1.1.  Order of "precision" (larger unit roundoff first):
@@ -50,8 +56,14 @@ enum {
 typedef enum { LYAP_F64 = 0, LYAP_F32 = 1, LYAP_F16 = 2, LYAP_BF16 = 3 } lyap_dtype;
 
 /* Precisions of Alg 2.1/2.2: solver u_s, working u, residual factorisation u_r and solution
- * update u_c, with u_s >= u >= u_r, u_c.  The library supports u = u_r = u_c = F64 and any
- * u_s (F64 gives the plain FP64 sign-function Newton solve). */
+ * update u_c, with u_s >= u >= u_r, u_c in unit roundoff (Table 1.1).  Supported: u = F64
+ * with u_r = u_c = F64 and any u_s (u_s = F64 gives the plain FP64 sign-function Newton
+ * solve), and u = F32 with u_r, u_c in {F32, F64} and u_s in {F32, F16, BF16} (Table 3.1's
+ * rows with u = fp32; the attainable residual is then at the binary32 level, about 1e-8).
+ * At u = F32 the factor Z and D are stored rounded to binary32; at u_r = F32 the product AZ
+ * of the residual factorisation runs on the binary32 matrix cores and the spectral
+ * decompositions of the residual (u_r = F32) and of the update (u_c = F32) use binary32
+ * rotations, their results rounded to binary32. */
 typedef struct {
   int u_s, u, u_r, u_c; /* lyap_dtype values */
 } lyap_precisions;
@@ -77,6 +89,23 @@ typedef struct {
                         (X ~ Z Z^T) and D is filled with ones.  The in-solver
                         truncation keeps singular values above sqrt(u_s) sigma_1 of the
                         factor (SVD reading of RankTruncChol).                              */
+  int scaling;       /* Newton scaling mu_k (Section 3): 0 Frobenius-norm (default, the one
+                        Section 4 uses), 1 determinantal |det A_k|^(-1/n) (log|det| from the
+                        pivots of the inversion), 2 2-norm sqrt(||A_k^-1||_2 / ||A_k||_2) and
+                        3 spectral sqrt(rho(A_k^-1) / rho(A_k)), the last two from power-
+                        iteration estimates (12 steps on A^T A; 24 steps on A).  Scaling is
+                        switched off once delta_k < delta_off in every case.               */
+  int escalate;      /* 1: when a refinement at reduced u_s stagnates (eq 4.2), runs out of
+                        steps, overflows or meets an exact zero pivot, continue it at the next
+                        solver precision (bf16 -> fp16 -> fp32 -> fp64, Table 1.1), from the
+                        current iterate when it is valid; 0 (default): stop there.  Table
+                        3.1 ties each u_s to the conditioning it can handle, so escalation
+                        picks the cheapest precision that converges.  The workspace is then
+                        sized for the FP64 inverse sequence.                                */
+  int reuse;         /* inverse-sequence replay: -1 (default) for lyap_solve_adjoint and
+                        lyap_refine when the workspace holds the sequence of the same A
+                        (64-bit content fingerprint of A, n, u_s and k_max), never for
+                        lyap_solve; 1 also for lyap_solve; 0 never.                          */
 } lyap_options;
 
 /* Per-solve diagnostics (Table 4.1 columns plus timings). */
@@ -105,6 +134,9 @@ typedef struct {
   double kern_ms[4];
   double kern_work[4];
   int kern_calls[4];
+  int u_s_final;          /* solver precision (lyap_dtype) of the last stage (escalate)   */
+  int escalations;        /* precision escalations performed                             */
+  int cache_reused;       /* 1 when the inverse sequence was replayed from the workspace  */
 } lyap_info;
 
 typedef struct lyap_handle_s* lyap_handle;
@@ -115,12 +147,24 @@ int lyap_create(lyap_handle* h, int device);
 /* Destroy a handle and free its workspace.  NULL is accepted. */
 int lyap_destroy(lyap_handle h);
 /* Section 4.1 defaults: tol 1e-13, i_max 50, k_max 50, rho 0.1, eta_r 1e-4, eta_s 10u,
- * delta_off 1e-2, theta 0.9, refine 1, psd -1. */
+ * delta_off 1e-2, theta 0.9, refine 1, psd -1, form 0, scaling 0 (Frobenius), escalate 0,
+ * reuse -1. */
 void lyap_default_options(lyap_options* opt);
 /* Human-readable text of a status code (static string). */
 const char* lyap_strerror(int code);
 /* Library version string and the GPU architecture it was built for. */
 const char* lyap_version(void);
+
+/*
+ * lyap_workspace_size -- bytes of device workspace (256-byte aligned) that lyap_solve,
+ * lyap_refine and lyap_solve_adjoint need for order n, m right-hand-side columns, solver
+ * precision u_s (a lyap_dtype) and the options ``opt`` (NULL: defaults; k_max fixes the
+ * number of cached inverses, form and escalate the buffer shapes).  About
+ * k_max n^2 b_s + (9 (2n + 2m + 64) n + 5 n^2) 8 bytes, b_s the bytes of a u_s value (8 with
+ * escalate): 6.5 GB at n = 4096, u_s = fp32 and the default k_max.  Returns LYAP_BADARG for
+ * sizes outside 1 <= m <= n <= 4096.
+ */
+int lyap_workspace_size(int n, int m, int u_s, const lyap_options* opt, size_t* bytes);
 
 /*
  * lyap_solve -- Alg 2.2 (LDL^T-type mixed-precision IR) with Alg 3.2 as the solver, or with
@@ -129,8 +173,11 @@ const char* lyap_version(void);
  *  n, m      order of A (n <= 4096) and number of columns of L (1 <= m <= n).
  *  A         n x n FP64, row-major, leading dimension lda >= n; A must be Hurwitz.
  *  L         n x m FP64, row-major, ldl >= m.
- *  S         m FP64 values: the diagonal of S (W = L diag(S) L^T), or NULL for W = L L^T.
- *  prec      precisions {u_s, u, u_r, u_c}; u, u_r, u_c must be LYAP_F64.
+ *  S, lds    NULL for W = L L^T; with lds == 0, the m diagonal entries of S
+ *            (W = L diag(S) L^T); with lds >= m, an m x m symmetric S (row-major, only its
+ *            symmetric part is used), diagonalised once on the device as S = Q_s diag(s) Q_s^T
+ *            with L replaced by L Q_s (the change of basis the paper's LDL^T form allows).
+ *  prec      precisions {u_s, u, u_r, u_c} (see lyap_precisions).
  *  opt       options or NULL for the defaults.
  *  Z         n x z_cap FP64 output, row-major, ldz >= z_cap; columns 0..rank-1 receive
  *            orthonormal factor columns (form 0) or the Cholesky-type factor (form 1).
@@ -138,34 +185,62 @@ const char* lyap_version(void);
  *            (S == NULL) D > 0 and Z diag(sqrt D) is a Cholesky-type factor; with form 1,
  *            D = 1.
  *  rank      host int: the number of columns written.
+ *  ws        device workspace of ws_bytes >= lyap_workspace_size(n, m, prec.u_s, opt) bytes,
+ *            256-byte aligned, or NULL for the handle's own.  The solve allocates no device
+ *            memory when ws is given.  Two calls that overlap in time must not share ws.
  *  info      host lyap_info or NULL.
  * Returns LYAP_OK when res <= tol.  LYAP_NOT_CONVERGED / LYAP_STAGNATED still write the
  * last iterate.  With opt->refine == 0 the call runs the plain sign-function Newton solve
- * at u_s and one residual evaluation (the FP64 baseline when u_s = LYAP_F64).
+ * at u_s and one residual evaluation (the FP64 baseline when u_s = LYAP_F64).  Non-finite
+ * values in A, L or S give LYAP_BADARG; overflow inside the iteration LYAP_NONFINITE.
  */
 int lyap_solve(lyap_handle h, void* stream, int n, int m, const double* A, int lda,
-               const double* L, int ldl, const double* S, lyap_precisions prec,
+               const double* L, int ldl, const double* S, int lds, lyap_precisions prec,
                const lyap_options* opt, double* Z, int ldz, int z_cap, double* D, int* rank,
-               lyap_info* info);
+               void* ws, size_t ws_bytes, lyap_info* info);
+
+/*
+ * lyap_refine -- Alg 2.1 / 2.2 started from a given approximation X_0 = Z0 diag(D0) Z0^T
+ * (r0 >= 0 columns, Z0 n x r0 row-major with ldz0 >= r0, D0 r0 values, device pointers) in
+ * place of the first solve (the first line of either algorithm accepts any starting factor):
+ * the residual of X_0 is tested, and while it exceeds tol the corrections are solved and
+ * the update applied exactly as in lyap_solve.  The inverse sequence is computed only if a
+ * correction is needed, and is replayed (no inversion) when the workspace holds the sequence
+ * of the same A and u_s, e.g. from a lyap_solve just made in it.  Z0/D0 may be the same
+ * buffers as Z/D.  Other arguments and return codes as for lyap_solve.
+ */
+int lyap_refine(lyap_handle h, void* stream, int n, int m, const double* A, int lda,
+                const double* L, int ldl, const double* S, int lds, lyap_precisions prec,
+                const lyap_options* opt, const double* Z0, int ldz0, const double* D0, int r0,
+                double* Z, int ldz, int z_cap, double* D, int* rank, void* ws,
+                size_t ws_bytes, lyap_info* info);
 
 /*
  * lyap_solve_batched -- ``count`` independent equations A_i X_i + X_i A_i^T + L_i S_i L_i^T = 0
  * of uneven n_i (<= 4096) and m_i, each solved exactly as lyap_solve would on its own.  The
  * instances are taken longest first (by n_i) by ``workers`` host threads (0: 8; at most
- * 32), each driving its own HIP stream and solver state kept in the handle, so the
+ * 32), each driving its own HIP stream and its own slice of the workspace, so the
  * latency-bound steps of different instances overlap on the GPU.  Per-instance arrays of
  * device pointers and leading dimensions (host arrays of length count); S may be NULL (all
- * instances W = L L^T) or hold NULL entries.  rank, infos (may be NULL) and codes are host
- * arrays of length count receiving each instance's rank, info and return code.  The call
- * waits for ``stream`` before starting and returns when every instance is complete; it
- * returns the first nonzero per-instance code in instance order, or LYAP_OK.
+ * instances W = L L^T) or hold NULL entries; a non-NULL S_i is the diagonal of S (m_i
+ * values).  ws: NULL (the handle's workers allocate their own) or a device workspace of
+ * ws_bytes >= lyap_workspace_size_batched(...) bytes split between the workers.  rank, infos
+ * (may be NULL) and codes are host arrays of length count receiving each instance's rank,
+ * info and return code.  The call waits for ``stream`` before starting and returns when every
+ * instance is complete; it returns the first nonzero per-instance code in instance order, or
+ * LYAP_OK.
  */
 int lyap_solve_batched(lyap_handle h, void* stream, int count, const int* n, const int* m,
                        const double* const* A, const int* lda, const double* const* L,
                        const int* ldl, const double* const* S, lyap_precisions prec,
                        const lyap_options* opt, double* const* Z, const int* ldz,
                        const int* z_cap, double* const* D, int* rank, lyap_info* infos,
-                       int* codes, int workers);
+                       int* codes, int workers, void* ws, size_t ws_bytes);
+/* Workspace bytes of lyap_solve_batched for these instances and worker count (``workers``
+ * as in lyap_solve_batched, 0 meaning 8): one slice per worker, each large enough for the
+ * largest instance. */
+int lyap_workspace_size_batched(int count, const int* n, const int* m, int u_s,
+                                const lyap_options* opt, int workers, size_t* bytes);
 
 /*
  * lyap_trace_loss -- loss = tr(C X C^T) for X = Z diag(D) Z^T: sum_j D_j ||C z_j||^2.
@@ -192,20 +267,20 @@ int lyap_trace_loss_grad(lyap_handle h, void* stream, int n, int m, int k, const
                          double* dL, int lddl, double* dS, double* dC, int lddc);
 
 /*
- * lyap_solve_adjoint -- the adjoint equation A^T Y + Y A + L diag(S) L^T = 0 of the same A,
- * by the same method (Alg 2.2 with Alg 3.2 as the solver), for gradients of losses of X:
- * with G = dloss/dX symmetric and Y solving A^T Y + Y A + G = 0, dloss/dA = 2 Y X and
- * dloss/dL = 2 Y L diag(S).  Arguments, outputs and return codes as for lyap_solve
- * (Y ~ Z diag(D) Z^T).  The sign iteration of A^T is the transpose of that of A, so when
- * the previous lyap_solve on this handle was called with the same A (pointer, n, lda and
- * ||A||_F) and the same u_s, its inverse sequence is replayed with transposed products and
- * no inversion is computed (info->inversions = 0); the caller must not have modified A in
- * between.  Otherwise the sequence is computed from A.
+ * lyap_solve_adjoint -- the adjoint equation A^T Y + Y A + L S L^T = 0 of the same A, by the
+ * same method (Alg 2.2 with Alg 3.2 as the solver), for gradients of losses of X: with
+ * G = dloss/dX symmetric and Y solving A^T Y + Y A + G = 0, dloss/dA = 2 Y X and
+ * dloss/dL = 2 Y L S.  Arguments, outputs and return codes as for lyap_solve
+ * (Y ~ Z diag(D) Z^T).  The sign iteration of A^T is the transpose of that of A, so when the
+ * workspace holds the inverse sequence of this A at this u_s (the 64-bit content fingerprint
+ * of A, n and k_max are compared, not the pointer: an A edited in place is recognised as a
+ * different matrix), it is replayed with transposed products and no inversion is computed
+ * (info->inversions = 0, info->cache_reused = 1).  Otherwise the sequence is computed.
  */
 int lyap_solve_adjoint(lyap_handle h, void* stream, int n, int m, const double* A, int lda,
-                       const double* L, int ldl, const double* S, lyap_precisions prec,
+                       const double* L, int ldl, const double* S, int lds, lyap_precisions prec,
                        const lyap_options* opt, double* Z, int ldz, int z_cap, double* D,
-                       int* rank, lyap_info* info);
+                       int* rank, void* ws, size_t ws_bytes, lyap_info* info);
 
 /* ---------------------------------------------------------------------------------
  * Component entry points.  Each runs one hot-path kernel family on the handle's stream

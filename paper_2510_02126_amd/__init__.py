@@ -6,6 +6,10 @@ current stream.  All arithmetic runs in the library's HIP kernels.
 
     solve(A, L, S=None, precisions=("fp16", "fp64", "fp64", "fp64"), tol=1e-13, ...)
         -> (Z, D, info) with X ~ Z diag(D) Z^T     (Alg 2.2 with Alg 3.2 as the solver)
+    refine(A, L, S, Z0, D0, ...)      -- the same refinement started from X_0 = Z0 diag(D0) Z0^T
+    workspace_size(n, m, u_s, **opts) -- bytes of the device workspace a solve needs
+    (every solve accepts ``ws=``, a uint8 CUDA tensor of at least that size; the call then
+     allocates no device memory)
     solve_batched(As, Ls, Ss=None, ...) -- independent equations of uneven sizes, concurrently
     solve_adjoint(A, L, S=None, ...)  -- A^T Y + Y A + L S L^T = 0, replaying the inverses
     lyapunov_trace_loss(A, L, S, C)   -- tr(C X C^T), differentiable (adjoint backward)
@@ -23,7 +27,7 @@ import torch
 from . import _lib
 from ._lib import DTYPES, Info, LyapError, Options, Precisions
 
-__all__ = ["solve", "solve_batched", "solve_adjoint", "trace_loss", "trace_loss_grad", "LyapunovTraceLoss",
+__all__ = ["solve", "refine", "workspace_size", "solve_batched", "solve_adjoint", "trace_loss", "trace_loss_grad", "LyapunovTraceLoss",
            "lyapunov_trace_loss", "inverse", "gemm", "qr", "syev", "LyapError", "version"]
 
 
@@ -135,18 +139,7 @@ def jacobi_schedule(nb: int):
     return pairs.reshape(nb, nb // 2, 2), bmap.reshape(nb, nb)
 
 
-def _solve(fn_name, A, L, S, precisions, tol, refine, z_cap, raise_on_error, opts):
-    dev = _dev(A, L, S)
-    n = A.shape[0]
-    m = L.shape[1]
-    A, lda = _rowmajor(A)
-    L, ldl = _rowmajor(L)
-    if S is not None:
-        S = S.contiguous()
-    if z_cap is None:
-        z_cap = n  # the rank of X never exceeds n
-    Z = torch.zeros((n, z_cap), dtype=torch.float64, device=A.device)
-    Dv = torch.zeros(z_cap, dtype=torch.float64, device=A.device)
+def _options(tol, refine, opts):
     o = _lib.default_options()
     o.tol = tol
     o.refine = int(bool(refine))
@@ -154,14 +147,67 @@ def _solve(fn_name, A, L, S, precisions, tol, refine, z_cap, raise_on_error, opt
         if not hasattr(o, k):
             raise TypeError(f"unknown option {k}")
         setattr(o, k, v)
+    return o
+
+
+def _s_args(S):
+    """(tensor, lds): lds = 0 for a vector of diagonal entries, the row stride for an m x m S."""
+    if S is None:
+        return None, 0
+    if S.dim() == 1:
+        return S.contiguous(), 0
+    S, lds = _rowmajor(S)
+    return S, lds
+
+
+def _ws_args(ws):
+    if ws is None:
+        return ctypes.c_void_p(0), 0
+    if not ws.is_cuda or ws.dtype != torch.uint8:
+        raise ValueError("ws must be a uint8 CUDA tensor")
+    return ctypes.c_void_p(ws.data_ptr()), ws.numel()
+
+
+def workspace_size(n, m, u_s="fp64", **opts) -> int:
+    """Bytes of device workspace a solve of order n with m columns in L needs
+    (lyap_workspace_size); ``opts`` are lyap_options fields (k_max, form, escalate, ...)."""
+    o = _options(1e-13, True, opts)
+    out = ctypes.c_size_t(0)
+    _lib.check(_lib.lib().lyap_workspace_size(int(n), int(m), DTYPES[u_s], ctypes.byref(o),
+                                              ctypes.byref(out)), "lyap_workspace_size")
+    return out.value
+
+
+def _solve(fn_name, A, L, S, precisions, tol, refine, z_cap, raise_on_error, opts, ws=None,
+           Z0=None, D0=None):
+    dev = _dev(A, L, S, Z0, D0)
+    n = A.shape[0]
+    m = L.shape[1]
+    A, lda = _rowmajor(A)
+    L, ldl = _rowmajor(L)
+    S, lds = _s_args(S)
+    if z_cap is None:
+        z_cap = n  # the rank of X never exceeds n
+    Z = torch.zeros((n, z_cap), dtype=torch.float64, device=A.device)
+    Dv = torch.zeros(z_cap, dtype=torch.float64, device=A.device)
+    o = _options(tol, refine, opts)
     prec = Precisions(*[DTYPES[p] for p in precisions])
     rank = ctypes.c_int(0)
     info = Info()
+    wsp, wsb = _ws_args(ws)
     fn = getattr(_lib.lib(), fn_name)
-    code = fn(_lib.handle(dev), _stream(dev), n, m, _ptr(A), lda, _ptr(L), ldl, _ptr(S), prec,
-              ctypes.byref(o), _ptr(Z), z_cap, z_cap, _ptr(Dv), ctypes.byref(rank),
-              ctypes.byref(info))
+    if fn_name == "lyap_refine":
+        Z0, ldz0 = _rowmajor(Z0) if Z0.shape[1] > 0 else (Z0, max(1, Z0.shape[1]))
+        D0 = D0.contiguous()
+        code = fn(_lib.handle(dev), _stream(dev), n, m, _ptr(A), lda, _ptr(L), ldl, _ptr(S), lds,
+                  prec, ctypes.byref(o), _ptr(Z0), ldz0, _ptr(D0), Z0.shape[1], _ptr(Z), z_cap,
+                  z_cap, _ptr(Dv), ctypes.byref(rank), wsp, wsb, ctypes.byref(info))
+    else:
+        code = fn(_lib.handle(dev), _stream(dev), n, m, _ptr(A), lda, _ptr(L), ldl, _ptr(S), lds,
+                  prec, ctypes.byref(o), _ptr(Z), z_cap, z_cap, _ptr(Dv), ctypes.byref(rank),
+                  wsp, wsb, ctypes.byref(info))
     d = info.as_dict()
+    d["code"] = code
     if code != 0 and raise_on_error and code not in (1, 2):
         _lib.check(code, fn_name)
     r = rank.value
@@ -169,15 +215,25 @@ def _solve(fn_name, A, L, S, precisions, tol, refine, z_cap, raise_on_error, opt
 
 
 def solve(A, L, S=None, precisions=("fp16", "fp64", "fp64", "fp64"), tol=1e-13, refine=True,
-          z_cap=None, raise_on_error=True, **opts):
+          z_cap=None, raise_on_error=True, ws=None, **opts):
     """Alg 2.2 (LDL^T-type mixed-precision IR) on the GPU for A X + X A^T + L S L^T = 0.
-    Returns (Z, D, info) with X ~ Z diag(D) Z^T.  ``form=1`` (with S = None) runs the
-    Cholesky type, Alg 2.1, and returns the Cholesky-type factor (X ~ Z Z^T, D = 1)."""
-    return _solve("lyap_solve", A, L, S, precisions, tol, refine, z_cap, raise_on_error, opts)
+    S: None (S = I), a vector (the diagonal of S) or an m x m symmetric matrix.  Returns
+    (Z, D, info) with X ~ Z diag(D) Z^T.  ``form=1`` (with S = None) runs the Cholesky type,
+    Alg 2.1, and returns the Cholesky-type factor (X ~ Z Z^T, D = 1).  ``ws``: optional
+    caller workspace (uint8 CUDA tensor of at least workspace_size(...) bytes)."""
+    return _solve("lyap_solve", A, L, S, precisions, tol, refine, z_cap, raise_on_error, opts,
+                  ws=ws)
+
+
+def refine(A, L, S, Z0, D0, precisions=("fp16", "fp64", "fp64", "fp64"), tol=1e-13,
+           z_cap=None, raise_on_error=True, ws=None, **opts):
+    """Alg 2.1 / 2.2 started from X_0 = Z0 diag(D0) Z0^T (lyap_refine).  Returns (Z, D, info)."""
+    return _solve("lyap_refine", A, L, S, precisions, tol, True, z_cap, raise_on_error, opts,
+                  ws=ws, Z0=Z0, D0=D0)
 
 
 def solve_batched(As, Ls, Ss=None, precisions=("fp16", "fp64", "fp64", "fp64"), tol=1e-13,
-                  refine=True, z_caps=None, workers=0, raise_on_error=True, **opts):
+                  refine=True, z_caps=None, workers=0, raise_on_error=True, ws=None, **opts):
     """Independent equations A_i X_i + X_i A_i^T + L_i S_i L_i^T = 0 of uneven sizes solved
     concurrently (lyap_solve_batched).  Returns a list of (Z_i, D_i, info_i)."""
     count = len(As)
@@ -195,13 +251,7 @@ def solve_batched(As, Ls, Ss=None, precisions=("fp16", "fp64", "fp64", "fp64"), 
     Ds = [torch.zeros(c, dtype=torch.float64, device=device) for c in caps]
     IA = ctypes.c_int * count
     PA = ctypes.c_void_p * count
-    o = _lib.default_options()
-    o.tol = tol
-    o.refine = int(bool(refine))
-    for k, v in opts.items():
-        if not hasattr(o, k):
-            raise TypeError(f"unknown option {k}")
-        setattr(o, k, v)
+    o = _options(tol, refine, opts)
     prec = Precisions(*[DTYPES[p] for p in precisions])
     rank = IA()
     codes = IA()
@@ -213,19 +263,19 @@ def solve_batched(As, Ls, Ss=None, precisions=("fp16", "fp64", "fp64", "fp64"), 
         PA(*[l.data_ptr() for l, _ in Ls]), IA(*[ld for _, ld in Ls]),
         s_ptrs if any(s is not None for s in Ss) else None, prec, ctypes.byref(o),
         PA(*[z.data_ptr() for z in Zs]), IA(*caps), IA(*caps), PA(*[d.data_ptr() for d in Ds]),
-        rank, infos, codes, int(workers))
+        rank, infos, codes, int(workers), *_ws_args(ws))
     if code != 0 and raise_on_error and code not in (1, 2):
         _lib.check(code, "lyap_solve_batched")
     return [(Zs[i][:, :rank[i]], Ds[i][:rank[i]], infos[i].as_dict()) for i in range(count)]
 
 
 def solve_adjoint(A, L, S=None, precisions=("fp16", "fp64", "fp64", "fp64"), tol=1e-13,
-                  refine=True, z_cap=None, raise_on_error=True, **opts):
+                  refine=True, z_cap=None, raise_on_error=True, ws=None, **opts):
     """The adjoint equation A^T Y + Y A + L S L^T = 0 (same method).  Replays the inverse
-    sequence of the previous ``solve`` on the same tensor A.  Returns (Z, D, info) with
-    Y ~ Z diag(D) Z^T."""
+    sequence left in the workspace by an earlier solve on a matrix with the same contents
+    (content fingerprint).  Returns (Z, D, info) with Y ~ Z diag(D) Z^T."""
     return _solve("lyap_solve_adjoint", A, L, S, precisions, tol, refine, z_cap, raise_on_error,
-                  opts)
+                  opts, ws=ws)
 
 
 def trace_loss(C, Z, D):

@@ -20,6 +20,7 @@ DTYPES = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3}
 STATUS = {
     0: "OK", 1: "NOT_CONVERGED", 2: "STAGNATED", 3: "NONFINITE", 4: "SINGULAR",
     5: "NOT_STABLE", 6: "CAPACITY", 7: "BADARG", 8: "HIP_ERROR", 9: "NO_MEMORY",
+    10: "WORKSPACE",
 }
 
 
@@ -39,7 +40,8 @@ class Options(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("i_max", ctypes.c_int), ("k_max", ctypes.c_int),
                 ("rho", ctypes.c_double), ("eta_r", ctypes.c_double), ("eta_s", ctypes.c_double),
                 ("delta_off", ctypes.c_double), ("theta", ctypes.c_double),
-                ("refine", ctypes.c_int), ("psd", ctypes.c_int), ("form", ctypes.c_int)]
+                ("refine", ctypes.c_int), ("psd", ctypes.c_int), ("form", ctypes.c_int),
+                ("scaling", ctypes.c_int), ("escalate", ctypes.c_int), ("reuse", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
@@ -49,7 +51,9 @@ class Info(ctypes.Structure):
                 ("refinements", ctypes.c_int), ("rank", ctypes.c_int), ("n_mu", ctypes.c_int),
                 ("mus", ctypes.c_double * 64), ("onenorm", ctypes.c_double * 64),
                 ("phase_ms", ctypes.c_double * 8), ("kern_ms", ctypes.c_double * 4),
-                ("kern_work", ctypes.c_double * 4), ("kern_calls", ctypes.c_int * 4)]
+                ("kern_work", ctypes.c_double * 4), ("kern_calls", ctypes.c_int * 4),
+                ("u_s_final", ctypes.c_int), ("escalations", ctypes.c_int),
+                ("cache_reused", ctypes.c_int)]
 
     def as_dict(self) -> dict:
         return {
@@ -67,6 +71,9 @@ class Info(ctypes.Structure):
             "kern_ms": list(self.kern_ms),
             "kern_work": list(self.kern_work),
             "kern_calls": list(self.kern_calls),
+            "u_s_final": {v: k for k, v in DTYPES.items()}.get(self.u_s_final, self.u_s_final),
+            "escalations": self.escalations,
+            "cache_reused": bool(self.cache_reused),
         }
 
 
@@ -83,15 +90,22 @@ _SIGS = {
     "lyap_default_options": (None, [ctypes.POINTER(Options)]),
     "lyap_strerror": (ctypes.c_char_p, [I]),
     "lyap_version": (ctypes.c_char_p, []),
-    "lyap_solve": (I, [P, P, I, I, P, I, P, I, P, Precisions, ctypes.POINTER(Options), P, I, I,
-                       P, ctypes.POINTER(I), ctypes.POINTER(Info)]),
+    "lyap_workspace_size": (I, [I, I, I, ctypes.POINTER(Options), ctypes.POINTER(ctypes.c_size_t)]),
+    "lyap_workspace_size_batched": (I, [I, P, P, I, ctypes.POINTER(Options), I,
+                                        ctypes.POINTER(ctypes.c_size_t)]),
+    "lyap_solve": (I, [P, P, I, I, P, I, P, I, P, I, Precisions, ctypes.POINTER(Options), P, I,
+                       I, P, ctypes.POINTER(I), P, ctypes.c_size_t, ctypes.POINTER(Info)]),
+    "lyap_refine": (I, [P, P, I, I, P, I, P, I, P, I, Precisions, ctypes.POINTER(Options), P, I,
+                        P, I, P, I, I, P, ctypes.POINTER(I), P, ctypes.c_size_t,
+                        ctypes.POINTER(Info)]),
     "lyap_solve_batched": (I, [P, P, I, P, P, P, P, P, P, P, Precisions, ctypes.POINTER(Options),
-                               P, P, P, P, P, P, P, I]),
+                               P, P, P, P, P, P, P, I, P, ctypes.c_size_t]),
     "lyap_trace_loss": (I, [P, P, I, I, P, I, I, P, I, P, ctypes.POINTER(D)]),
     "lyap_trace_loss_grad": (I, [P, P, I, I, I, P, I, P, P, I, I, P, I, P, I, P, I, P, D, P, I,
                                  P, I, P, P, I]),
-    "lyap_solve_adjoint": (I, [P, P, I, I, P, I, P, I, P, Precisions, ctypes.POINTER(Options), P,
-                               I, I, P, ctypes.POINTER(I), ctypes.POINTER(Info)]),
+    "lyap_solve_adjoint": (I, [P, P, I, I, P, I, P, I, P, I, Precisions, ctypes.POINTER(Options),
+                               P, I, I, P, ctypes.POINTER(I), P, ctypes.c_size_t,
+                               ctypes.POINTER(Info)]),
     "lyap_inverse": (I, [P, P, I, I, I, P, I, P, I]),
     "lyap_gemm": (I, [P, P, I, I, I, I, I, I, D, P, I, P, I, D, P, I]),
     "lyap_qr": (I, [P, P, I, I, P, I, P, I, P, I]),

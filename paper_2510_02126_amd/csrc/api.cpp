@@ -90,67 +90,99 @@ void KernTimer::release() {
 
 }  // namespace lyap
 
-// Solver state of one batched-solve worker: its own stream, scratch, buffers and flags.
+// Solver state of one batched-solve worker: its own stream, workspace and solver.
 struct BatchWorker {
   hipStream_t stream = nullptr;
-  Arena ws;
+  DevBuf own;              // used when the caller gives no workspace
+  unsigned long epoch = 0;
   Solver solver;
-  int* flags = nullptr;
   ~BatchWorker() {
     solver.release();
-    ws.release();
-    if (flags) (void)hipFree(flags);
+    own.release();
     if (stream) (void)hipStreamDestroy(stream);
   }
 };
 
 struct lyap_handle_s {
   int device = 0;
-  Arena ws;          // per-call scratch
-  Solver solver;     // owns the cached inverse sequence and persistent buffers
-  int* flags = nullptr;  // device status flags
+  Arena ws;              // scratch of the component entry points
+  DevBuf own;            // the handle's own solve workspace (ws == NULL)
+  unsigned long epoch = 0;  // bumped whenever ``own`` is reallocated
+  Solver solver;         // host state, including which workspace holds which inverse sequence
+  int* flags = nullptr;  // device status flags of the component entry points
   std::vector<std::unique_ptr<BatchWorker>> workers;  // batched solves
 };
 
-static bool valid_dtype(int d);
+static bool valid_dtype(int d) { return d >= LYAP_F64 && d <= LYAP_BF16; }
 
-static int solve_on(Solver& solver, Arena& ws, int* flags, hipStream_t stream, int n, int m,
-                    const double* A, int lda, const double* L, int ldl, const double* S,
-                    lyap_precisions prec, const lyap_options* opt, double* Z, int ldz,
-                    int z_cap, double* D, int* rank, lyap_info* info, bool adjoint) {
+static double uroff(int d) { return unit_roundoff((Prec)d); }
+
+// u_s >= u >= u_r, u_c in unit roundoff, with u in {F64, F32}; u_s = F64 only with u = F64.
+static bool valid_precisions(const lyap_precisions& p) {
+  if (!valid_dtype(p.u_s) || !valid_dtype(p.u) || !valid_dtype(p.u_r) || !valid_dtype(p.u_c))
+    return false;
+  if (p.u != LYAP_F64 && p.u != LYAP_F32) return false;
+  if (p.u_r != LYAP_F64 && p.u_r != LYAP_F32) return false;
+  if (p.u_c != LYAP_F64 && p.u_c != LYAP_F32) return false;
+  return uroff(p.u_s) >= uroff(p.u) && uroff(p.u) >= uroff(p.u_r) &&
+         uroff(p.u) >= uroff(p.u_c);
+}
+
+static bool valid_options(const lyap_options& o, const double* S, int lds) {
+  return o.tol >= 0 && o.i_max >= 0 && o.i_max <= 63 && o.k_max >= 1 && o.k_max <= 64 &&
+         o.rho > 0 && o.eta_r >= 0 && o.theta > 0 && (o.form == 0 || o.form == 1) &&
+         !(o.form == 1 && S != nullptr) && o.scaling >= 0 && o.scaling <= 3 &&
+         (o.escalate == 0 || o.escalate == 1) && o.reuse >= -1 && o.reuse <= 1 &&
+         o.delta_off >= 0 && lds >= 0;
+}
+
+static int solve_on(Solver& solver, DevBuf& own, unsigned long& epoch, hipStream_t stream,
+                    int n, int m, const double* A, int lda, const double* L, int ldl,
+                    const double* S, int lds, lyap_precisions prec, const lyap_options* opt,
+                    const double* Z0, int ldz0, const double* D0, int r0, double* Z, int ldz,
+                    int z_cap, double* D, int* rank, void* ws, size_t ws_bytes, lyap_info* info,
+                    bool adjoint) {
   if (n <= 0 || m <= 0 || m > n || !A || !L || !Z || !D || !rank || lda < n || ldl < m ||
-      z_cap < 1 || ldz < z_cap)
+      z_cap < 1 || ldz < z_cap || (S && lds != 0 && lds < m))
     return LYAP_BADARG;
-  if (!valid_dtype(prec.u_s) || prec.u != LYAP_F64 || prec.u_r != LYAP_F64 ||
-      prec.u_c != LYAP_F64)
-    return LYAP_BADARG;
+  if (r0 >= 0 && (r0 > n || (r0 > 0 && (!Z0 || !D0 || ldz0 < r0)))) return LYAP_BADARG;
+  if (!valid_precisions(prec)) return LYAP_BADARG;
   if (n > 4096) return LYAP_BADARG;
   lyap_options o;
   if (opt) o = *opt;
   else lyap_default_options(&o);
-  if (!(o.tol >= 0) || o.i_max < 0 || o.i_max > 63 || o.k_max < 1 || o.k_max > 64 ||
-      !(o.rho > 0) || !(o.eta_r >= 0) || !(o.theta > 0) || (o.form != 0 && o.form != 1) ||
-      (o.form == 1 && S != nullptr))
-    return LYAP_BADARG;
+  if (!valid_options(o, S, lds)) return LYAP_BADARG;
   lyap_info local;
   lyap_info* inf = info ? info : &local;
   std::memset(inf, 0, sizeof(*inf));
-  int code = solver.solve(stream, ws, flags, n, m, A, lda, L, ldl, S, (Prec)prec.u_s, o, Z, ldz,
-                          z_cap, D, rank, inf, adjoint);
+  const Layout lay = solver_layout(n, m, (Prec)prec.u_s, o);
+  char* base = static_cast<char*>(ws);
+  unsigned long ep = 0;
+  if (!ws) {
+    if (own.bytes < lay.total) {
+      ++epoch;
+      if (own.ensure(lay.total) != LYAP_OK) return inf->status = LYAP_NO_MEMORY;
+    }
+    base = own.as<char>();
+    ws_bytes = own.bytes;
+    ep = epoch;
+  }
+  int code = solver.solve(stream, base, ws_bytes, ep, n, m, A, lda, L, ldl, S, lds, prec, o, Z0,
+                          ldz0, D0, r0, Z, ldz, z_cap, D, rank, inf, adjoint);
   inf->status = code;
   return code;
 }
 
 static int solve_impl(bool adjoint, lyap_handle h, void* stream, int n, int m, const double* A,
-                      int lda, const double* L, int ldl, const double* S, lyap_precisions prec,
-                      const lyap_options* opt, double* Z, int ldz, int z_cap, double* D,
-                      int* rank, lyap_info* info) {
+                      int lda, const double* L, int ldl, const double* S, int lds,
+                      lyap_precisions prec, const lyap_options* opt, const double* Z0, int ldz0,
+                      const double* D0, int r0, double* Z, int ldz, int z_cap, double* D,
+                      int* rank, void* ws, size_t ws_bytes, lyap_info* info) {
   if (!h) return LYAP_BADARG;
-  return solve_on(h->solver, h->ws, h->flags, (hipStream_t)stream, n, m, A, lda, L, ldl, S, prec,
-                  opt, Z, ldz, z_cap, D, rank, info, adjoint);
+  return solve_on(h->solver, h->own, h->epoch, (hipStream_t)stream, n, m, A, lda, L, ldl, S, lds,
+                  prec, opt, Z0, ldz0, D0, r0, Z, ldz, z_cap, D, rank, ws, ws_bytes, info,
+                  adjoint);
 }
-
-static bool valid_dtype(int d) { return d >= LYAP_F64 && d <= LYAP_BF16; }
 
 extern "C" {
 
@@ -166,6 +198,7 @@ const char* lyap_strerror(int code) {
     case LYAP_BADARG: return "invalid argument";
     case LYAP_HIP_ERROR: return "HIP runtime error";
     case LYAP_NO_MEMORY: return "device memory allocation failed";
+    case LYAP_WORKSPACE: return "workspace smaller than lyap_workspace_size() or misaligned";
     default: return "unknown status";
   }
 }
@@ -185,6 +218,49 @@ void lyap_default_options(lyap_options* o) {
   o->refine = 1;
   o->psd = -1;
   o->form = 0;
+  o->scaling = 0;
+  o->escalate = 0;
+  o->reuse = -1;
+}
+
+int lyap_workspace_size(int n, int m, int u_s, const lyap_options* opt, size_t* bytes) {
+  if (!bytes || n <= 0 || m <= 0 || m > n || n > 4096 || !valid_dtype(u_s)) return LYAP_BADARG;
+  lyap_options o;
+  if (opt) o = *opt;
+  else lyap_default_options(&o);
+  if (o.k_max < 1 || o.k_max > 64 || (o.form != 0 && o.form != 1)) return LYAP_BADARG;
+  *bytes = solver_layout(n, m, (Prec)u_s, o).total;
+  return LYAP_OK;
+}
+
+static int batch_workers(int count, int workers) {
+  return std::max(1, std::min(workers > 0 ? workers : 8, std::min(count, 32)));
+}
+
+// One worker slice: large enough for the largest instance (every layout buffer grows with
+// n and m, so the maximum over the instances is taken per dimension).
+static size_t batch_slice(int count, const int* n, const int* m, int u_s, const lyap_options& o) {
+  int nmax = 1, mmax = 1;
+  for (int i = 0; i < count; ++i) {
+    nmax = std::max(nmax, n[i]);
+    mmax = std::max(mmax, m[i]);
+  }
+  return align_up(solver_layout(nmax, std::min(mmax, nmax), (Prec)u_s, o).total, 256);
+}
+
+int lyap_workspace_size_batched(int count, const int* n, const int* m, int u_s,
+                                const lyap_options* opt, int workers, size_t* bytes) {
+  if (!bytes || count < 0 || (count > 0 && (!n || !m)) || !valid_dtype(u_s)) return LYAP_BADARG;
+  *bytes = 0;
+  if (count == 0) return LYAP_OK;
+  for (int i = 0; i < count; ++i)
+    if (n[i] <= 0 || m[i] <= 0 || m[i] > n[i] || n[i] > 4096) return LYAP_BADARG;
+  lyap_options o;
+  if (opt) o = *opt;
+  else lyap_default_options(&o);
+  if (o.k_max < 1 || o.k_max > 64 || (o.form != 0 && o.form != 1)) return LYAP_BADARG;
+  *bytes = batch_slice(count, n, m, u_s, o) * (size_t)batch_workers(count, workers);
+  return LYAP_OK;
 }
 
 int lyap_create(lyap_handle* h, int device) {
@@ -210,6 +286,7 @@ int lyap_destroy(lyap_handle h) {
   (void)hipDeviceSynchronize();
   h->workers.clear();
   h->solver.release();
+  h->own.release();
   h->ws.release();
   if (h->flags) (void)hipFree(h->flags);
   delete h;
@@ -455,7 +532,7 @@ int lyap_solve_batched(lyap_handle h, void* stream, int count, const int* n, con
                        const int* ldl, const double* const* S, lyap_precisions prec,
                        const lyap_options* opt, double* const* Z, const int* ldz,
                        const int* z_cap, double* const* D, int* rank, lyap_info* infos,
-                       int* codes, int workers) {
+                       int* codes, int workers, void* ws, size_t ws_bytes) {
   if (!h || count < 0 || (count > 0 && (!n || !m || !A || !lda || !L || !ldl || !Z || !ldz ||
                                         !z_cap || !D || !rank || !codes)))
     return LYAP_BADARG;
@@ -464,14 +541,21 @@ int lyap_solve_batched(lyap_handle h, void* stream, int count, const int* n, con
     if (n[i] <= 0 || m[i] <= 0 || m[i] > n[i] || n[i] > 4096 || !A[i] || !L[i] || !Z[i] ||
         !D[i] || lda[i] < n[i] || ldl[i] < m[i] || z_cap[i] < 1 || ldz[i] < z_cap[i])
       return LYAP_BADARG;
-  const int W = std::max(1, std::min(workers > 0 ? workers : 8, std::min(count, 32)));
+  lyap_options o;
+  if (opt) o = *opt;
+  else lyap_default_options(&o);
+  const int W = batch_workers(count, workers);
+  size_t slice = 0;
+  if (ws) {
+    slice = batch_slice(count, n, m, prec.u_s, o);
+    if (ws_bytes < slice * W || ((uintptr_t)ws & 255) != 0) return LYAP_WORKSPACE;
+  }
   // inputs are ready once the caller's stream has drained; outputs are complete on return
   LYAP_HIP(hipStreamSynchronize((hipStream_t)stream));
   while ((int)h->workers.size() < W) {
     std::unique_ptr<BatchWorker> w(new (std::nothrow) BatchWorker());
     if (!w) return LYAP_NO_MEMORY;
     LYAP_HIP(hipStreamCreateWithFlags(&w->stream, hipStreamNonBlocking));
-    if (hipMalloc(&w->flags, 16 * sizeof(int)) != hipSuccess) return LYAP_NO_MEMORY;
     h->workers.push_back(std::move(w));
   }
   // longest-processing-time first: instances by decreasing n^3
@@ -482,13 +566,14 @@ int lyap_solve_batched(lyap_handle h, void* stream, int count, const int* n, con
   auto run = [&](int wi) {
     BatchWorker& w = *h->workers[wi];
     if (hipSetDevice(h->device) != hipSuccess) return;
+    char* mine = ws ? static_cast<char*>(ws) + slice * wi : nullptr;
     for (int q = next.fetch_add(1); q < count; q = next.fetch_add(1)) {
       const int i = order[q];
       lyap_info local;
       lyap_info* inf = infos ? &infos[i] : &local;
-      codes[i] = solve_on(w.solver, w.ws, w.flags, w.stream, n[i], m[i], A[i], lda[i], L[i],
-                          ldl[i], S ? S[i] : nullptr, prec, opt, Z[i], ldz[i], z_cap[i], D[i],
-                          &rank[i], inf, false);
+      codes[i] = solve_on(w.solver, w.own, w.epoch, w.stream, n[i], m[i], A[i], lda[i], L[i],
+                          ldl[i], S ? S[i] : nullptr, 0, prec, opt, nullptr, 0, nullptr, -1, Z[i],
+                          ldz[i], z_cap[i], D[i], &rank[i], mine, slice, inf, false);
     }
   };
   std::vector<std::thread> pool;
@@ -501,19 +586,29 @@ int lyap_solve_batched(lyap_handle h, void* stream, int count, const int* n, con
 }
 
 int lyap_solve(lyap_handle h, void* stream, int n, int m, const double* A, int lda,
-               const double* L, int ldl, const double* S, lyap_precisions prec,
+               const double* L, int ldl, const double* S, int lds, lyap_precisions prec,
                const lyap_options* opt, double* Z, int ldz, int z_cap, double* D, int* rank,
-               lyap_info* info) {
-  return solve_impl(false, h, stream, n, m, A, lda, L, ldl, S, prec, opt, Z, ldz, z_cap, D, rank,
-                    info);
+               void* ws, size_t ws_bytes, lyap_info* info) {
+  return solve_impl(false, h, stream, n, m, A, lda, L, ldl, S, lds, prec, opt, nullptr, 0,
+                    nullptr, -1, Z, ldz, z_cap, D, rank, ws, ws_bytes, info);
+}
+
+int lyap_refine(lyap_handle h, void* stream, int n, int m, const double* A, int lda,
+                const double* L, int ldl, const double* S, int lds, lyap_precisions prec,
+                const lyap_options* opt, const double* Z0, int ldz0, const double* D0, int r0,
+                double* Z, int ldz, int z_cap, double* D, int* rank, void* ws,
+                size_t ws_bytes, lyap_info* info) {
+  if (r0 < 0) return LYAP_BADARG;
+  return solve_impl(false, h, stream, n, m, A, lda, L, ldl, S, lds, prec, opt, Z0, ldz0, D0, r0,
+                    Z, ldz, z_cap, D, rank, ws, ws_bytes, info);
 }
 
 int lyap_solve_adjoint(lyap_handle h, void* stream, int n, int m, const double* A, int lda,
-                       const double* L, int ldl, const double* S, lyap_precisions prec,
+                       const double* L, int ldl, const double* S, int lds, lyap_precisions prec,
                        const lyap_options* opt, double* Z, int ldz, int z_cap, double* D,
-                       int* rank, lyap_info* info) {
-  return solve_impl(true, h, stream, n, m, A, lda, L, ldl, S, prec, opt, Z, ldz, z_cap, D, rank,
-                    info);
+                       int* rank, void* ws, size_t ws_bytes, lyap_info* info) {
+  return solve_impl(true, h, stream, n, m, A, lda, L, ldl, S, lds, prec, opt, nullptr, 0,
+                    nullptr, -1, Z, ldz, z_cap, D, rank, ws, ws_bytes, info);
 }
 
 }  // extern "C"

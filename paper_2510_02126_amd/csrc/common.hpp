@@ -18,6 +18,27 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
+// Round-to-nearest-even conversion of a binary64 value to a narrower format, with a single
+// rounding.  binary32 is converted directly.  For fp16 and bf16 the value is first rounded to
+// binary32 by truncation with the last bit set when inexact ("round to odd"); since binary32
+// carries more than p + 1 bits for both targets (p = 11 and 8), the following nearest-even
+// rounding then gives the correctly rounded result (Boldo and Melquiond, 2008), where the
+// direct route through a nearest-even binary32 value can round twice.
+__device__ inline float f32_round_odd(double x) {
+  float f = __double2float_rz(x);
+  if ((double)f != x) f = __int_as_float(__float_as_int(f) | 1);
+  return f;
+}
+template <class T> __device__ inline T rne_from_f64(double x);
+template <> __device__ inline double rne_from_f64<double>(double x) { return x; }
+template <> __device__ inline float rne_from_f64<float>(double x) { return (float)x; }
+template <> __device__ inline _Float16 rne_from_f64<_Float16>(double x) {
+  return (_Float16)f32_round_odd(x);
+}
+template <> __device__ inline __bf16 rne_from_f64<__bf16>(double x) {
+  return (__bf16)f32_round_odd(x);
+}
+
 // Operand formats of the matrix-core products.
 enum class Prec : int { F64 = LYAP_F64, F32 = LYAP_F32, F16 = LYAP_F16, BF16 = LYAP_BF16 };
 
@@ -111,6 +132,12 @@ struct GemmDesc {
   long sbr = 0, sbc = 0;
   void* C = nullptr;
   long ldc = 0;
+  // Power-of-two scalings of reduced-precision operands (device ints, may be NULL):
+  // op(A) is stored as 2^-a_exp times the matrix it stands for, so the product is multiplied
+  // by 2^a_exp; column j of op(B) is multiplied by 2^-b_colexp[j] before it is rounded to the
+  // operand format and column j of the product by 2^b_colexp[j] afterwards.  Both are exact.
+  const int* a_exp = nullptr;
+  const int* b_colexp = nullptr;
 };
 
 // Storage type codes for operands/results.

@@ -34,17 +34,23 @@ template <> struct Cvt<float> {
   __device__ static float f(__bf16 x) { return (float)x; }
 };
 template <> struct Cvt<_Float16> {
-  __device__ static _Float16 f(double x) { return (_Float16)(float)x; }
+  __device__ static _Float16 f(double x) { return rne_from_f64<_Float16>(x); }
   __device__ static _Float16 f(float x) { return (_Float16)x; }
   __device__ static _Float16 f(_Float16 x) { return x; }
   __device__ static _Float16 f(__bf16 x) { return (_Float16)(float)x; }
 };
 template <> struct Cvt<__bf16> {
-  __device__ static __bf16 f(double x) { return (__bf16)(float)x; }
+  __device__ static __bf16 f(double x) { return rne_from_f64<__bf16>(x); }
   __device__ static __bf16 f(float x) { return (__bf16)x; }
   __device__ static __bf16 f(_Float16 x) { return (__bf16)(float)x; }
   __device__ static __bf16 f(__bf16 x) { return x; }
 };
+
+// Operand element rounded to MF after an exact scaling by 2^-e (e = 0: plain rounding).
+template <class MF, class S> __device__ inline MF cvt_scaled(S x, int e) {
+  if (e == 0) return Cvt<MF>::f(x);
+  return Cvt<MF>::f(ldexp(to_d(x), -e));
+}
 
 template <class MF> struct Acc;
 template <> struct Acc<double> { typedef f64x4 V; typedef double S; };
@@ -66,7 +72,9 @@ __global__ __launch_bounds__(NT) void gemm_k4(int M, int N, int K, int kchunk, d
                                               double beta, const TA* __restrict__ A, long sar,
                                               long sac, const TB* __restrict__ B, long sbr,
                                               long sbc, TC* __restrict__ C, long ldc,
-                                              TC* __restrict__ part) {
+                                              TC* __restrict__ part,
+                                              const int* __restrict__ aexp,
+                                              const int* __restrict__ bexp) {
   constexpr int BK = 16;
   typedef typename Acc<MF>::V AV;
   typedef typename Acc<MF>::S AS;
@@ -101,7 +109,8 @@ __global__ __launch_bounds__(NT) void gemm_k4(int M, int N, int K, int kchunk, d
       if (BN_) { nn = e % BN; kk = e / BN; } else { kk = e % BK; nn = e / BK; }
       int gn = n0 + nn, gk = k0 + kk;
       MF v = (MF)0;
-      if (gn < N && gk < kend) v = Cvt<MF>::f(B[(long)gk * sbr + (long)gn * sbc]);
+      if (gn < N && gk < kend)
+        v = cvt_scaled<MF>(B[(long)gk * sbr + (long)gn * sbc], bexp ? bexp[gn] : 0);
       Bs[kk][nn] = v;
     }
     __syncthreads();
@@ -122,6 +131,7 @@ __global__ __launch_bounds__(NT) void gemm_k4(int M, int N, int K, int kchunk, d
   // D layout of the 16x16 tile, lane l, register i: column l % 16; row 4*i + l/16 for the
   // FP64 instruction and 4*(l/16) + i for the binary32 one.
   constexpr bool kF64 = sizeof(MF) == 8;
+  const int ea = aexp ? *aexp : 0;
 #pragma unroll
   for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
@@ -133,11 +143,13 @@ __global__ __launch_bounds__(NT) void gemm_k4(int M, int N, int K, int kchunk, d
         int gn = n0 + wn + tj * 16 + (lane & 15);
         if (gm < M && gn < N) {
           AS v = acc[ti][tj][i];
+          const int es = ea + (bexp ? bexp[gn] : 0);
+          const double al = es == 0 ? alpha : ldexp(alpha, es);
           if (part) {
-            part[((long)blockIdx.z * M + gm) * N + gn] = (TC)((double)v * alpha);
+            part[((long)blockIdx.z * M + gm) * N + gn] = (TC)((double)v * al);
           } else {
             TC* cp = C + (long)gm * ldc + gn;
-            double out = alpha * (double)v;
+            double out = al * (double)v;
             if (beta != 0.0) out += beta * (double)(*cp);
             *cp = (TC)out;
           }
@@ -161,7 +173,9 @@ template <class TA, class TB, class MF, class TC, bool AK, bool BN_>
 __global__ __launch_bounds__(NT) void gemm_k32(int M, int N, int K, double alpha, double beta,
                                                const TA* __restrict__ A, long sar, long sac,
                                                const TB* __restrict__ B, long sbr, long sbc,
-                                               TC* __restrict__ C, long ldc) {
+                                               TC* __restrict__ C, long ldc,
+                                               const int* __restrict__ aexp,
+                                               const int* __restrict__ bexp) {
   constexpr int BK = 32, PK = BK + 8;
   typedef typename V8<MF>::T VT;
   __shared__ __attribute__((aligned(16))) MF As[BM][PK];
@@ -193,7 +207,8 @@ __global__ __launch_bounds__(NT) void gemm_k32(int M, int N, int K, double alpha
       if (BN_) { nn = e % BN; kk = e / BN; } else { kk = e % BK; nn = e / BK; }
       int gn = n0 + nn, gk = k0 + kk;
       MF v = Cvt<MF>::f(0.0f);
-      if (gn < N && gk < K) v = Cvt<MF>::f(B[(long)gk * sbr + (long)gn * sbc]);
+      if (gn < N && gk < K)
+        v = cvt_scaled<MF>(B[(long)gk * sbr + (long)gn * sbc], bexp ? bexp[gn] : 0);
       Bs[nn][kk] = v;
     }
     __syncthreads();
@@ -209,6 +224,7 @@ __global__ __launch_bounds__(NT) void gemm_k32(int M, int N, int K, double alpha
     acc[1][1] = mfma32(a1, b1, acc[1][1]);
     __syncthreads();
   }
+  const int ea = aexp ? *aexp : 0;
 #pragma unroll
   for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
@@ -219,7 +235,8 @@ __global__ __launch_bounds__(NT) void gemm_k32(int M, int N, int K, double alpha
         int gn = n0 + wn + tj * 16 + (lane & 15);
         if (gm < M && gn < N) {
           TC* cp = C + (long)gm * ldc + gn;
-          double out = alpha * (double)acc[ti][tj][i];
+          const int es = ea + (bexp ? bexp[gn] : 0);
+          double out = (es == 0 ? alpha : ldexp(alpha, es)) * (double)acc[ti][tj][i];
           if (beta != 0.0) out += beta * (double)(*cp);
           *cp = (TC)out;
         }
@@ -251,7 +268,7 @@ int launch_k4(hipStream_t s, const GemmDesc& d, int splits, TC* part) {
 #define K4(a, b)                                                                              \
   hipLaunchKernelGGL((gemm_k4<TA, TB, MF, TC, a, b>), grid, dim3(NT), 0, s, d.M, d.N, d.K,   \
                      kchunk, d.alpha, d.beta, A, d.sar, d.sac, B, d.sbr, d.sbc, C, d.ldc,  \
-                     part)
+                     part, d.a_exp, d.b_colexp)
   if (ak && bn) K4(true, true);
   else if (ak) K4(true, false);
   else if (bn) K4(false, true);
@@ -270,7 +287,8 @@ int launch_k32(hipStream_t s, const GemmDesc& d) {
   auto C = static_cast<TC*>(d.C);
 #define K32(a, b)                                                                             \
   hipLaunchKernelGGL((gemm_k32<TA, TB, MF, TC, a, b>), grid, dim3(NT), 0, s, d.M, d.N, d.K,  \
-                     d.alpha, d.beta, A, d.sar, d.sac, B, d.sbr, d.sbc, C, d.ldc)
+                     d.alpha, d.beta, A, d.sar, d.sac, B, d.sbr, d.sbc, C, d.ldc, d.a_exp,     \
+                     d.b_colexp)
   if (ak && bn) K32(true, true);
   else if (ak) K32(true, false);
   else if (bn) K32(false, true);

@@ -11,8 +11,10 @@ size_t inverse_workspace_bytes(Prec op, int n);
 // pivot, flags_dev[1] <- 1 on a non-finite input or result (device ints zeroed by caller).
 // pivot = false skips the pivot search (pivot row = diagonal row); valid when A is strictly
 // column diagonally dominant, where partial pivoting makes no interchanges.
+// With logdet_dev, log|det A| (from the pivots) is written to logdet_dev[0].
 int invert(hipStream_t s, Prec op, int n, const double* A, long lda, double* out, long ldo,
-           Arena& ws, int* flags_dev, bool pivot = true, KernTimer* kt = nullptr);
+           Arena& ws, int* flags_dev, bool pivot = true, KernTimer* kt = nullptr,
+           double* logdet_dev = nullptr);
 
 // ---- elem.hip
 int fill_int(hipStream_t s, int* p, int count, int value);
@@ -24,6 +26,23 @@ int copy_block(hipStream_t s, int rows, int cols, const double* src, long lds, d
 // Round an FP64 rows x cols block to storage ``st`` (F64/F32/F16/BF16) into dst (ld = cols).
 int cast_store(hipStream_t s, Store st, int rows, int cols, const double* src, long lds,
                void* dst);
+// e_dev[0] <- e with 2^(e-1) <= max|A_ij| < 2^e (0 for a zero block); bad_dev[0] <- 1 for a
+// NaN or infinite entry (bad_dev may be NULL).  partial >= 1024 doubles.
+int absmax_exp(hipStream_t s, int rows, int cols, const double* A, long lda, int* e_dev,
+               int* bad_dev, double* partial);
+// dst = RNE(2^-e src) at storage ``st`` (row-major, ld = cols), e = e_dev[0] (NULL: 0); one
+// rounding from FP64 for every format.
+int cast_scaled(hipStream_t s, Store st, int rows, int cols, const double* src, long lds,
+                void* dst, const int* e_dev);
+// X <- RNE(X) at storage ``st`` in place (the values stay in FP64 storage).
+int round_block(hipStream_t s, Store st, int rows, int cols, double* X, long ldx);
+// e_dev[j] <- e_j with 2^(e_j-1) <= max_i |X_ij| < 2^e_j (0 for a zero column); bad_dev[0] <- 1
+// for a non-finite entry.  bits: cols scratch words.
+int col_exponents(hipStream_t s, int rows, int cols, const double* X, long ldx, int* e_dev,
+                  int* bad_dev, unsigned long long* bits);
+// 64-bit content fingerprint of a rows x cols FP64 block (order-independent integer sum).
+int fingerprint(hipStream_t s, int rows, int cols, const double* A, long lda,
+                unsigned long long* out);
 // sum of squares of a rows x cols FP64 block into out[0] (deterministic two-stage).
 int sumsq(hipStream_t s, int rows, int cols, const double* A, long lda, double* out,
           double* partial /* >= 256 doubles, >= 1024 when rows >= 1024 */);
@@ -33,9 +52,19 @@ int sumsq(hipStream_t s, int rows, int cols, const double* A, long lda, double* 
 int newton_update(hipStream_t s, int n, const double* A, long lda, const double* Ainv, long ldi,
                   const double* mu_dev, double* Anew, long ldn, double* out4, double* colsum,
                   double* partial);
-// mu = sqrt(sqrt(inv_sumsq) / sqrt(a_sumsq)) when scaling, else 1 (device scalars).
-int newton_mu(hipStream_t s, const double* inv_sumsq, const double* a_sumsq, int scaling,
+// Scaling parameter (device scalars, 1 when scaling == 0): mode 0 Frobenius
+// sqrt(sqrt(x) / sqrt(y)) from x = ||A^-1||_F^2, y = ||A||_F^2; mode 1 determinantal
+// exp(-x / n) from x = log|det A|; mode 2 sqrt(x / y) from estimates x of A^-1 and y of A.
+int newton_mu(hipStream_t s, int mode, const double* x, const double* y, int n, int scaling,
               double* mu_dev);
+// Power-iteration estimate of ||M||_2 (iters steps on M^T M from the normalised ones vector)
+// into out[0]; work: 19 n doubles.
+int norm2_est(hipStream_t s, int n, const double* M, long ld, int iters, double* out,
+              double* work);
+// Estimate of the spectral radius rho(M): the geometric mean of ||M x_k|| over the last half
+// of ``iters`` normalised power steps, into out[0]; work: 19 n doubles.
+int specrad_est(hipStream_t s, int n, const double* M, long ld, int iters, double* out,
+                double* work);
 
 // sum_ij d_i d_j G_ij^2 for a symmetric c x c G into out[0]; partial >= 256 doubles.
 int wsumsq(hipStream_t s, int c, const double* G, long ldg, const double* d, double* out,

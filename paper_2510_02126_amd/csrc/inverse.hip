@@ -216,7 +216,8 @@ __global__ __launch_bounds__(LEAF_THREADS) void gj_leaf(int n, T* __restrict__ W
                                                          int* __restrict__ used,
                                                          int* __restrict__ piv,
                                                          int* __restrict__ sing, int gc, int gv,
-                                                         T* __restrict__ RT) {
+                                                         T* __restrict__ RT,
+                                                         T* __restrict__ pv) {
   constexpr int NW = LEAF_THREADS / 64;
   __shared__ T crow[2][NW][WC];  // per-wave candidate rows, double-buffered by column parity
   __shared__ T cval[2][NW];
@@ -278,6 +279,7 @@ __global__ __launch_bounds__(LEAF_THREADS) void gj_leaf(int n, T* __restrict__ W
     for (int c = 0; c < WC; ++c) pr[c] = crow[buf][gw][c];
     if (t == 0) lpiv[j] = rp == NO_ROW ? 0 : rp;
     T p = pr[j];
+    if (t == 0) pv[c0 + j] = rp == NO_ROW ? (T)0 : p;
     const bool zero = rp == NO_ROW || !(best > (T)0) || !(fabs(p) > (T)0);
     if (t == 0 && zero) *sing = 1;
     if (zero) p = (T)1;  // singular: keep going, flagged
@@ -326,7 +328,8 @@ __global__ __launch_bounds__(LEAF_THREADS) void gj_leaf(int n, T* __restrict__ W
 template <class T>
 __global__ __launch_bounds__(256) void nop_diag(int n, const T* __restrict__ WT, int c0, int w,
                                                 T* __restrict__ Dinv, int* __restrict__ used,
-                                                int* __restrict__ piv, int* __restrict__ sing) {
+                                                int* __restrict__ piv, int* __restrict__ sing,
+                                                T* __restrict__ pv) {
   __shared__ T rowk[2][WN];
   __shared__ T colk[2][WN];
   const int t = threadIdx.x, i = t & 63, g = t >> 6;
@@ -355,6 +358,7 @@ __global__ __launch_bounds__(256) void nop_diag(int n, const T* __restrict__ WT,
     }
     __syncthreads();
     T p = rowk[buf][k];
+    if (t == 0) pv[c0 + k] = p;
     if (!(fabs(p) > (T)0)) {
       if (t == 0) *sing = 1;
       p = (T)1;
@@ -459,6 +463,28 @@ __global__ __launch_bounds__(256) void unpermute(int n, const T* __restrict__ WT
   if (nonfinite) *bad = 1;
 }
 
+// log|det A| = sum_j log|p_j| + n e log 2 from the Gauss-Jordan pivots p_j of the working
+// copy 2^-e A (the pivots of Gauss-Jordan elimination are those of LU with the same row
+// order); one workgroup, fixed summation order.
+template <class T>
+__global__ __launch_bounds__(256) void logdet_pivots(int n, const T* __restrict__ pv,
+                                                     const int* __restrict__ e, bool scale,
+                                                     double* __restrict__ out) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int j = threadIdx.x; j < n; j += 256) acc += log(fabs((double)pv[j]));
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double ex = scale ? (double)(*e) : 0.0;
+    *out = red[0] + (double)n * ex * 0.69314718055994530942;
+  }
+}
+
 template <class T> struct Inv {
   hipStream_t s;
   int n;
@@ -468,6 +494,7 @@ template <class T> struct Inv {
   int* used;
   int* piv;
   int* sing;
+  T* pv;
   Prec op;
   bool pivot;
 
@@ -477,7 +504,7 @@ template <class T> struct Inv {
   int leaf(int c0, int wc, int gc = 0, int gv = 0) {
     if (!pivot) {
       hipLaunchKernelGGL((nop_diag<T>), dim3(1), dim3(256), 0, s, n, WT, c0, wc, Dinv, used, piv,
-                         sing);
+                         sing, pv);
       hipLaunchKernelGGL((nop_apply<T>), dim3((unsigned)ceil_div(n, AR)), dim3(256), 0, s, n, WT,
                          c0, wc, Dinv);
       LYAP_HIP(hipGetLastError());
@@ -487,7 +514,7 @@ template <class T> struct Inv {
     const int rpt = ceil_div(n, LEAF_THREADS);
 #define LEAF(RPT)                                                                          \
   hipLaunchKernelGGL((gj_leaf<T, RPT, WC>), dim3(1), dim3(LEAF_THREADS), 0, s, n, WT, c0, wc, \
-                     used, piv, sing, gc, gv, RT)
+                     used, piv, sing, gc, gv, RT, pv)
     if (rpt <= 1) LEAF(1);
     else if (rpt <= 2) LEAF(2);
     else if (rpt <= 4) LEAF(4);
@@ -543,7 +570,7 @@ template <class T> struct Inv {
 
 template <class T>
 int invert_t(hipStream_t s, Prec op, int n, const double* A, long lda, double* out, long ldo,
-             Arena& ws, int* flags_dev, bool pivot) {
+             Arena& ws, int* flags_dev, bool pivot, double* logdet) {
   size_t nn = (size_t)n * n;
   const size_t half = (size_t)((n + 1) / 2 + WN);
   T* WT = ws.take<T>(nn);
@@ -552,17 +579,20 @@ int invert_t(hipStream_t s, Prec op, int n, const double* A, long lda, double* o
   int* used = ws.take<int>(n);
   int* piv = ws.take<int>(n);
   int* ex = ws.take<int>(1);
+  T* pv = ws.take<T>(n);
   const int nparts = n >= 1024 ? 1024 : 256;  // four workgroups per CU for a large matrix
   double* part = ws.take<double>(nparts);
-  if (!WT || !RT || !Dinv || !used || !piv || !ex || !part) return LYAP_NO_MEMORY;
+  if (!WT || !RT || !Dinv || !used || !piv || !ex || !part || !pv) return LYAP_NO_MEMORY;
   const bool scale = !std::is_same<T, double>::value;
   const dim3 tiles((unsigned)ceil_div(n, TT), (unsigned)ceil_div(n, TT));
   hipLaunchKernelGGL(absmax_partial, dim3(nparts), dim3(256), 0, s, n, A, lda, part);
   hipLaunchKernelGGL(absmax_exponent, dim3(1), dim3(256), 0, s, nparts, part, ex, flags_dev + 1);
   hipLaunchKernelGGL((load_transposed<T>), tiles, dim3(256), 0, s, n, A, lda, ex, scale, WT, used);
   LYAP_HIP(hipGetLastError());
-  Inv<T> inv{s, n, WT, RT, Dinv, used, piv, flags_dev + 0, op, pivot};
+  Inv<T> inv{s, n, WT, RT, Dinv, used, piv, flags_dev + 0, pv, op, pivot};
   LYAP_TRY(inv.rec(0, n));
+  if (logdet)
+    hipLaunchKernelGGL((logdet_pivots<T>), dim3(1), dim3(256), 0, s, n, pv, ex, scale, logdet);
   hipLaunchKernelGGL((unpermute<T>), tiles, dim3(256), 0, s, n, WT, piv, ex, scale, out, ldo,
                      flags_dev + 1);
   LYAP_HIP(hipGetLastError());
@@ -575,19 +605,20 @@ size_t inverse_workspace_bytes(Prec op, int n) {
   size_t el = op == Prec::F64 ? 8 : 4;
   size_t half = (size_t)((n + 1) / 2 + WN);
   return (size_t)n * n * el + half * half * el + (size_t)WN * WN * el + 4 * (size_t)n * 4 +
-         1024 * 8 + 10 * 256;
+         (size_t)n * el + 1024 * 8 + 12 * 256;
 }
 
 // flags_dev[0] = singular pivot seen, flags_dev[1] = non-finite input/output (device ints,
 // zeroed by the caller).
 int invert(hipStream_t s, Prec op, int n, const double* A, long lda, double* out, long ldo,
-           Arena& ws, int* flags_dev, bool pivot, KernTimer* kt) {
+           Arena& ws, int* flags_dev, bool pivot, KernTimer* kt, double* logdet) {
   if (n <= 0) return LYAP_OK;
   if (n > 8 * LEAF_THREADS) return LYAP_BADARG;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (kt) LYAP_TRY(kt->mark(s, &e0));
-  if (op == Prec::F64) LYAP_TRY(invert_t<double>(s, op, n, A, lda, out, ldo, ws, flags_dev, pivot));
-  else LYAP_TRY(invert_t<float>(s, op, n, A, lda, out, ldo, ws, flags_dev, pivot));
+  if (op == Prec::F64)
+    LYAP_TRY(invert_t<double>(s, op, n, A, lda, out, ldo, ws, flags_dev, pivot, logdet));
+  else LYAP_TRY(invert_t<float>(s, op, n, A, lda, out, ldo, ws, flags_dev, pivot, logdet));
   if (kt) {
     LYAP_TRY(kt->mark(s, &e1));
     kt->add(e0, e1, 0, 2.0 * (double)n * n * n, 1);

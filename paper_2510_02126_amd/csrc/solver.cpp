@@ -1,17 +1,20 @@
 // Host driver of the solver: the scaled sign-function Newton A-iteration with its cached
 // sequence of inverses (Section 3.4), the factored LDL^T iteration (eq 3.3, Alg 3.2) with
 // RankTruncLdlt, and the mixed-precision iterative refinement of Alg 2.2 with the residual
-// factorisation (Fragment 2.3) and the projected solution update (Fragment 2.4).
+// factorisation (Fragment 2.3) and the projected solution update (Fragment 2.4); the
+// Cholesky type (Alg 2.1, Fragments 2.1 / 2.2) shares the same pieces.
 //
 // Every matrix operation runs in the library's HIP kernels; the host only keeps scalars
 // (the scalings mu_k, stopping quantities, the diagonal factors D, kept-index lists) and
 // decides ranks and stops from them.  Tall factors are row-major n x cols with a common
-// leading dimension ``cap``.
+// leading dimension ``cap``.  All device memory of a solve is carved from one workspace
+// (Layout), so a caller can provide it and the solve allocates nothing.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstring>
 #include <vector>
 
 #include "common.hpp"
@@ -40,11 +43,7 @@ void DevBuf::release() {
 }
 
 void Solver::release() {
-  DevBuf* all[] = {&Ak_, &An_, &Ainv_, &colsum_, &part_, &scal_, &dvec_, &dvec2_, &idx_, &Zs_,
-                   &Zc_, &Zd_, &F_, &Uq_, &Tq_, &TN_, &Hm_, &Vm_, &wv_, &Gm_};
-  for (DevBuf* b : all) b->release();
-  for (auto& b : cache_) b.release();
-  cache_.clear();
+  key_ = CacheKey();
   kt_.release();
 }
 
@@ -70,18 +69,93 @@ size_t store_bytes(Store s) {
   return s == Store::F64 ? 8 : (s == Store::F32 ? 4 : 2);
 }
 
+// Next precision up in unit roundoff (Table 1.1): bf16 -> fp16 -> fp32 -> fp64.
+Prec next_up(Prec p) {
+  switch (p) {
+    case Prec::BF16: return Prec::F16;
+    case Prec::F16: return Prec::F32;
+    default: return Prec::F64;
+  }
+}
+
+double round_host(double x, Prec p) {
+  if (p == Prec::F32) return (double)(float)x;
+  return x;
+}
+
+// power-iteration steps of the 2-norm and spectral-radius estimates of the optional scalings
+constexpr int NORM_ITERS = 12;
+constexpr int RHO_ITERS = 24;
+
 }  // namespace
+
+Layout solver_layout(int n, int m, Prec us, const lyap_options& opt) {
+  Layout L;
+  L.n = n;
+  L.m = m;
+  L.cap = (opt.form == 1 ? 3 : 2) * n + 2 * m + 64;
+  L.slots = std::max(1, std::min(opt.k_max, 64));
+  const Prec cache_prec = opt.escalate ? Prec::F64 : us;
+  L.slot_bytes = align_up((size_t)n * n * store_bytes(store_of(cache_prec)), 256);
+  const size_t nn = (size_t)n * n, ncap = (size_t)n * L.cap, cap = (size_t)L.cap;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += align_up(std::max(bytes, (size_t)8), 256);
+    return o;
+  };
+  L.cache = take(L.slot_bytes * L.slots);
+  L.cexp = take(64 * sizeof(int));
+  L.Ak = take(nn * 8);
+  L.An = take(nn * 8);
+  L.Ainv = take(nn * 8);
+  L.colsum = take((size_t)n * 8);
+  L.part = take((2 * 256 + 256 * (size_t)n + 1024) * 8);
+  L.scal = take(64 * 8);
+  L.flags = take(16 * sizeof(int));
+  L.fpr = take(2 * sizeof(unsigned long long));
+  L.vecs = take((size_t)(3 + 16) * n * 8);
+  L.dvec = take(cap * 8);
+  L.dvec2 = take(cap * 8);
+  L.idx = take(cap * 4);
+  L.colexp = take(cap * 4);
+  L.bits = take(cap * 8);
+  L.Lq = take((size_t)n * m * 8);
+  L.Sm = take((size_t)m * m * 8);
+  L.Sv = take((size_t)m * m * 8);
+  L.Sw = take((size_t)m * 8);
+  L.Zs = take(ncap * 8);
+  L.Zc = take(ncap * 8);
+  L.Zd = take(ncap * 8);
+  L.F = take(ncap * 8);
+  L.Uq = take(ncap * 8);
+  L.Tq = take(ncap * 8);
+  L.TN = take(ncap * 8);
+  L.Hm = take(ncap * 8);
+  L.Vm = take(ncap * 8);
+  L.Gm = take(nn * 8);
+  L.wv = take(cap * 8);
+  const Prec inv_prec = opt.escalate ? Prec::F64 : us;
+  L.arena_bytes = std::max(std::max(qr_workspace_bytes(n, L.cap), syev_workspace_bytes(n)),
+                           syev_workspace_bytes(std::max(m, 1))) +
+                  std::max(inverse_workspace_bytes(inv_prec, n), (size_t)64 << 20);
+  L.arena = take(L.arena_bytes);
+  L.total = off;
+  return L;
+}
 
 struct Solver::Ctx {
   hipStream_t s;
-  Arena* ws;
+  char* base;
+  Layout lay;
+  Arena arena;
   int* flags;
   int n, m;
   const double* A;
   long lda;
   const double* L;
   long ldl;
-  Prec us;
+  Prec us, u, ur, uc;
   Store cstore;
   lyap_options opt;
   bool psd;
@@ -90,6 +164,9 @@ struct Solver::Ctx {
   int K = 0;
   std::vector<double> mus;
   double normA = 0.0, normW = 0.0;
+  unsigned long long fp = 0;
+  unsigned long epoch = 0;
+  bool may_reuse = false;
   lyap_info* info;
   double* scal;
   double* part;
@@ -101,6 +178,15 @@ struct Solver::Ctx {
   int orth = 0;
   bool zc_orth = false;
   bool chol = false;  // Cholesky-type IR (Alg 2.1)
+  // buffers
+  char* cache;
+  int* cexp;
+  double *Ak, *An, *Ainv, *colsum, *vecs, *dvec, *dvec2;
+  int *idx, *colexp;
+  unsigned long long *bits, *fpr;
+  double *Zs, *Zc, *Zd, *F, *Uq, *Tq, *TN, *Hm, *Vm, *Gm, *wv;
+  template <class T> T* at(size_t off) const { return reinterpret_cast<T*>(base + off); }
+  void* slot(int k) const { return cache + (size_t)k * lay.slot_bytes; }
 };
 
 int Solver::upload_d(Ctx& c, const std::vector<double>& d, double* dst) {
@@ -109,16 +195,44 @@ int Solver::upload_d(Ctx& c, const std::vector<double>& d, double* dst) {
   return LYAP_OK;
 }
 
+// mu_{k-1} of the chosen scaling (Section 3): Frobenius sqrt(||A^-1||_F / ||A||_F),
+// determinantal |det A|^(-1/n), 2-norm sqrt(||A^-1||_2 / ||A||_2), spectral
+// sqrt(rho(A^-1) / rho(A)); 1 once scaling is switched off.  The 2-norms and spectral radii
+// are power-iteration estimates.  Result on the device in mu_dev.
+int Solver::scaling_mu(Ctx& c, const double* Ak, const double* Ainv, const double* a_ss,
+                       const double* logdet, bool scaling, double* mu_dev) {
+  hipStream_t s = c.s;
+  const int n = c.n;
+  double* sc = c.scal;
+  switch (scaling ? c.opt.scaling : 0) {
+    case 1:
+      return newton_mu(s, 1, logdet, nullptr, n, scaling ? 1 : 0, mu_dev);
+    case 2:
+      LYAP_TRY(norm2_est(s, n, Ak, n, NORM_ITERS, sc + 7, c.vecs));
+      LYAP_TRY(norm2_est(s, n, Ainv, n, NORM_ITERS, sc + 8, c.vecs));
+      return newton_mu(s, 2, sc + 8, sc + 7, n, 1, mu_dev);
+    case 3:
+      LYAP_TRY(specrad_est(s, n, Ak, n, RHO_ITERS, sc + 7, c.vecs));
+      LYAP_TRY(specrad_est(s, n, Ainv, n, RHO_ITERS, sc + 8, c.vecs));
+      return newton_mu(s, 2, sc + 8, sc + 7, n, 1, mu_dev);
+    default:
+      return newton_mu(s, 0, sc + 1, a_ss, n, scaling ? 1 : 0, mu_dev);
+  }
+}
+
 // ---------------------------------------------------------------------------- A-iteration
-// eq (3.1a) with Frobenius scaling; stop when ||A_k + I||_1 <= tau_N = 10 sqrt(n u_s), or
+// eq (3.1a) with the chosen scaling; stop when ||A_k + I||_1 <= tau_N = 10 sqrt(n u_s), or
 // when scaling is already off and delta_k > delta_{k-1}/2; the step that meets the test is
 // followed by one further step.  Scaling is switched off for good once delta_k < delta_off.
+// Each inverse is cached at u_s as a power of two times a value of the format (per matrix).
 int Solver::a_iteration(Ctx& c) {
   const int n = c.n;
   hipStream_t s = c.s;
-  double* Ak = Ak_.as<double>();
-  double* An = An_.as<double>();
+  double* Ak = c.Ak;
+  double* An = c.An;
   double* scal = c.scal;
+  c.mus.clear();
+  c.K = 0;
   LYAP_TRY(copy_block(s, n, n, c.A, c.lda, Ak, n));
   LYAP_TRY(sumsq(s, n, n, Ak, n, scal + 0, c.part));
   const double tau = 10.0 * std::sqrt(n * unit_roundoff(c.us));
@@ -128,30 +242,37 @@ int Solver::a_iteration(Ctx& c) {
   double last_onenorm = INFINITY;
   bool stopped = false;
   const double* a_ss = scal + 0;
-  for (int k = 1; k <= c.opt.k_max; ++k) {
-    if ((int)cache_.size() < k) cache_.emplace_back();
-    size_t eb = store_bytes(c.cstore);
-    LYAP_TRY(cache_[k - 1].ensure((size_t)n * n * eb));
-    double* out = (c.us == Prec::F64) ? cache_[k - 1].as<double>() : Ainv_.as<double>();
+  const int kmax = std::min(c.opt.k_max, c.lay.slots);
+  for (int k = 1; k <= kmax; ++k) {
+    double* out = (c.us == Prec::F64) ? static_cast<double*>(c.slot(k - 1)) : c.Ainv;
     LYAP_TRY(fill_int(s, c.flags, 2, 0));
-    c.ws->reset();
+    c.arena.reset();
     // ||A_{k-1} + I||_1 < 1 makes A_{k-1} strictly column diagonally dominant: partial
     // pivoting would pick the diagonal, so the pivot search is skipped (same result)
     const bool pivot = !(last_onenorm < 1.0);
-    LYAP_TRY(invert(s, c.us, n, Ak, n, out, n, *c.ws, c.flags, pivot, c.kt));
-    if (c.us != Prec::F64) LYAP_TRY(cast_store(s, c.cstore, n, n, out, n, cache_[k - 1].p));
+    const bool want_det = scaling && c.opt.scaling == 1;
+    LYAP_TRY(invert(s, c.us, n, Ak, n, out, n, c.arena, c.flags, pivot, c.kt,
+                    want_det ? scal + 6 : nullptr));
+    if (c.us != Prec::F64) {
+      // cached copy 2^-e A_k^-1 rounded once to u_s (e from its largest entry)
+      LYAP_TRY(absmax_exp(s, n, n, out, n, c.cexp + (k - 1), c.flags + 1, c.part));
+      LYAP_TRY(cast_scaled(s, c.cstore, n, n, out, n, c.slot(k - 1), c.cexp + (k - 1)));
+    } else {
+      LYAP_TRY(fill_int(s, c.cexp + (k - 1), 1, 0));
+    }
     LYAP_TRY(sumsq(s, n, n, out, n, scal + 1, c.part));
-    LYAP_TRY(newton_mu(s, scal + 1, a_ss, scaling ? 1 : 0, scal + 2));
-    LYAP_TRY(newton_update(s, n, Ak, n, out, n, scal + 2, An, n, scal + 3,
-                           colsum_.as<double>(), c.part));
+    LYAP_TRY(scaling_mu(c, Ak, out, a_ss, scal + 6, scaling, scal + 2));
+    LYAP_TRY(newton_update(s, n, Ak, n, out, n, scal + 2, An, n, scal + 3, c.colsum, c.part));
     double h[6];
     int fl[2];
     LYAP_HIP(hipMemcpyAsync(h, scal, sizeof(h), hipMemcpyDeviceToHost, s));
     LYAP_HIP(hipMemcpyAsync(fl, c.flags, sizeof(fl), hipMemcpyDeviceToHost, s));
     LYAP_HIP(hipStreamSynchronize(s));
+    c.info->inversions += 1;
     if (fl[0]) return LYAP_SINGULAR;
     const double mu = h[2], dsq = h[3], anew = h[4], onenorm = h[5];
-    if (fl[1] || !std::isfinite(mu) || !std::isfinite(anew) || !std::isfinite(onenorm))
+    if (fl[1] || !std::isfinite(mu) || !(mu > 0.0) || !std::isfinite(anew) ||
+        !std::isfinite(onenorm) || !std::isfinite(h[1]))
       return LYAP_NONFINITE;
     const double delta = std::sqrt(dsq / anew);
     c.mus.push_back(mu);
@@ -161,7 +282,6 @@ int Solver::a_iteration(Ctx& c) {
       c.info->n_mu = k;
     }
     std::swap(Ak, An);
-    std::swap(Ak_, An_);
     a_ss = scal + 4;
     c.K = k;
     last_onenorm = onenorm;
@@ -186,6 +306,46 @@ int Solver::a_iteration(Ctx& c) {
   return LYAP_NOT_STABLE;
 }
 
+// The inverse sequence of A at u_s: replayed from the workspace when it holds the sequence of
+// this A (content fingerprint, n, u_s, same workspace) and the call allows it, else computed.
+int Solver::ensure_sequence(Ctx& c) {
+  if (c.K > 0) return LYAP_OK;
+  auto t0 = clk::now();
+  const bool match = key_.K > 0 && key_.ws == c.base && key_.epoch == c.epoch &&
+                     key_.fp == c.fp && key_.n == c.n && key_.us == c.us &&
+                     key_.slots == c.lay.slots;
+  if (c.may_reuse && match) {
+    c.K = key_.K;
+    c.mus = key_.mus;
+    c.info->cache_reused = 1;
+    c.info->n_mu = std::min(c.K, 64);
+    for (int k = 0; k < c.info->n_mu; ++k) {
+      c.info->mus[k] = key_.mus[k];
+      c.info->onenorm[k] = key_.onenorm[k];
+    }
+  } else {
+    key_ = CacheKey();
+    const int code = a_iteration(c);
+    c.info->phase_ms[0] += ms_since(t0);
+    if (code != LYAP_OK) {
+      c.K = 0;
+      return code;
+    }
+    key_.ws = c.base;
+    key_.epoch = c.epoch;
+    key_.fp = c.fp;
+    key_.n = c.n;
+    key_.us = c.us;
+    key_.slots = c.lay.slots;
+    key_.mus = c.mus;
+    key_.onenorm.assign(c.info->onenorm, c.info->onenorm + std::min(c.K, 64));
+    key_.K = c.K;
+    return LYAP_OK;
+  }
+  c.info->phase_ms[0] += ms_since(t0);
+  return LYAP_OK;
+}
+
 // -------------------------------------------------------------------- rank truncation
 // RankTruncLdlt: Z = Q R, R diag(d) R^T = V Lambda V^T, keep lambda > thr max|lambda|
 // (|lambda| for an indefinite problem); Z <- Q V_kept, d <- lambda_kept.
@@ -195,23 +355,18 @@ int Solver::rank_trunc(Ctx& c, double* Zb, long ldb, int& cols, std::vector<doub
   const int n = c.n, cap = c.cap;
   if (cols == 0) return LYAP_OK;
   const int k = std::min(n, cols);
-  double* Uq = Uq_.as<double>();
-  double* Tq = Tq_.as<double>();
-  double* TN = TN_.as<double>();
-  double* Hm = Hm_.as<double>();
-  double* Vm = Vm_.as<double>();
-  double* wv = wv_.as<double>();
-  c.ws->reset();
-  LYAP_TRY(qr_lead(s, n, cols, std::min(c.orth, cols), Zb, ldb, Uq, cap, Tq, cap, *c.ws, c.kt));
-  LYAP_TRY(upload_d(c, d, dvec_.as<double>()));
-  LYAP_TRY(copy_block(s, k, cols, Tq, cap, TN, cap, dvec_.as<double>()));
+  c.arena.reset();
+  LYAP_TRY(qr_lead(s, n, cols, std::min(c.orth, cols), Zb, ldb, c.Uq, cap, c.Tq, cap, c.arena,
+                   c.kt));
+  LYAP_TRY(upload_d(c, d, c.dvec));
+  LYAP_TRY(copy_block(s, k, cols, c.Tq, cap, c.TN, cap, c.dvec));
   GemmDesc g;
   g.M = k; g.N = k; g.K = cols;
-  g.A = TN; g.sar = cap; g.sac = 1;
-  g.B = Tq; g.sbr = 1; g.sbc = cap;
-  g.C = Hm; g.ldc = cap;
+  g.A = c.TN; g.sar = cap; g.sac = 1;
+  g.B = c.Tq; g.sbr = 1; g.sbc = cap;
+  g.C = c.Hm; g.ldc = cap;
   LYAP_TRY(gemm_f64(s, g));
-  c.ws->reset();
+  c.arena.reset();
   // Inside the solver only eigenvalues above thr max|lambda| are kept and the solver works
   // at u_s: accuracy relative to ||H|| (absolute rotation threshold) is what it can use;
   // relative accuracy for the discarded small eigenvalues would cost many extra sweeps.  For
@@ -219,10 +374,10 @@ int Solver::rank_trunc(Ctx& c, double* Zb, long ldb, int& cols, std::vector<doub
   // the threshold far above its own rounding).  For u_s = FP32 they stay FP64: FP32
   // rotations would leave noise eigenvalues at the size of the threshold itself.
   const bool single = c.us == Prec::F16 || c.us == Prec::BF16;
-  LYAP_TRY(syev(s, k, Hm, cap, wv, Vm, cap, *c.ws, std::max(10.0 * thr, 1e-15), nullptr, c.kt,
-                false, single));
+  LYAP_TRY(syev(s, k, c.Hm, cap, c.wv, c.Vm, cap, c.arena, std::max(10.0 * thr, 1e-15), nullptr,
+                c.kt, false, single));
   std::vector<double> lam(k);
-  LYAP_HIP(hipMemcpyAsync(lam.data(), wv, k * sizeof(double), hipMemcpyDeviceToHost, s));
+  LYAP_HIP(hipMemcpyAsync(lam.data(), c.wv, k * sizeof(double), hipMemcpyDeviceToHost, s));
   LYAP_HIP(hipStreamSynchronize(s));
   const double t = thr * std::fabs(lam[0]);
   std::vector<int> keep;
@@ -232,12 +387,12 @@ int Solver::rank_trunc(Ctx& c, double* Zb, long ldb, int& cols, std::vector<doub
   d.resize(r);
   for (int i = 0; i < r; ++i) d[i] = lam[keep[i]];
   if (r > 0) {
-    LYAP_HIP(hipMemcpyAsync(idx_.p, keep.data(), r * sizeof(int), hipMemcpyHostToDevice, s));
-    LYAP_TRY(gather_cols(s, k, r, Vm, cap, idx_.as<int>(), TN, cap));
+    LYAP_HIP(hipMemcpyAsync(c.idx, keep.data(), r * sizeof(int), hipMemcpyHostToDevice, s));
+    LYAP_TRY(gather_cols(s, k, r, c.Vm, cap, c.idx, c.TN, cap));
     GemmDesc z;
     z.M = n; z.N = r; z.K = k;
-    z.A = Uq; z.sar = cap; z.sac = 1;
-    z.B = TN; z.sbr = cap; z.sbc = 1;
+    z.A = c.Uq; z.sar = cap; z.sac = 1;
+    z.B = c.TN; z.sbr = cap; z.sbc = 1;
     z.C = Zb; z.ldc = ldb;
     LYAP_TRY(gemm_f64(s, z));
   }
@@ -249,14 +404,16 @@ int Solver::rank_trunc(Ctx& c, double* Zb, long ldb, int& cols, std::vector<doub
 // ------------------------------------------------------------------ factor iteration
 // eq (3.3): Z_k = [Z_{k-1}, A_{k-1}^{-1} Z_{k-1}], D_k = (mu D, D / mu) / 2, truncating
 // whenever the column count exceeds floor(rho n); finally D <- D / 2.  The products use the
-// cached inverses with operands at the solver precision.  Result in Zs (n x cols); the first
-// ``orth0`` columns of L0 are orthonormal, and c.orth tells the same of the result.
+// cached inverses with operands at the solver precision: the cache holds 2^-e_k A_k^-1 and each
+// column j of Z enters as 2^-f_j Z_:j rounded once to u_s, both scales undone exactly in the
+// product.  Result in Zs (n x cols); the first ``orth0`` columns of L0 are orthonormal, and
+// c.orth tells the same of the result.
 int Solver::factor_iteration(Ctx& c, const double* L0, long ld0, int m0, int orth0,
                              const std::vector<double>& d0, bool psd, int& cols,
                              std::vector<double>& d) {
   hipStream_t s = c.s;
   const int n = c.n, cap = c.cap;
-  double* Zs = Zs_.as<double>();
+  double* Zs = c.Zs;
   LYAP_TRY(copy_block(s, n, m0, L0, ld0, Zs, cap));
   cols = m0;
   c.orth = std::min(orth0, m0);
@@ -267,13 +424,19 @@ int Solver::factor_iteration(Ctx& c, const double* L0, long ld0, int m0, int ort
     if (cols > 0) {
       GemmDesc g;
       g.M = n; g.N = cols; g.K = n;
-      g.A = cache_[k].p;
+      g.A = c.slot(k);
       if (c.trans) { g.sar = 1; g.sac = n; }  // (A_k^{-1})^T = (A_k^T)^{-1}
       else { g.sar = n; g.sac = 1; }
       g.B = Zs; g.sbr = cap; g.sbc = 1;
       g.C = Zs + cols; g.ldc = cap;
-      if (c.us == Prec::F64) LYAP_TRY(gemm_f64(s, g));
-      else LYAP_TRY(gemm_lp(s, c.us, c.cstore, Store::F64, Store::F64, g));
+      if (c.us == Prec::F64) {
+        LYAP_TRY(gemm_f64(s, g));
+      } else {
+        LYAP_TRY(col_exponents(s, n, cols, Zs, cap, c.colexp, c.flags + 1, c.bits));
+        g.a_exp = c.cexp + k;
+        g.b_colexp = c.colexp;
+        LYAP_TRY(gemm_lp(s, c.us, c.cstore, Store::F64, Store::F64, g));
+      }
     }
     const double mu = c.mus[k];
     const int c0 = cols;
@@ -298,18 +461,17 @@ int Solver::xnorm(Ctx& c, const double* Zb, long ldb, int cols, const std::vecto
     out = 0.0;
     return LYAP_OK;
   }
-  double* Gm = Gm_.as<double>();
   GemmDesc g;
   g.M = cols; g.N = cols; g.K = c.n;
   g.A = Zb; g.sar = 1; g.sac = ldb;
   g.B = Zb; g.sbr = ldb; g.sbc = 1;
-  g.C = Gm; g.ldc = cols;
-  c.ws->reset();
-  size_t welems = std::min((size_t)64 * cols * cols, (c.ws->cap - 4096) / sizeof(double));
-  double* part = c.ws->take<double>(welems);
+  g.C = c.Gm; g.ldc = cols;
+  c.arena.reset();
+  size_t welems = std::min((size_t)64 * cols * cols, (c.arena.cap - 4096) / sizeof(double));
+  double* part = c.arena.take<double>(welems);
   LYAP_TRY(gemm_f64(s, g, part, part ? welems : 0));
-  LYAP_TRY(upload_d(c, d, dvec_.as<double>()));
-  LYAP_TRY(wsumsq(s, cols, Gm, cols, dvec_.as<double>(), c.scal + 9, c.part));
+  LYAP_TRY(upload_d(c, d, c.dvec));
+  LYAP_TRY(wsumsq(s, cols, c.Gm, cols, c.dvec, c.scal + 9, c.part));
   double v = 0.0;
   LYAP_HIP(hipMemcpyAsync(&v, c.scal + 9, sizeof(double), hipMemcpyDeviceToHost, s));
   LYAP_HIP(hipStreamSynchronize(s));
@@ -320,7 +482,8 @@ int Solver::xnorm(Ctx& c, const double* Zb, long ldb, int cols, const std::vecto
 // ------------------------------------------------------------ residual factorisation
 // Fragment 2.3: F = [Z, AZ, L] = U T, H = T N T^T with N = [[0, D, 0], [D, 0, 0], [0, 0, S]],
 // ||R||_F = ||H||_F; with want_factor, H = Q Lambda Q^T and the residual factor
-// L^D = U Q_t (into Zd), S^D = Lambda_t for |lambda| >= eta_r max|lambda|.
+// L^D = U Q_t (into Zd), S^D = Lambda_t for |lambda| >= eta_r max|lambda|.  At u_r = FP32 the
+// product AZ runs on the binary32 matrix cores and U, T, H are rounded to binary32.
 int Solver::res_fac(Ctx& c, const double* Zb, long ldb, int cols, const std::vector<double>& d,
                     bool want_factor, double& normR, int& rd, std::vector<double>& sd) {
   hipStream_t s = c.s;
@@ -328,12 +491,8 @@ int Solver::res_fac(Ctx& c, const double* Zb, long ldb, int cols, const std::vec
   const int p = 2 * cols + m;
   if (p > cap) return LYAP_CAPACITY;
   const int k = std::min(n, p);
-  double* F = F_.as<double>();
-  double* Uq = Uq_.as<double>();
-  double* Tq = Tq_.as<double>();
-  double* TN = TN_.as<double>();
-  double* Hm = Hm_.as<double>();
-  LYAP_TRY(copy_block(s, n, cols, Zb, ldb, F, cap));
+  const Store rs = store_of(c.ur);
+  LYAP_TRY(copy_block(s, n, cols, Zb, ldb, c.F, cap));
   if (cols > 0) {
     GemmDesc g;
     g.M = n; g.N = cols; g.K = n;
@@ -341,27 +500,31 @@ int Solver::res_fac(Ctx& c, const double* Zb, long ldb, int cols, const std::vec
     if (c.trans) { g.sar = 1; g.sac = c.lda; }
     else { g.sar = c.lda; g.sac = 1; }
     g.B = Zb; g.sbr = ldb; g.sbc = 1;
-    g.C = F + cols; g.ldc = cap;
-    LYAP_TRY(gemm_f64(s, g));
+    g.C = c.F + cols; g.ldc = cap;
+    if (c.ur == Prec::F64) LYAP_TRY(gemm_f64(s, g));
+    else LYAP_TRY(gemm_lp(s, c.ur, Store::F64, Store::F64, Store::F64, g));
   }
-  LYAP_TRY(copy_block(s, n, m, c.L, c.ldl, F + 2 * cols, cap));
-  c.ws->reset();
-  LYAP_TRY(qr_lead(s, n, p, c.zc_orth ? cols : 0, F, cap, Uq, cap, Tq, cap, *c.ws, c.kt));
+  LYAP_TRY(copy_block(s, n, m, c.L, c.ldl, c.F + 2 * cols, cap));
+  c.arena.reset();
+  LYAP_TRY(qr_lead(s, n, p, c.zc_orth ? cols : 0, c.F, cap, c.Uq, cap, c.Tq, cap, c.arena, c.kt));
+  LYAP_TRY(round_block(s, rs, n, k, c.Uq, cap));
+  LYAP_TRY(round_block(s, rs, k, p, c.Tq, cap));
   // TN = T N = [T2 D, T1 D, T3 S]
-  LYAP_TRY(upload_d(c, d, dvec_.as<double>()));
-  LYAP_TRY(upload_d(c, c.svec, dvec2_.as<double>()));
+  LYAP_TRY(upload_d(c, d, c.dvec));
+  LYAP_TRY(upload_d(c, c.svec, c.dvec2));
   if (cols > 0) {
-    LYAP_TRY(copy_block(s, k, cols, Tq + cols, cap, TN, cap, dvec_.as<double>()));
-    LYAP_TRY(copy_block(s, k, cols, Tq, cap, TN + cols, cap, dvec_.as<double>()));
+    LYAP_TRY(copy_block(s, k, cols, c.Tq + cols, cap, c.TN, cap, c.dvec));
+    LYAP_TRY(copy_block(s, k, cols, c.Tq, cap, c.TN + cols, cap, c.dvec));
   }
-  LYAP_TRY(copy_block(s, k, m, Tq + 2 * cols, cap, TN + 2 * cols, cap, dvec2_.as<double>()));
+  LYAP_TRY(copy_block(s, k, m, c.Tq + 2 * cols, cap, c.TN + 2 * cols, cap, c.dvec2));
   GemmDesc h;
   h.M = k; h.N = k; h.K = p;
-  h.A = TN; h.sar = cap; h.sac = 1;
-  h.B = Tq; h.sbr = 1; h.sbc = cap;
-  h.C = Hm; h.ldc = cap;
+  h.A = c.TN; h.sar = cap; h.sac = 1;
+  h.B = c.Tq; h.sbr = 1; h.sbc = cap;
+  h.C = c.Hm; h.ldc = cap;
   LYAP_TRY(gemm_f64(s, h));
-  LYAP_TRY(sumsq(s, k, k, Hm, cap, c.scal + 10, c.part));
+  LYAP_TRY(round_block(s, rs, k, k, c.Hm, cap));
+  LYAP_TRY(sumsq(s, k, k, c.Hm, cap, c.scal + 10, c.part));
   double ss = 0.0;
   LYAP_HIP(hipMemcpyAsync(&ss, c.scal + 10, sizeof(double), hipMemcpyDeviceToHost, s));
   LYAP_HIP(hipStreamSynchronize(s));
@@ -379,28 +542,28 @@ int Solver::res_fac(Ctx& c, const double* Zb, long ldb, int cols, const std::vec
 int Solver::res_factor(Ctx& c, int& rd, std::vector<double>& sd) {
   hipStream_t s = c.s;
   const int n = c.n, cap = c.cap, k = last_k_;
-  double* Uq = Uq_.as<double>();
-  double* Hm = Hm_.as<double>();
-  double* Vm = Vm_.as<double>();
-  double* wv = wv_.as<double>();
   rd = 0;
   sd.clear();
   if (k == 0) return LYAP_OK;
-  c.ws->reset();
-  LYAP_TRY(syev(s, k, Hm, cap, wv, Vm, cap, *c.ws, 1e-10, nullptr, c.kt));
+  c.arena.reset();
+  const bool single = c.ur != Prec::F64;
+  LYAP_TRY(syev(s, k, c.Hm, cap, c.wv, c.Vm, cap, c.arena, single ? 1e-6 : 1e-10, nullptr, c.kt,
+                true, single));
   std::vector<double> lam(k);
-  LYAP_HIP(hipMemcpyAsync(lam.data(), wv, k * sizeof(double), hipMemcpyDeviceToHost, s));
+  LYAP_HIP(hipMemcpyAsync(lam.data(), c.wv, k * sizeof(double), hipMemcpyDeviceToHost, s));
   LYAP_HIP(hipStreamSynchronize(s));
   const double t = c.opt.eta_r * std::fabs(lam[0]);
   while (rd < k && std::fabs(lam[rd]) >= t && lam[rd] != 0.0) ++rd;
   sd.assign(lam.begin(), lam.begin() + rd);
+  for (double& x : sd) x = round_host(x, c.ur);
   if (rd > 0) {
     GemmDesc z;
     z.M = n; z.N = rd; z.K = k;
-    z.A = Uq; z.sar = cap; z.sac = 1;
-    z.B = Vm; z.sbr = cap; z.sbc = 1;
-    z.C = Zd_.as<double>(); z.ldc = cap;
+    z.A = c.Uq; z.sar = cap; z.sac = 1;
+    z.B = c.Vm; z.sbr = cap; z.sbc = 1;
+    z.C = c.Zd; z.ldc = cap;
     LYAP_TRY(gemm_f64(s, z));
+    LYAP_TRY(round_block(s, store_of(c.ur), n, rd, c.Zd, cap));
   }
   return LYAP_OK;
 }
@@ -410,7 +573,9 @@ int Solver::res_factor(Ctx& c, int& rd, std::vector<double>& sd) {
 // keep sigma >= eta_s max|sigma| (|sigma| when the PSD projection is off);
 // Z <- V Theta_t (into Zc), D <- Sigma_t.  The correction Z^D (cd columns) is read from Zcor.
 // Fragment 2.2 (Cholesky type) is the same with Z^D = [Z+, Z-], D^D = (D+, -D-) and the PSD
-// projection: G = [Z, Z+, Z-] scaled by the square roots of the weights gives its K.
+// projection: G = [Z, Z+, Z-] scaled by the square roots of the weights gives its K.  At
+// u_c = FP32 the rotations run in binary32 and V, Gamma, K are rounded to binary32; the new
+// factor is stored at the working precision u.
 int Solver::sol_upt(Ctx& c, int& cols, std::vector<double>& d, const double* Zcor, int cd,
                     const std::vector<double>& dd, double eta_s, bool psd) {
   hipStream_t s = c.s;
@@ -419,32 +584,30 @@ int Solver::sol_upt(Ctx& c, int& cols, std::vector<double>& d, const double* Zco
   if (q > cap) return LYAP_CAPACITY;
   if (q == 0) return LYAP_OK;
   const int k = std::min(n, q);
-  double* F = F_.as<double>();
-  double* Zc = Zc_.as<double>();
-  double* Uq = Uq_.as<double>();
-  double* Tq = Tq_.as<double>();
-  double* TN = TN_.as<double>();
-  double* Hm = Hm_.as<double>();
-  double* Vm = Vm_.as<double>();
-  double* wv = wv_.as<double>();
-  LYAP_TRY(copy_block(s, n, cols, Zc, cap, F, cap));
-  LYAP_TRY(copy_block(s, n, cd, Zcor, cap, F + cols, cap));
-  c.ws->reset();
-  LYAP_TRY(qr_lead(s, n, q, c.zc_orth ? cols : 0, F, cap, Uq, cap, Tq, cap, *c.ws, c.kt));
+  const Store cs = store_of(c.uc);
+  LYAP_TRY(copy_block(s, n, cols, c.Zc, cap, c.F, cap));
+  LYAP_TRY(copy_block(s, n, cd, Zcor, cap, c.F + cols, cap));
+  c.arena.reset();
+  LYAP_TRY(qr_lead(s, n, q, c.zc_orth ? cols : 0, c.F, cap, c.Uq, cap, c.Tq, cap, c.arena, c.kt));
+  LYAP_TRY(round_block(s, cs, n, k, c.Uq, cap));
+  LYAP_TRY(round_block(s, cs, k, q, c.Tq, cap));
   std::vector<double> ups(d);
   ups.insert(ups.end(), dd.begin(), dd.end());
-  LYAP_TRY(upload_d(c, ups, dvec_.as<double>()));
-  LYAP_TRY(copy_block(s, k, q, Tq, cap, TN, cap, dvec_.as<double>()));
+  LYAP_TRY(upload_d(c, ups, c.dvec));
+  LYAP_TRY(copy_block(s, k, q, c.Tq, cap, c.TN, cap, c.dvec));
   GemmDesc g;
   g.M = k; g.N = k; g.K = q;
-  g.A = TN; g.sar = cap; g.sac = 1;
-  g.B = Tq; g.sbr = 1; g.sbc = cap;
-  g.C = Hm; g.ldc = cap;
+  g.A = c.TN; g.sar = cap; g.sac = 1;
+  g.B = c.Tq; g.sbr = 1; g.sbc = cap;
+  g.C = c.Hm; g.ldc = cap;
   LYAP_TRY(gemm_f64(s, g));
-  c.ws->reset();
-  LYAP_TRY(syev(s, k, Hm, cap, wv, Vm, cap, *c.ws, 0.0, nullptr, c.kt));
+  LYAP_TRY(round_block(s, cs, k, k, c.Hm, cap));
+  c.arena.reset();
+  const bool single = c.uc != Prec::F64;
+  LYAP_TRY(syev(s, k, c.Hm, cap, c.wv, c.Vm, cap, c.arena, single ? 1e-6 : 0.0, nullptr, c.kt,
+                true, single));
   std::vector<double> sig(k);
-  LYAP_HIP(hipMemcpyAsync(sig.data(), wv, k * sizeof(double), hipMemcpyDeviceToHost, s));
+  LYAP_HIP(hipMemcpyAsync(sig.data(), c.wv, k * sizeof(double), hipMemcpyDeviceToHost, s));
   LYAP_HIP(hipStreamSynchronize(s));
   const double t = eta_s * std::fabs(sig[0]);
   std::vector<int> keep;
@@ -453,173 +616,71 @@ int Solver::sol_upt(Ctx& c, int& cols, std::vector<double>& d, const double* Zco
       keep.push_back(i);
   const int r = (int)keep.size();
   d.resize(r);
-  for (int i = 0; i < r; ++i) d[i] = sig[keep[i]];
+  for (int i = 0; i < r; ++i) d[i] = round_host(sig[keep[i]], c.u);
   if (r > 0) {
-    LYAP_HIP(hipMemcpyAsync(idx_.p, keep.data(), r * sizeof(int), hipMemcpyHostToDevice, s));
-    LYAP_TRY(gather_cols(s, k, r, Vm, cap, idx_.as<int>(), TN, cap));
+    LYAP_HIP(hipMemcpyAsync(c.idx, keep.data(), r * sizeof(int), hipMemcpyHostToDevice, s));
+    LYAP_TRY(gather_cols(s, k, r, c.Vm, cap, c.idx, c.TN, cap));
     GemmDesc z;
     z.M = n; z.N = r; z.K = k;
-    z.A = Uq; z.sar = cap; z.sac = 1;
-    z.B = TN; z.sbr = cap; z.sbc = 1;
-    z.C = Zc; z.ldc = cap;
+    z.A = c.Uq; z.sar = cap; z.sac = 1;
+    z.B = c.TN; z.sbr = cap; z.sbc = 1;
+    z.C = c.Zc; z.ldc = cap;
     LYAP_TRY(gemm_f64(s, z));
+    LYAP_TRY(round_block(s, store_of(c.u), n, r, c.Zc, cap));
   }
   cols = r;
-  c.zc_orth = true;  // U Theta_t
+  c.zc_orth = c.u == Prec::F64;  // U Theta_t (orthonormal to working precision)
   return LYAP_OK;
 }
 
-// ------------------------------------------------------------------------ IR driver
-int Solver::solve(hipStream_t s, Arena& ws, int* flags, int n, int m, const double* A, int lda,
-                  const double* L, int ldl, const double* S, Prec us, const lyap_options& opt,
-                  double* Z, int ldz, int z_cap, double* D, int* rank, lyap_info* info,
-                  bool adjoint) {
-  const auto t_start = clk::now();
-  Ctx c;
-  c.s = s;
-  c.ws = &ws;
-  c.flags = flags;
-  c.n = n;
-  c.m = m;
-  c.A = A;
-  c.lda = lda;
-  c.L = L;
-  c.ldl = ldl;
-  c.us = us;
-  c.cstore = store_of(us);
-  c.opt = opt;
-  c.info = info;
-  c.trans = adjoint;
-  kt_.reset();
-  c.kt = &kt_;
-  c.svec.assign(m, 1.0);
-  if (S) {
-    LYAP_HIP(hipMemcpyAsync(c.svec.data(), S, m * sizeof(double), hipMemcpyDeviceToHost, s));
-    LYAP_HIP(hipStreamSynchronize(s));
-    for (double v : c.svec)
-      if (!std::isfinite(v)) return LYAP_BADARG;
-  }
-  bool all_nonneg = true;
-  for (double v : c.svec) all_nonneg = all_nonneg && v >= 0.0;
-  c.chol = opt.form == 1;
-  c.psd = c.chol || (opt.psd < 0 ? all_nonneg : (opt.psd != 0));
-  // column capacity of the tall buffers: [Z, AZ, L] and [Z, Z^D]; the Cholesky type keeps two
-  // corrections, [Z, Z+, Z-]
-  c.cap = (c.chol ? 3 : 2) * n + 2 * m + 64;
-  const int cap = c.cap;
-  const size_t nn = (size_t)n * n, ncap = (size_t)n * cap;
-  const size_t RP = 256;
-  LYAP_TRY(Ak_.ensure(nn * 8));
-  LYAP_TRY(An_.ensure(nn * 8));
-  if (us != Prec::F64) LYAP_TRY(Ainv_.ensure(nn * 8));
-  LYAP_TRY(colsum_.ensure((size_t)n * 8));
-  LYAP_TRY(part_.ensure((2 * RP + RP * (size_t)n) * 8));
-  LYAP_TRY(scal_.ensure(64 * 8));
-  LYAP_TRY(dvec_.ensure((size_t)cap * 8));
-  LYAP_TRY(dvec2_.ensure((size_t)cap * 8));
-  LYAP_TRY(idx_.ensure((size_t)cap * 4));
-  DevBuf* tall[] = {&Zs_, &Zc_, &Zd_, &F_, &Uq_, &Tq_, &TN_};
-  for (DevBuf* b : tall) LYAP_TRY(b->ensure(ncap * 8));
-  LYAP_TRY(Hm_.ensure(ncap * 8));
-  LYAP_TRY(Vm_.ensure(ncap * 8));
-  LYAP_TRY(Gm_.ensure((size_t)cap * cap * 8));
-  LYAP_TRY(wv_.ensure((size_t)cap * 8));
-  LYAP_TRY(ws.reserve(std::max(qr_workspace_bytes(n, cap), syev_workspace_bytes(n)) +
-                      std::max(inverse_workspace_bytes(us, n), (size_t)64 << 20)));
-  c.scal = scal_.as<double>();
-  c.part = part_.as<double>();
-
-  // ||A||_F and ||W||_F = sqrt(tr((L^T L S)^2))
-  LYAP_TRY(sumsq(s, n, n, A, lda, c.scal + 11, c.part));
-  {
-    GemmDesc g;
-    g.M = m; g.N = m; g.K = n;
-    g.A = L; g.sar = 1; g.sac = ldl;
-    g.B = L; g.sbr = ldl; g.sbc = 1;
-    g.C = Gm_.as<double>(); g.ldc = m;
-    LYAP_TRY(gemm_f64(s, g));
-    LYAP_TRY(upload_d(c, c.svec, dvec2_.as<double>()));
-    LYAP_TRY(wsumsq(s, m, Gm_.as<double>(), m, dvec2_.as<double>(), c.scal + 12, c.part));
-    double h2[2];
-    LYAP_HIP(hipMemcpyAsync(h2, c.scal + 11, sizeof(h2), hipMemcpyDeviceToHost, s));
-    LYAP_HIP(hipStreamSynchronize(s));
-    c.normA = std::sqrt(h2[0]);
-    c.normW = std::sqrt(std::max(h2[1], 0.0));
-    if (!std::isfinite(c.normA) || !std::isfinite(c.normW)) return LYAP_BADARG;
-  }
-
-  // The sign iteration of A^T is the transpose of that of A (same mu_k: transposition keeps
-  // Frobenius norms), so the adjoint equation runs on A's inverse sequence with transposed
-  // products.  It replays the sequence of the previous forward solve when that was computed
-  // for the same A and solver precision (its stop is then the forward's, on ||A_k + I||_1).
-  auto t0 = clk::now();
-  const bool reuse = adjoint && key_.K > 0 && key_.A == A && key_.n == n && key_.lda == lda &&
-                     key_.us == us && key_.normA == c.normA && (int)cache_.size() >= key_.K;
-  if (reuse) {
-    c.K = key_.K;
-    c.mus = key_.mus;
-    info->inversions = 0;
-    info->n_mu = std::min(c.K, 64);
-    for (int k = 0; k < info->n_mu; ++k) {
-      info->mus[k] = key_.mus[k];
-      info->onenorm[k] = key_.onenorm[k];
-    }
-  } else {
-    key_ = CacheKey();
-    LYAP_TRY(a_iteration(c));
-    info->inversions = c.K;
-    key_.A = A;
-    key_.n = n;
-    key_.lda = lda;
-    key_.us = us;
-    key_.normA = c.normA;
-    key_.mus = c.mus;
-    key_.onenorm.assign(info->onenorm, info->onenorm + std::min(c.K, 64));
-    key_.K = c.K;
-  }
-  info->phase_ms[0] += ms_since(t0);
-
-  // first solve (Alg 2.2, line 1)
-  t0 = clk::now();
-  int cols = 0;
-  std::vector<double> d;
-  LYAP_TRY(factor_iteration(c, L, ldl, m, 0, c.svec, c.psd, cols, d));
-  c.zc_orth = cols > 0 && c.orth >= cols;
-  LYAP_TRY(copy_block(s, n, cols, Zs_.as<double>(), cap, Zc_.as<double>(), cap));
-  LYAP_HIP(hipStreamSynchronize(s));
-  info->phase_ms[2] += ms_since(t0);
-  info->newton_total = info->newton_max = c.K;
-
-  const double eta_s = opt.eta_s > 0.0 ? opt.eta_s : 10.0 * unit_roundoff(Prec::F64);
-  int status = LYAP_NOT_CONVERGED;
-  const int steps = opt.refine ? std::max(opt.i_max, 1) : 1;
+// ------------------------------------------------------------------ refinement loop
+// Alg 2.1 / 2.2 from the current iterate (Zc, d): residual test (eq 4.1) against tau_I, the
+// early stop of eq (4.2), then the correction solve(s) reusing the cached inverses and the
+// projected update.  ``status`` receives OK / NOT_CONVERGED / STAGNATED / NONFINITE; the
+// return value is a hard error code (or LYAP_OK).
+int Solver::refine_loop(Ctx& c, int& cols, std::vector<double>& d, int steps, int& status) {
+  hipStream_t s = c.s;
+  const int n = c.n, cap = c.cap;
+  lyap_info* info = c.info;
+  const double eta_s = c.opt.eta_s > 0.0 ? c.opt.eta_s : 10.0 * unit_roundoff(c.u);
+  std::vector<double> hist;  // residuals of this stage (the eq (4.2) test looks at these)
+  status = LYAP_NOT_CONVERGED;
   for (int i = 1; i <= steps; ++i) {
-    t0 = clk::now();
+    auto t0 = clk::now();
     double normR = 0.0, nx = 0.0;
     int rd = 0;
     std::vector<double> sd;
-    LYAP_TRY(res_fac(c, Zc_.as<double>(), cap, cols, d, false, normR, rd, sd));
-    LYAP_TRY(xnorm(c, Zc_.as<double>(), cap, cols, d, nx));
+    LYAP_TRY(res_fac(c, c.Zc, cap, cols, d, false, normR, rd, sd));
+    LYAP_TRY(xnorm(c, c.Zc, cap, cols, d, nx));
     const double res = normR / (c.normW + 2.0 * nx * c.normA);
     if (info->n_res < 64) info->res_hist[info->n_res++] = res;
     info->res = res;
+    hist.push_back(res);
     info->phase_ms[4] += ms_since(t0);
     if (!std::isfinite(res)) {
       status = LYAP_NONFINITE;
-      break;
+      return LYAP_OK;
     }
-    if (res <= opt.tol) {
+    if (res <= c.opt.tol) {
       status = LYAP_OK;
-      break;
+      return LYAP_OK;
     }
-    if (!opt.refine) break;
-    const int nh = info->n_res;
-    if (nh >= 3 && info->res_hist[nh - 1] > opt.theta * info->res_hist[nh - 2] &&
-        info->res_hist[nh - 2] > opt.theta * info->res_hist[nh - 3]) {
+    if (!c.opt.refine) return LYAP_OK;
+    const int nh = (int)hist.size();
+    if (nh >= 3 && hist[nh - 1] > c.opt.theta * hist[nh - 2] &&
+        hist[nh - 2] > c.opt.theta * hist[nh - 3]) {
       status = LYAP_STAGNATED;
-      break;
+      return LYAP_OK;
     }
-    if (i == steps) break;
+    if (i == steps) return LYAP_OK;
+    // the inverse sequence (computed on demand when the refinement started from a given X_0)
+    {
+      const int code = ensure_sequence(c);
+      if (code != LYAP_OK) {
+        status = code;
+        return LYAP_OK;
+      }
+    }
     // residual factor (Fragment 2.3, truncated at eta_r), from the H and U just formed
     t0 = clk::now();
     LYAP_TRY(res_factor(c, rd, sd));
@@ -628,9 +689,15 @@ int Solver::solve(hipStream_t s, Arena& ws, int* flags, int n, int m, const doub
     t0 = clk::now();
     int cd = 0;
     std::vector<double> dd;
-    const double* Zcor = Zs_.as<double>();
+    const double* Zcor = c.Zs;
     if (!c.chol) {
-      LYAP_TRY(factor_iteration(c, Zd_.as<double>(), cap, rd, rd, sd, false, cd, dd));  // U Q_t
+      // the correction is solved for 2^-e W^D (largest |S^D| in [1/2, 1)) and scaled back
+      int e = 0;
+      if (rd > 0) std::frexp(std::fabs(sd[0]), &e);
+      std::vector<double> sds(sd);
+      for (double& x : sds) x = std::ldexp(x, -e);
+      LYAP_TRY(factor_iteration(c, c.Zd, cap, rd, rd, sds, false, cd, dd));  // U Q_t
+      for (double& x : dd) x = std::ldexp(x, e);
     } else {
       // Fragment 2.1: R = L+ L+^T - L- L-^T with L+- = U Q_+- |Lambda_+-|^(1/2), here as
       // (U Q_+-, |lambda|); the two correction equations (Alg 2.1) share the inverse sequence
@@ -638,54 +705,249 @@ int Solver::solve(hipStream_t s, Arena& ws, int* flags, int n, int m, const doub
       // and the corrections Z+ and Z- are collected in Zd.
       std::vector<int> order;
       std::vector<double> dp, dm;
-      for (int i = 0; i < rd; ++i)
-        if (sd[i] > 0.0) { order.push_back(i); dp.push_back(sd[i]); }
+      for (int j = 0; j < rd; ++j)
+        if (sd[j] > 0.0) { order.push_back(j); dp.push_back(sd[j]); }
       const int rp = (int)order.size();
-      for (int i = 0; i < rd; ++i)
-        if (sd[i] < 0.0) { order.push_back(i); dm.push_back(-sd[i]); }
+      for (int j = 0; j < rd; ++j)
+        if (sd[j] < 0.0) { order.push_back(j); dm.push_back(-sd[j]); }
       const int rm = (int)order.size() - rp;
-      double* Fb = F_.as<double>();
-      double* Zpm = Zd_.as<double>();
+      double* Fb = c.F;
+      double* Zpm = c.Zd;
       if (!order.empty()) {
-        LYAP_HIP(hipMemcpyAsync(idx_.p, order.data(), order.size() * sizeof(int),
+        LYAP_HIP(hipMemcpyAsync(c.idx, order.data(), order.size() * sizeof(int),
                                 hipMemcpyHostToDevice, s));
-        LYAP_TRY(gather_cols(s, n, (int)order.size(), Zd_.as<double>(), cap, idx_.as<int>(), Fb,
-                             cap));
+        LYAP_TRY(gather_cols(s, n, (int)order.size(), c.Zd, cap, c.idx, Fb, cap));
       }
       int cp = 0, cm = 0;
       std::vector<double> ddp, ddm;
       LYAP_TRY(factor_iteration(c, Fb, cap, rp, rp, dp, true, cp, ddp));
-      LYAP_TRY(copy_block(s, n, cp, Zs_.as<double>(), cap, Zpm, cap));
+      LYAP_TRY(copy_block(s, n, cp, c.Zs, cap, Zpm, cap));
       LYAP_TRY(factor_iteration(c, Fb + rp, cap, rm, rm, dm, true, cm, ddm));
       if (cp + cm > cap) return LYAP_CAPACITY;
-      LYAP_TRY(copy_block(s, n, cm, Zs_.as<double>(), cap, Zpm + cp, cap));
+      LYAP_TRY(copy_block(s, n, cm, c.Zs, cap, Zpm + cp, cap));
       cd = cp + cm;
       dd = ddp;
       for (double x : ddm) dd.push_back(-x);
       Zcor = Zpm;
     }
+    // the correction is stored at the working precision
+    LYAP_TRY(round_block(s, store_of(c.u), n, cd, const_cast<double*>(Zcor), cap));
+    for (double& x : dd) x = round_host(x, c.u);
     LYAP_HIP(hipStreamSynchronize(s));
     info->phase_ms[2] += ms_since(t0);
     info->newton_total += c.K;
+    info->newton_max = std::max(info->newton_max, c.K);
     info->refinements += 1;
     // projected solution update (Fragment 2.4; Fragment 2.2 for the Cholesky type)
     t0 = clk::now();
     LYAP_TRY(sol_upt(c, cols, d, Zcor, cd, dd, eta_s, c.psd));
     info->phase_ms[5] += ms_since(t0);
   }
+  return LYAP_OK;
+}
+
+// ------------------------------------------------------------------------ driver
+int Solver::solve(hipStream_t s, char* ws, size_t ws_bytes, unsigned long ws_epoch, int n, int m,
+                  const double* A, int lda, const double* L, int ldl, const double* S, int lds,
+                  const lyap_precisions& prec, const lyap_options& opt, const double* Z0,
+                  int ldz0, const double* D0, int r0, double* Z, int ldz, int z_cap, double* D,
+                  int* rank, lyap_info* info, bool adjoint) {
+  const auto t_start = clk::now();
+  Ctx c;
+  c.s = s;
+  c.base = ws;
+  c.epoch = ws_epoch;
+  c.us = (Prec)prec.u_s;
+  c.u = (Prec)prec.u;
+  c.ur = (Prec)prec.u_r;
+  c.uc = (Prec)prec.u_c;
+  c.lay = solver_layout(n, m, c.us, opt);
+  if (!ws || ws_bytes < c.lay.total || ((uintptr_t)ws & 255) != 0) return LYAP_WORKSPACE;
+  const Layout& ly = c.lay;
+  c.arena.base = ws + ly.arena;
+  c.arena.cap = ly.arena_bytes;
+  c.arena.top = 0;
+  c.cache = ws + ly.cache;
+  c.cexp = c.at<int>(ly.cexp);
+  c.Ak = c.at<double>(ly.Ak);
+  c.An = c.at<double>(ly.An);
+  c.Ainv = c.at<double>(ly.Ainv);
+  c.colsum = c.at<double>(ly.colsum);
+  c.part = c.at<double>(ly.part);
+  c.scal = c.at<double>(ly.scal);
+  c.flags = c.at<int>(ly.flags);
+  c.fpr = c.at<unsigned long long>(ly.fpr);
+  c.vecs = c.at<double>(ly.vecs);
+  c.dvec = c.at<double>(ly.dvec);
+  c.dvec2 = c.at<double>(ly.dvec2);
+  c.idx = c.at<int>(ly.idx);
+  c.colexp = c.at<int>(ly.colexp);
+  c.bits = c.at<unsigned long long>(ly.bits);
+  c.Zs = c.at<double>(ly.Zs);
+  c.Zc = c.at<double>(ly.Zc);
+  c.Zd = c.at<double>(ly.Zd);
+  c.F = c.at<double>(ly.F);
+  c.Uq = c.at<double>(ly.Uq);
+  c.Tq = c.at<double>(ly.Tq);
+  c.TN = c.at<double>(ly.TN);
+  c.Hm = c.at<double>(ly.Hm);
+  c.Vm = c.at<double>(ly.Vm);
+  c.Gm = c.at<double>(ly.Gm);
+  c.wv = c.at<double>(ly.wv);
+  c.n = n;
+  c.m = m;
+  c.A = A;
+  c.lda = lda;
+  c.L = L;
+  c.ldl = ldl;
+  c.cstore = store_of(c.us);
+  c.opt = opt;
+  c.info = info;
+  c.trans = adjoint;
+  c.cap = ly.cap;
+  kt_.reset();
+  c.kt = &kt_;
+  const int cap = c.cap;
+
+  // A0: S.  A diagonal S is taken as given; a full symmetric S = Q_s diag(s) Q_s^T is
+  // diagonalised on the device once and L replaced by L Q_s (an exact orthogonal change:
+  // L S L^T = (L Q_s) diag(s) (L Q_s)^T).
+  c.svec.assign(m, 1.0);
+  if (S && lds == 0) {
+    LYAP_HIP(hipMemcpyAsync(c.svec.data(), S, m * sizeof(double), hipMemcpyDeviceToHost, s));
+    LYAP_HIP(hipStreamSynchronize(s));
+  } else if (S) {
+    double* Sm = c.at<double>(ly.Sm);
+    double* Sv = c.at<double>(ly.Sv);
+    double* Sw = c.at<double>(ly.Sw);
+    double* Lq = c.at<double>(ly.Lq);
+    LYAP_TRY(copy_block(s, m, m, S, lds, Sm, m));
+    c.arena.reset();
+    LYAP_TRY(syev(s, m, Sm, m, Sw, Sv, m, c.arena, 0.0, nullptr, nullptr, true, false));
+    GemmDesc g;
+    g.M = n; g.N = m; g.K = m;
+    g.A = L; g.sar = ldl; g.sac = 1;
+    g.B = Sv; g.sbr = m; g.sbc = 1;
+    g.C = Lq; g.ldc = m;
+    LYAP_TRY(gemm_f64(s, g));
+    LYAP_HIP(hipMemcpyAsync(c.svec.data(), Sw, m * sizeof(double), hipMemcpyDeviceToHost, s));
+    LYAP_HIP(hipStreamSynchronize(s));
+    c.L = Lq;
+    c.ldl = m;
+  }
+  for (double v : c.svec)
+    if (!std::isfinite(v)) return LYAP_BADARG;
+  bool all_nonneg = true;
+  for (double v : c.svec) all_nonneg = all_nonneg && v >= 0.0;
+  c.chol = opt.form == 1;
+  c.psd = c.chol || (opt.psd < 0 ? all_nonneg : (opt.psd != 0));
+
+  // ||A||_F, ||W||_F = sqrt(tr((L^T L S)^2)) and the content fingerprint of A
+  LYAP_TRY(sumsq(s, n, n, A, lda, c.scal + 11, c.part));
+  {
+    GemmDesc g;
+    g.M = m; g.N = m; g.K = n;
+    g.A = c.L; g.sar = 1; g.sac = c.ldl;
+    g.B = c.L; g.sbr = c.ldl; g.sbc = 1;
+    g.C = c.Gm; g.ldc = m;
+    LYAP_TRY(gemm_f64(s, g));
+    LYAP_TRY(upload_d(c, c.svec, c.dvec2));
+    LYAP_TRY(wsumsq(s, m, c.Gm, m, c.dvec2, c.scal + 12, c.part));
+    LYAP_TRY(fingerprint(s, n, n, A, lda, c.fpr));
+    double h2[2];
+    LYAP_HIP(hipMemcpyAsync(h2, c.scal + 11, sizeof(h2), hipMemcpyDeviceToHost, s));
+    LYAP_HIP(hipMemcpyAsync(&c.fp, c.fpr, sizeof(c.fp), hipMemcpyDeviceToHost, s));
+    LYAP_HIP(hipStreamSynchronize(s));
+    c.normA = std::sqrt(h2[0]);
+    c.normW = std::sqrt(std::max(h2[1], 0.0));
+    if (!std::isfinite(c.normA) || !std::isfinite(c.normW)) return LYAP_BADARG;
+  }
+  const bool warm = r0 >= 0;
+  c.may_reuse = opt.reuse > 0 || (opt.reuse < 0 && (adjoint || warm));
+  info->u_s_final = (int)c.us;
+
+  int cols = 0;
+  std::vector<double> d;
+  int status = LYAP_OK;
+  int refinements_left = opt.refine ? std::max(opt.i_max, 1) : 1;
+  bool fresh = !warm;
+  if (warm) {
+    // X_0 = Z0 diag(D0) Z0^T, stored at the working precision
+    if (r0 > cap) return LYAP_CAPACITY;
+    d.assign(r0, 0.0);
+    if (r0 > 0) {
+      LYAP_TRY(copy_block(s, n, r0, Z0, ldz0, c.Zc, cap));
+      LYAP_TRY(round_block(s, store_of(c.u), n, r0, c.Zc, cap));
+      LYAP_HIP(hipMemcpyAsync(d.data(), D0, r0 * sizeof(double), hipMemcpyDeviceToHost, s));
+      LYAP_HIP(hipStreamSynchronize(s));
+      for (double& x : d) {
+        if (!std::isfinite(x)) return LYAP_BADARG;
+        x = round_host(x, c.u);
+      }
+    }
+    cols = r0;
+    c.zc_orth = false;
+  }
+  for (;;) {
+    int code = LYAP_OK;
+    if (fresh) {
+      // first solve (Alg 2.2, line 1)
+      code = ensure_sequence(c);
+      if (code == LYAP_OK) {
+        auto t0 = clk::now();
+        LYAP_TRY(factor_iteration(c, c.L, c.ldl, m, 0, c.svec, c.psd, cols, d));
+        c.zc_orth = cols > 0 && c.orth >= cols && c.u == Prec::F64;
+        LYAP_TRY(copy_block(s, n, cols, c.Zs, cap, c.Zc, cap));
+        LYAP_TRY(round_block(s, store_of(c.u), n, cols, c.Zc, cap));
+        for (double& x : d) x = round_host(x, c.u);
+        LYAP_HIP(hipStreamSynchronize(s));
+        info->phase_ms[2] += ms_since(t0);
+        info->newton_total += c.K;
+        info->newton_max = std::max(info->newton_max, c.K);
+      }
+    }
+    if (code == LYAP_OK) {
+      const int before = info->refinements;
+      LYAP_TRY(refine_loop(c, cols, d, refinements_left, code));
+      refinements_left = std::max(1, refinements_left - (info->refinements - before));
+    }
+    // precision escalation: a stage that stagnated, overflowed, hit an exact zero pivot or
+    // ran out of steps at a reduced solver precision is continued one precision up
+    const bool escalatable = code == LYAP_STAGNATED || code == LYAP_NOT_CONVERGED ||
+                             code == LYAP_NONFINITE || code == LYAP_SINGULAR;
+    if (!(opt.escalate && opt.refine && escalatable &&
+          unit_roundoff(c.us) > unit_roundoff(c.u))) {
+      status = code;
+      break;
+    }
+    const bool have_iterate = code == LYAP_STAGNATED || code == LYAP_NOT_CONVERGED;
+    c.us = next_up(c.us);
+    c.cstore = store_of(c.us);
+    c.K = 0;
+    c.mus.clear();
+    info->escalations += 1;
+    info->u_s_final = (int)c.us;
+    fresh = !(have_iterate && cols > 0);
+    if (fresh) {
+      cols = 0;
+      d.clear();
+    }
+  }
   info->rank = cols;
   *rank = cols;
+  if (status != LYAP_OK && status != LYAP_NOT_CONVERGED && status != LYAP_STAGNATED)
+    return status;
   if (cols > z_cap) return LYAP_CAPACITY;
   if (!c.chol) {
-    LYAP_TRY(copy_block(s, n, cols, Zc_.as<double>(), cap, Z, ldz));
+    LYAP_TRY(copy_block(s, n, cols, c.Zc, cap, Z, ldz));
     if (cols > 0)
       LYAP_HIP(hipMemcpyAsync(D, d.data(), cols * sizeof(double), hipMemcpyHostToDevice, s));
   } else if (cols > 0) {
     // Cholesky-type factor Z diag(d)^(1/2) (d >= 0 after the PSD projection), D = 1
     std::vector<double> sq(cols), ones(cols, 1.0);
     for (int i = 0; i < cols; ++i) sq[i] = std::sqrt(std::max(d[i], 0.0));
-    LYAP_TRY(upload_d(c, sq, dvec_.as<double>()));
-    LYAP_TRY(copy_block(s, n, cols, Zc_.as<double>(), cap, Z, ldz, dvec_.as<double>()));
+    LYAP_TRY(upload_d(c, sq, c.dvec));
+    LYAP_TRY(copy_block(s, n, cols, c.Zc, cap, Z, ldz, c.dvec));
     LYAP_HIP(hipMemcpyAsync(D, ones.data(), cols * sizeof(double), hipMemcpyHostToDevice, s));
   }
   LYAP_HIP(hipStreamSynchronize(s));

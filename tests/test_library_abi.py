@@ -64,3 +64,25 @@ def test_struct_layouts_match_header(tmp_path):
         assert int(out[st]) == ctypes.sizeof(cls), st
         for f, _ in cls._fields_:
             assert int(out[f"{st}.{f}"]) == getattr(cls, f).offset, (st, f)
+
+
+def test_workspace_size_is_host_only():
+    # lyap_workspace_size needs no handle and no GPU
+    L = _lib.lib()
+    out = ctypes.c_size_t(0)
+    o = _lib.default_options()
+    assert L.lyap_workspace_size(4096, 8, 1, ctypes.byref(o), ctypes.byref(out)) == 0
+    fp32 = out.value
+    # k_max cached binary32 inverses of 4096 x 4096 are part of it
+    assert fp32 > o.k_max * 4096 * 4096 * 4
+    o.escalate = 1
+    assert L.lyap_workspace_size(4096, 8, 1, ctypes.byref(o), ctypes.byref(out)) == 0
+    assert out.value > fp32
+    for bad in ((0, 1, 0), (4097, 8, 0), (16, 17, 0), (16, 2, 9)):
+        assert L.lyap_workspace_size(*bad, None, ctypes.byref(out)) == 7
+    ns = (ctypes.c_int * 3)(100, 512, 64)
+    ms = (ctypes.c_int * 3)(1, 8, 2)
+    assert L.lyap_workspace_size_batched(3, ns, ms, 2, None, 2, ctypes.byref(out)) == 0
+    one = ctypes.c_size_t(0)
+    assert L.lyap_workspace_size(512, 8, 2, None, ctypes.byref(one)) == 0
+    assert out.value >= 2 * one.value
