@@ -47,8 +47,10 @@ enum {
   LYAP_BADARG = 7,        /* invalid size, pointer, precision order or option               */
   LYAP_HIP_ERROR = 8,     /* a HIP runtime call failed                                      */
   LYAP_NO_MEMORY = 9,     /* the handle could not allocate its workspace                    */
-  LYAP_WORKSPACE = 10     /* the caller's workspace is smaller than lyap_workspace_size()
+  LYAP_WORKSPACE = 10,    /* the caller's workspace is smaller than lyap_workspace_size()
                              or not 256-byte aligned                                        */
+  LYAP_TOO_LARGE = 11     /* lyap_solve_static: the problem's workspace exceeds its fixed
+                             64 MiB device scratch                                          */
 };
 
 /* Arithmetic formats of Table 1.1.  Order of "precision" (larger unit roundoff first):
@@ -198,6 +200,24 @@ int lyap_solve(lyap_handle h, void* stream, int n, int m, const double* A, int l
                const double* L, int ldl, const double* S, int lds, lyap_precisions prec,
                const lyap_options* opt, double* Z, int ldz, int z_cap, double* D, int* rank,
                void* ws, size_t ws_bytes, lyap_info* info);
+
+/*
+ * lyap_solve_static -- lyap_solve for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the solve runs in
+ * a fixed 64 MiB device scratch array compiled into the library, one per GPU, held until the
+ * process ends; the call makes no hipMalloc / hipFree and creates no events (info->kern_*
+ * stay zero).  Arguments, outputs and status codes as for lyap_solve; a problem whose
+ * lyap_workspace_size() exceeds 64 MiB (for example n > 256 at the default k_max with m = 8
+ * and u_s = fp64; the limit grows when k_max is lowered) is rejected with LYAP_TOO_LARGE
+ * before any device work.  Every call on a GPU shares that GPU's scratch, which keeps the
+ * last call's contents: calls that overlap in time on one GPU (two streams, two threads,
+ * two handles) race and must be serialised by the caller.  No call replays an inverse
+ * sequence left in the scratch by an earlier call.
+ */
+int lyap_solve_static(lyap_handle h, void* stream, int n, int m, const double* A, int lda,
+                      const double* L, int ldl, const double* S, int lds, lyap_precisions prec,
+                      const lyap_options* opt, double* Z, int ldz, int z_cap, double* D,
+                      int* rank, lyap_info* info);
 
 /*
  * lyap_refine -- Alg 2.1 / 2.2 started from a given approximation X_0 = Z0 diag(D0) Z0^T

@@ -27,7 +27,7 @@ import torch
 from . import _lib
 from ._lib import DTYPES, Info, LyapError, Options, Precisions
 
-__all__ = ["solve", "refine", "workspace_size", "solve_batched", "solve_adjoint", "trace_loss", "trace_loss_grad", "LyapunovTraceLoss",
+__all__ = ["solve", "solve_static", "refine", "workspace_size", "solve_batched", "solve_adjoint", "trace_loss", "trace_loss_grad", "LyapunovTraceLoss",
            "lyapunov_trace_loss", "inverse", "gemm", "qr", "syev", "LyapError", "version"]
 
 
@@ -202,6 +202,10 @@ def _solve(fn_name, A, L, S, precisions, tol, refine, z_cap, raise_on_error, opt
         code = fn(_lib.handle(dev), _stream(dev), n, m, _ptr(A), lda, _ptr(L), ldl, _ptr(S), lds,
                   prec, ctypes.byref(o), _ptr(Z0), ldz0, _ptr(D0), Z0.shape[1], _ptr(Z), z_cap,
                   z_cap, _ptr(Dv), ctypes.byref(rank), wsp, wsb, ctypes.byref(info))
+    elif fn_name == "lyap_solve_static":
+        code = fn(_lib.handle(dev), _stream(dev), n, m, _ptr(A), lda, _ptr(L), ldl, _ptr(S), lds,
+                  prec, ctypes.byref(o), _ptr(Z), z_cap, z_cap, _ptr(Dv), ctypes.byref(rank),
+                  ctypes.byref(info))
     else:
         code = fn(_lib.handle(dev), _stream(dev), n, m, _ptr(A), lda, _ptr(L), ldl, _ptr(S), lds,
                   prec, ctypes.byref(o), _ptr(Z), z_cap, z_cap, _ptr(Dv), ctypes.byref(rank),
@@ -223,6 +227,15 @@ def solve(A, L, S=None, precisions=("fp16", "fp64", "fp64", "fp64"), tol=1e-13, 
     caller workspace (uint8 CUDA tensor of at least workspace_size(...) bytes)."""
     return _solve("lyap_solve", A, L, S, precisions, tol, refine, z_cap, raise_on_error, opts,
                   ws=ws)
+
+
+def solve_static(A, L, S=None, precisions=("fp16", "fp64", "fp64", "fp64"), tol=1e-13,
+                 refine=True, z_cap=None, raise_on_error=True, **opts):
+    """lyap_solve in the library's fixed 64 MiB device scratch (lyap_solve_static): no
+    device allocation inside the call; problems needing more workspace raise TOO_LARGE.
+    Calls overlapping in time on one GPU must be serialised by the caller."""
+    return _solve("lyap_solve_static", A, L, S, precisions, tol, refine, z_cap, raise_on_error,
+                  opts)
 
 
 def refine(A, L, S, Z0, D0, precisions=("fp16", "fp64", "fp64", "fp64"), tol=1e-13,

@@ -20,7 +20,7 @@ DTYPES = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3}
 STATUS = {
     0: "OK", 1: "NOT_CONVERGED", 2: "STAGNATED", 3: "NONFINITE", 4: "SINGULAR",
     5: "NOT_STABLE", 6: "CAPACITY", 7: "BADARG", 8: "HIP_ERROR", 9: "NO_MEMORY",
-    10: "WORKSPACE",
+    10: "WORKSPACE", 11: "TOO_LARGE",
 }
 
 
@@ -95,6 +95,8 @@ _SIGS = {
                                         ctypes.POINTER(ctypes.c_size_t)]),
     "lyap_solve": (I, [P, P, I, I, P, I, P, I, P, I, Precisions, ctypes.POINTER(Options), P, I,
                        I, P, ctypes.POINTER(I), P, ctypes.c_size_t, ctypes.POINTER(Info)]),
+    "lyap_solve_static": (I, [P, P, I, I, P, I, P, I, P, I, Precisions, ctypes.POINTER(Options),
+                              P, I, I, P, ctypes.POINTER(I), ctypes.POINTER(Info)]),
     "lyap_refine": (I, [P, P, I, I, P, I, P, I, P, I, Precisions, ctypes.POINTER(Options), P, I,
                         P, I, P, I, I, P, ctypes.POINTER(I), P, ctypes.c_size_t,
                         ctypes.POINTER(Info)]),

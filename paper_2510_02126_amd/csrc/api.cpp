@@ -5,6 +5,7 @@
 #include <atomic>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <thread>
@@ -136,12 +137,16 @@ static bool valid_options(const lyap_options& o, const double* S, int lds) {
          o.delta_off >= 0 && lds >= 0;
 }
 
+// ws == NULL: the solve runs in ``own`` (grown on demand, ``epoch`` bumped on every
+// reallocation).  Otherwise in ws, whose contents are identified by ws_epoch.  With
+// ``static_max`` > 0 the workspace is the fixed scratch of lyap_solve_static: problems whose
+// workspace exceeds it are rejected, and no kernel timing events are recorded.
 static int solve_on(Solver& solver, DevBuf& own, unsigned long& epoch, hipStream_t stream,
                     int n, int m, const double* A, int lda, const double* L, int ldl,
                     const double* S, int lds, lyap_precisions prec, const lyap_options* opt,
                     const double* Z0, int ldz0, const double* D0, int r0, double* Z, int ldz,
                     int z_cap, double* D, int* rank, void* ws, size_t ws_bytes, lyap_info* info,
-                    bool adjoint) {
+                    bool adjoint, unsigned long ws_epoch = 0, size_t static_max = 0) {
   if (n <= 0 || m <= 0 || m > n || !A || !L || !Z || !D || !rank || lda < n || ldl < m ||
       z_cap < 1 || ldz < z_cap || (S && lds != 0 && lds < m))
     return LYAP_BADARG;
@@ -156,8 +161,9 @@ static int solve_on(Solver& solver, DevBuf& own, unsigned long& epoch, hipStream
   lyap_info* inf = info ? info : &local;
   std::memset(inf, 0, sizeof(*inf));
   const Layout lay = solver_layout(n, m, (Prec)prec.u_s, o);
+  if (static_max > 0 && lay.total > static_max) return inf->status = LYAP_TOO_LARGE;
   char* base = static_cast<char*>(ws);
-  unsigned long ep = 0;
+  unsigned long ep = ws_epoch;
   if (!ws) {
     if (own.bytes < lay.total) {
       ++epoch;
@@ -168,7 +174,7 @@ static int solve_on(Solver& solver, DevBuf& own, unsigned long& epoch, hipStream
     ep = epoch;
   }
   int code = solver.solve(stream, base, ws_bytes, ep, n, m, A, lda, L, ldl, S, lds, prec, o, Z0,
-                          ldz0, D0, r0, Z, ldz, z_cap, D, rank, inf, adjoint);
+                          ldz0, D0, r0, Z, ldz, z_cap, D, rank, inf, adjoint, static_max == 0);
   inf->status = code;
   return code;
 }
@@ -182,6 +188,34 @@ static int solve_impl(bool adjoint, lyap_handle h, void* stream, int n, int m, c
   return solve_on(h->solver, h->own, h->epoch, (hipStream_t)stream, n, m, A, lda, L, ldl, S, lds,
                   prec, opt, Z0, ldz0, D0, r0, Z, ldz, z_cap, D, rank, ws, ws_bytes, info,
                   adjoint);
+}
+
+// ---------------------------------------------------------------- allocation-free solve
+// The workspace of lyap_solve_static: a fixed device array, one copy per GPU, held for the
+// life of the process.  Host code uses only the per-device address returned by
+// hipGetSymbolAddress (taken once per device in lyap_create, with that device current); the
+// array's name itself is a host-side stand-in, not a device address.
+static constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+// Every static call gets a fresh epoch, so no call replays an inverse sequence another call
+// left in the shared array (the high bit keeps these apart from handle workspace epochs).
+std::atomic<unsigned long> g_scratch_epoch[kMaxDevices];
+}  // namespace
+
+static int static_scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return LYAP_BADARG;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return LYAP_OK;
+  void* ptr = nullptr;
+  if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr)
+    return LYAP_HIP_ERROR;
+  g_scratch_ptr[device] = ptr;
+  return LYAP_OK;
 }
 
 extern "C" {
@@ -199,6 +233,8 @@ const char* lyap_strerror(int code) {
     case LYAP_HIP_ERROR: return "HIP runtime error";
     case LYAP_NO_MEMORY: return "device memory allocation failed";
     case LYAP_WORKSPACE: return "workspace smaller than lyap_workspace_size() or misaligned";
+    case LYAP_TOO_LARGE:
+      return "problem needs more workspace than lyap_solve_static's 64 MiB device scratch";
     default: return "unknown status";
   }
 }
@@ -276,6 +312,12 @@ int lyap_create(lyap_handle* h, int device) {
   if (hipMalloc(&p->flags, 16 * sizeof(int)) != hipSuccess) {
     delete p;
     return LYAP_NO_MEMORY;
+  }
+  const int sc = static_scratch_init(device);
+  if (sc != LYAP_OK) {
+    (void)hipFree(p->flags);
+    delete p;
+    return sc;
   }
   *h = p;
   return LYAP_OK;
@@ -591,6 +633,19 @@ int lyap_solve(lyap_handle h, void* stream, int n, int m, const double* A, int l
                void* ws, size_t ws_bytes, lyap_info* info) {
   return solve_impl(false, h, stream, n, m, A, lda, L, ldl, S, lds, prec, opt, nullptr, 0,
                     nullptr, -1, Z, ldz, z_cap, D, rank, ws, ws_bytes, info);
+}
+
+int lyap_solve_static(lyap_handle h, void* stream, int n, int m, const double* A, int lda,
+                      const double* L, int ldl, const double* S, int lds, lyap_precisions prec,
+                      const lyap_options* opt, double* Z, int ldz, int z_cap, double* D,
+                      int* rank, lyap_info* info) {
+  if (!h || h->device < 0 || h->device >= kMaxDevices) return LYAP_BADARG;
+  void* ptr = g_scratch_ptr[h->device];
+  if (!ptr) return LYAP_HIP_ERROR;
+  const unsigned long ep = (1ul << 63) | (g_scratch_epoch[h->device].fetch_add(1) + 1);
+  return solve_on(h->solver, h->own, h->epoch, (hipStream_t)stream, n, m, A, lda, L, ldl, S, lds,
+                  prec, opt, nullptr, 0, nullptr, -1, Z, ldz, z_cap, D, rank, ptr,
+                  kStaticScratchBytes, info, false, ep, kStaticScratchBytes);
 }
 
 int lyap_refine(lyap_handle h, void* stream, int n, int m, const double* A, int lda,

@@ -136,9 +136,13 @@ Layout solver_layout(int n, int m, Prec us, const lyap_options& opt) {
   L.Gm = take(nn * 8);
   L.wv = take(cap * 8);
   const Prec inv_prec = opt.escalate ? Prec::F64 : us;
+  // scratch of one step at a time: a thin QR (qr_lead adds its Gram-Schmidt coefficients and
+  // split-K partial products, at most n^2/4 and min(2 n^2, 2^22) doubles, in front of the
+  // QR of the rest), a spectral decomposition, or an inversion
+  const size_t lead = ((nn / 4) + std::min(2 * nn, (size_t)1 << 22)) * 8 + ((size_t)1 << 16);
   L.arena_bytes = std::max(std::max(qr_workspace_bytes(n, L.cap), syev_workspace_bytes(n)),
                            syev_workspace_bytes(std::max(m, 1))) +
-                  std::max(inverse_workspace_bytes(inv_prec, n), (size_t)64 << 20);
+                  std::max(inverse_workspace_bytes(inv_prec, n), lead);
   L.arena = take(L.arena_bytes);
   L.total = off;
   return L;
@@ -751,7 +755,7 @@ int Solver::solve(hipStream_t s, char* ws, size_t ws_bytes, unsigned long ws_epo
                   const double* A, int lda, const double* L, int ldl, const double* S, int lds,
                   const lyap_precisions& prec, const lyap_options& opt, const double* Z0,
                   int ldz0, const double* D0, int r0, double* Z, int ldz, int z_cap, double* D,
-                  int* rank, lyap_info* info, bool adjoint) {
+                  int* rank, lyap_info* info, bool adjoint, bool timing) {
   const auto t_start = clk::now();
   Ctx c;
   c.s = s;
@@ -806,7 +810,7 @@ int Solver::solve(hipStream_t s, char* ws, size_t ws_bytes, unsigned long ws_epo
   c.trans = adjoint;
   c.cap = ly.cap;
   kt_.reset();
-  c.kt = &kt_;
+  c.kt = timing ? &kt_ : nullptr;
   const int cap = c.cap;
 
   // A0: S.  A diagonal S is taken as given; a full symmetric S = Q_s diag(s) Q_s^T is

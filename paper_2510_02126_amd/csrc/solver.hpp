@@ -48,7 +48,7 @@ class Solver {
             const double* A, int lda, const double* L, int ldl, const double* S, int lds,
             const lyap_precisions& prec, const lyap_options& opt, const double* Z0, int ldz0,
             const double* D0, int r0, double* Z, int ldz, int z_cap, double* D, int* rank,
-            lyap_info* info, bool adjoint);
+            lyap_info* info, bool adjoint, bool timing = true);
 
  private:
   struct Ctx;
