@@ -243,6 +243,146 @@ __global__ __launch_bounds__(NT) void gemm_k32(int M, int N, int K, double alpha
       }
 }
 
+// ------------------------------------------------------------------------- big kernel
+// 128 x 128 block tile, eight waves in a 2 x 4 grid, each wave 64 x 32 (4 x 2 MFMA tiles of
+// 16 x 16, one operand element per lane: FP64 16x16x4 or binary32 16x16x4); two waves per
+// SIMD interleave, so one wave's loads and barriers overlap the other's products.  The k-slice of
+// BK elements (BK * sizeof(MF) = 128 bytes) is double-buffered in LDS; the next slice is
+// loaded into registers while the current one feeds the matrix cores.  The LDS layout follows
+// the operand's layout in memory so that the stores are straight copies: a k-contiguous A is
+// kept as As[m][k] (row stride BK + 1, so the 16 lanes reading 16 rows at one k hit distinct
+// banks), an m-contiguous A as As[k][m]; B likewise as Bs[k][n] or Bs[n][k].
+constexpr int GBM = 128, GBN = 128, GNT = 512;
+
+template <class MF, bool KC, int BK, int BMN>
+struct LdsTile {
+  // KC: k contiguous -> [BMN][BK + 1]; otherwise [BK][BMN]
+  static constexpr int R = KC ? BMN : BK;
+  static constexpr int C = KC ? BK + 1 : BMN;
+  __device__ static inline int at(int mn, int k) { return KC ? mn * C + k : k * C + mn; }
+};
+
+template <class TA, class TB, class MF, class TC, bool AK, bool BN_>
+__global__ __launch_bounds__(GNT, 1) void gemm_big(int M, int N, int K, double alpha,
+                                                   double beta, const TA* __restrict__ A,
+                                                   long sar, long sac, const TB* __restrict__ B,
+                                                   long sbr, long sbc, TC* __restrict__ C,
+                                                   long ldc, const int* __restrict__ aexp,
+                                                   const int* __restrict__ bexp) {
+  constexpr int BK = 128 / (int)sizeof(MF);  // 16 (FP64) or 32 (binary32)
+  typedef typename Acc<MF>::V AV;
+  typedef LdsTile<MF, AK, BK, GBM> LA;
+  typedef LdsTile<MF, !BN_, BK, GBN> LB;
+  constexpr int AE = LA::R * LA::C, BE = LB::R * LB::C;
+  __shared__ MF lds[2 * (AE + BE)];
+  // per thread: (GBM * BK) / GNT = 8 (FP64) or 16 (binary32) elements of each operand
+  constexpr int PT = GBM * BK / GNT;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int m0 = blockIdx.y * GBM, n0 = blockIdx.x * GBN;
+  const int wm = (wave >> 2) * 64, wn = (wave & 3) * 32;
+
+  // global -> register slice loaders: element e of this thread, contiguous runs along the
+  // operand's unit-stride dimension
+  MF ra[PT], rb[PT];
+  auto load_a = [&](int k0) {
+#pragma unroll
+    for (int e = 0; e < PT; ++e) {
+      const int q = tid + GNT * e;
+      int mm, kk;
+      if (AK) { kk = q % BK; mm = q / BK; } else { mm = q % GBM; kk = q / GBM; }
+      const int gm = m0 + mm, gk = k0 + kk;
+      ra[e] = (gm < M && gk < K) ? Cvt<MF>::f(A[(long)gm * sar + (long)gk * sac]) : (MF)0;
+    }
+  };
+  auto load_b = [&](int k0) {
+#pragma unroll
+    for (int e = 0; e < PT; ++e) {
+      const int q = tid + GNT * e;
+      int nn, kk;
+      if (BN_) { nn = q % GBN; kk = q / GBN; } else { kk = q % BK; nn = q / BK; }
+      const int gn = n0 + nn, gk = k0 + kk;
+      rb[e] = (gn < N && gk < K)
+                  ? cvt_scaled<MF>(B[(long)gk * sbr + (long)gn * sbc], bexp ? bexp[gn] : 0)
+                  : (MF)0;
+    }
+  };
+  auto store = [&](int buf) {
+    MF* As = lds + buf * (AE + BE);
+    MF* Bs = As + AE;
+#pragma unroll
+    for (int e = 0; e < PT; ++e) {
+      const int q = tid + GNT * e;
+      int mm, kk, nn, kb;
+      if (AK) { kk = q % BK; mm = q / BK; } else { mm = q % GBM; kk = q / GBM; }
+      if (BN_) { nn = q % GBN; kb = q / GBN; } else { kb = q % BK; nn = q / BK; }
+      As[LA::at(mm, kk)] = ra[e];
+      Bs[LB::at(nn, kb)] = rb[e];
+    }
+  };
+
+  AV acc[4][2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = AV{0, 0, 0, 0};
+
+  const int nk = (K + BK - 1) / BK;
+  if (nk > 0) {
+    load_a(0);
+    load_b(0);
+    store(0);
+  }
+  __syncthreads();
+  for (int t = 0; t < nk; ++t) {
+    const int buf = t & 1;
+    if (t + 1 < nk) {
+      load_a((t + 1) * BK);
+      load_b((t + 1) * BK);
+    }
+    const MF* As = lds + buf * (AE + BE);
+    const MF* Bs = As + AE;
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 4) {
+      const int kq = ks + (lane >> 4);
+      MF a[4], b[2];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = As[LA::at(wm + 16 * i + (lane & 15), kq)];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) b[j] = Bs[LB::at(wn + 16 * j + (lane & 15), kq)];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = mfma4(a[i], b[j], acc[i][j]);
+    }
+    if (t + 1 < nk) store(buf ^ 1);
+    __syncthreads();
+  }
+  // D layout of a 16x16 tile, lane l, register r: column l % 16; row 4 r + l / 16 (FP64
+  // instruction) or 4 (l / 16) + r (binary32 instruction).
+  constexpr bool kF64 = sizeof(MF) == 8;
+  const int ea = aexp ? *aexp : 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int gn = n0 + wn + 16 * j + (lane & 15);
+      if (gn >= N) continue;
+      const int es = ea + (bexp ? bexp[gn] : 0);
+      const double al = es == 0 ? alpha : ldexp(alpha, es);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int rr = kF64 ? (4 * r + (lane >> 4)) : (4 * (lane >> 4) + r);
+        const int gm = m0 + wm + 16 * i + rr;
+        if (gm < M) {
+          TC* cp = C + (long)gm * ldc + gn;
+          double out = al * (double)acc[i][j][r];
+          if (beta != 0.0) out += beta * (double)(*cp);
+          *cp = (TC)out;
+        }
+      }
+    }
+}
+
 // Sum split-K partial products in a fixed order: C = sum_z part[z] + beta * C.
 __global__ void splitk_reduce(int M, int N, int splits, const double* __restrict__ part,
                               double beta, double* __restrict__ C, long ldc) {
@@ -255,6 +395,33 @@ __global__ void splitk_reduce(int M, int N, int splits, const double* __restrict
   double* cp = C + (long)gm * ldc + gn;
   if (beta != 0.0) s += beta * (*cp);
   *cp = s;
+}
+
+template <class TA, class TB, class MF, class TC>
+int launch_big(hipStream_t s, const GemmDesc& d) {
+  dim3 grid(ceil_div(d.N, GBN), ceil_div(d.M, GBM), 1);
+  bool ak = (d.sac == 1), bn = (d.sbc == 1);
+  auto A = static_cast<const TA*>(d.A);
+  auto B = static_cast<const TB*>(d.B);
+  auto C = static_cast<TC*>(d.C);
+#define KB(a, b)                                                                              \
+  hipLaunchKernelGGL((gemm_big<TA, TB, MF, TC, a, b>), grid, dim3(GNT), 0, s, d.M, d.N, d.K,  \
+                     d.alpha, d.beta, A, d.sar, d.sac, B, d.sbr, d.sbc, C, d.ldc, d.a_exp,    \
+                     d.b_colexp)
+  if (ak && bn) KB(true, true);
+  else if (ak) KB(true, false);
+  else if (bn) KB(false, true);
+  else KB(false, false);
+#undef KB
+  LYAP_HIP(hipGetLastError());
+  return LYAP_OK;
+}
+
+// The 128 x 128 kernel pays off once the grid has a few waves of workgroups and the k-loop a
+// few slices; smaller products keep the 64 x 64 kernel.
+inline bool use_big(const GemmDesc& d) {
+  const long tiles = (long)ceil_div(d.M, GBM) * ceil_div(d.N, GBN);
+  return d.M >= 96 && d.N >= 96 && d.K >= 32 && tiles >= 48;
 }
 
 template <class TA, class TB, class MF, class TC>
@@ -301,7 +468,9 @@ int launch_k32(hipStream_t s, const GemmDesc& d) {
 template <class TA, class TB, class TC>
 int dispatch_lp_op(hipStream_t s, Prec op, const GemmDesc& d) {
   switch (op) {
-    case Prec::F32: return launch_k4<TA, TB, float, TC>(s, d, 1, nullptr);
+    case Prec::F32:
+      if (use_big(d)) return launch_big<TA, TB, float, TC>(s, d);
+      return launch_k4<TA, TB, float, TC>(s, d, 1, nullptr);
     case Prec::F16: return launch_k32<TA, TB, _Float16, TC>(s, d);
     case Prec::BF16: return launch_k32<TA, TB, __bf16, TC>(s, d);
     default: return LYAP_BADARG;
@@ -338,7 +507,10 @@ int gemm_f64(hipStream_t s, const GemmDesc& d, double* ws, size_t ws_elems) {
     splits = std::min(splits, d.K / 256);
     while (splits > 1 && (size_t)splits * d.M * d.N > ws_elems) --splits;
   }
-  if (splits <= 1) return launch_k4<double, double, double, double>(s, d, 1, nullptr);
+  if (splits <= 1) {
+    if (use_big(d)) return launch_big<double, double, double, double>(s, d);
+    return launch_k4<double, double, double, double>(s, d, 1, nullptr);
+  }
   LYAP_TRY((launch_k4<double, double, double, double>(s, d, splits, ws)));
   long total = (long)d.M * d.N;
   hipLaunchKernelGGL(splitk_reduce, dim3((unsigned)ceil_div((int)total, 256)), dim3(256), 0, s,
