@@ -7,9 +7,13 @@ indefinite; A = Q T Q^T with Q Haar orthogonal and T upper triangular, diag(T) =
 
 One step = one complete lyap_solve call (inversions, factor iteration, residual
 factorisations, corrections and updates) that must end with res <= 1e-13; a run whose solves
-do not reach it is reported as DNF.  Prints one JSON line.
+do not reach it is reported as DNF with its attained residual.  The plain FP64 solve and IR
+with fp16, bf16 and fp32 inner solvers are timed; ``value`` is the IR with the fp16 inner
+solver (the inner precision the workload names), the others are reported beside it.  The
+first timed solve of each path is re-checked on the host: its residual (eq 4.1) recomputed
+in float64 NumPy from the returned factors.  Prints one JSON line.
 
-  python bench.py [--steps K] [--warmup W] [--us fp32] [--skip-cpu] [--batched]
+  python bench.py [--steps K] [--warmup W] [--inner fp16,bf16,fp32] [--skip-cpu] [--batched]
   python bench.py --traffic-run   (one IR solve and a calibration copy, for HBM counters)
   python bench.py --mfma-run [--us fp64]   (one solve and calibration products, for MFMA counters)
 """
@@ -26,21 +30,6 @@ sys.path.insert(0, ROOT)
 
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "fp16": 2500.0, "bf16": 2500.0}
 PEAK_HBM_GBS = 8000.0
-
-
-def _time_solves(lyap, torch, A, L, S, us, steps, warmup):
-    for _ in range(warmup):
-        lyap.solve(A, L, S, precisions=(us, "fp64", "fp64", "fp64"), raise_on_error=False)
-    torch.cuda.synchronize()
-    infos = []
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        _, _, info = lyap.solve(A, L, S, precisions=(us, "fp64", "fp64", "fp64"),
-                                raise_on_error=False)
-        infos.append(info)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    return dt, infos
 
 
 def _time_inverse(lyap, torch, A, us, reps=3):
@@ -128,50 +117,79 @@ def _mfma_run(lyap, torch, A, L, S, us):
         print("calibration matmul", dt, "flops", 2 * 4096 ** 3, float(c[0, 0]), flush=True)
 
 
-def _measured_traffic(kernel):
-    """HBM bytes per launch of ``kernel`` from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
-    summary, or None when there is none or the kernel's source changed since it was taken."""
-    import hashlib
-    import re
-
-    if kernel != "jac_round":
-        return None
-    path = os.path.join(ROOT, "profiles", "jac_round_n4096_ir_fp32_hbm_traffic.md")
-    src = os.path.join(ROOT, "paper_2510_02126_amd", "csrc", "eig.hip")
-    try:
-        text = open(path).read()
-        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    except OSError:
-        return None
-    t = re.search(r"^traffic_bytes_per_launch: (\d+)", text, re.M)
-    h = re.search(r"^eig_hip_sha256: ([0-9a-f]+)", text, re.M)
-    if not t or not h or h.group(1) != digest:
-        return None
-    return float(t.group(1))
-
-
-def _cpu_baseline(cfg, steps=6):
-    """The oracle's FP64 sign-function Newton solve (Alg 3.2) on the host cores, on a bounded
-    sample: its first ``steps`` Newton steps (inversion, scaled update, factor product), scaled
-    to the full solve by K / steps with the Newton count K taken from the GPU run."""
+def _host_relres(A, L, S, Z, D):
+    """Relative residual of eq (4.1) for X = Z diag(D) Z^T, in float64 NumPy on the host from
+    the factored form: R = F N F^T with F = [Z, AZ, L] and N = [[0, D, 0], [D, 0, 0],
+    [0, 0, S]]; with the thin QR F = U T, ||R||_F = ||T N T^T||_F (no Gram matrix, so a
+    residual near the rounding level is resolved).  ||X||_F = ||T_Z diag(D) T_Z^T||_F from
+    the QR of Z alone."""
     import numpy as np
+
+    r, m = Z.shape[1], L.shape[1]
+    F = np.hstack([Z, A @ Z, L])
+    T = np.linalg.qr(F, mode="r")
+    N = np.zeros((2 * r + m, 2 * r + m))
+    N[:r, r:2 * r] = np.diag(D)
+    N[r:2 * r, :r] = np.diag(D)
+    N[2 * r:, 2 * r:] = np.diag(S)
+    normR = np.linalg.norm(T @ N @ T.T, "fro")
+    Tz = np.linalg.qr(Z, mode="r")
+    normX = np.linalg.norm((Tz * D[None, :]) @ Tz.T, "fro")
+    Tl = np.linalg.qr(L, mode="r")
+    normW = np.linalg.norm((Tl * S[None, :]) @ Tl.T, "fro")
+    return normR / (normW + 2.0 * normX * np.linalg.norm(A, "fro"))
+
+
+def _cpu_baseline(cfg):
+    """The oracle's whole FP64 sign-function Newton solve (Alg 3.2 through the first residual
+    evaluation, oracle.refine.ir_ldlt with refine=False) of the workload on the host cores."""
     from threadpoolctl import threadpool_info
 
-    from oracle import signnewton as SN
+    from oracle import refine as IR
 
-    A, L = cfg["A"], cfg["L"]
     t0 = time.perf_counter()
-    # ``steps`` Newton steps through the oracle's own routines
-    Ak = A.copy()
-    Z = L.copy()
-    for _ in range(steps):
-        Ainv = SN.inverse_at(Ak, "fp64")
-        mu = float(np.sqrt(np.linalg.norm(Ainv, "fro") / np.linalg.norm(Ak, "fro")))
-        Ak = 0.5 * (mu * Ak + Ainv / mu)
-        Z = np.hstack([Z, Ainv @ Z])
+    _, _, info = IR.ir_ldlt(cfg["A"], cfg["L"], cfg["S"], prec=("fp64",) * 4, refine=False)
     dt = time.perf_counter() - t0
     threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [os.cpu_count()])
-    return dt / steps, threads
+    return dt, threads, info
+
+
+def _run_path(lyap, torch, cfg, A, L, S, us, steps, warmup, **opts):
+    """Time ``steps`` solves of one path; the first timed solve is re-checked on the host."""
+    prec = (us, "fp64", "fp64", "fp64")
+    for _ in range(warmup):
+        lyap.solve(A, L, S, precisions=prec, raise_on_error=False, **opts)
+    torch.cuda.synchronize()
+    infos, first = [], None
+    t0 = time.perf_counter()
+    for i in range(steps):
+        Z, D, info = lyap.solve(A, L, S, precisions=prec, raise_on_error=False, **opts)
+        infos.append(info)
+        if i == 0:
+            first = (Z, D)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    Zh, Dh = first[0].cpu().numpy(), first[1].cpu().numpy()
+    host_res = _host_relres(cfg["A"], cfg["L"], cfg["S"], Zh, Dh)
+    ok = all(i["status"] == "OK" and i["res"] <= 1e-13 for i in infos) and host_res <= 1e-13
+    last = infos[-1]
+    fam = {f: sum(i["kern_ms"][f] for i in infos) for f in range(4)}
+    work = {f: sum(i["kern_work"][f] for i in infos) for f in range(4)}
+    calls = {f: sum(i["kern_calls"][f] for i in infos) for f in range(4)}
+    return {
+        "us": us, "ok": ok, "dt": dt, "steps": steps, "infos": infos, "fam_ms": fam,
+        "fam_work": work, "fam_calls": calls,
+        "summary": {
+            "status": "OK" if ok else "DNF",
+            "solves_per_s": round(steps / dt, 4) if ok else 0.0,
+            "ms_per_solve": round(1e3 * dt / steps, 2),
+            "res": last["res"], "res_host_first": host_res, "rank": last["rank"],
+            "refinements": last["refinements"],
+            "iters": f'{last["newton_total"]}({last["newton_max"]})',
+            "inversions": last["inversions"],
+            "phase_ms": [round(x, 2) for x in last["phase_ms"]],
+        },
+    }
 
 
 def main():
@@ -179,7 +197,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--us", default="fp32", help="solver precision of the IR run")
+    ap.add_argument("--inner", default="fp16,bf16,fp32",
+                    help="inner (solver) precisions of the IR runs; the first is the headline")
+    ap.add_argument("--us", default=None, help="(untimed runs) solver precision")
+    ap.add_argument("--adaptive", default="fp16,fp32",
+                    help="inner precisions also timed with adaptive inexact inner tolerances")
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--batched", action="store_true",
                     help="also time 256 independent equations, n in [64, 512] (batched mode)")
@@ -205,93 +227,89 @@ def main():
     S = torch.from_numpy(cfg["S"]).cuda()
     n = A.shape[0]
     if args.traffic_run:
-        _traffic_run(lyap, torch, A, L, S, args.us)
+        _traffic_run(lyap, torch, A, L, S, args.us or "fp32")
         return
     if args.mfma_run:
-        _mfma_run(lyap, torch, A, L, S, args.us)
+        _mfma_run(lyap, torch, A, L, S, args.us or "fp32")
         return
 
-    # plain FP64 sign-function Newton solve (the baseline), then mixed-precision IR
-    dt64, inf64 = _time_solves(lyap, torch, A, L, S, "fp64", args.steps, args.warmup)
-    dtir, infir = _time_solves(lyap, torch, A, L, S, args.us, args.steps, args.warmup)
-    ok64 = all(i["status"] == "OK" and i["res"] <= 1e-13 for i in inf64)
-    okir = all(i["status"] == "OK" and i["res"] <= 1e-13 for i in infir)
-    sps64 = args.steps / dt64 if ok64 else 0.0
-    spsir = args.steps / dtir if okir else 0.0
+    inner = [x.strip() for x in args.inner.split(",") if x.strip()]
+    base = _run_path(lyap, torch, cfg, A, L, S, "fp64", args.steps, args.warmup)
+    print(f"fp64: {base['summary']}", file=sys.stderr, flush=True)
+    runs = {}
+    for us in inner:
+        # bf16 solves take many refinements at this condition number: one timed solve
+        st, wu = (1, 0) if us == "bf16" else (args.steps, args.warmup)
+        runs[us] = _run_path(lyap, torch, cfg, A, L, S, us, st, wu)
+        print(f"ir {us}: {runs[us]['summary']}", file=sys.stderr, flush=True)
+    adaptive = {}
+    for us in [x.strip() for x in args.adaptive.split(",") if x.strip()]:
+        adaptive[us] = _run_path(lyap, torch, cfg, A, L, S, us, args.steps, args.warmup,
+                                 adaptive=1)
+        print(f"ir {us} adaptive: {adaptive[us]['summary']}", file=sys.stderr, flush=True)
+    head = runs[inner[0]] if inner else base
+    sps64 = base["summary"]["solves_per_s"]
 
-    # roofline of the dominant kernel family of the timed IR solves, from the HIP-event
-    # accounting the library keeps per solve (summed over the timed solves)
-    fam_ms = [sum(i["kern_ms"][f] for i in infir) for f in range(4)]
-    fam_work = [sum(i["kern_work"][f] for i in infir) for f in range(4)]
-    fam_calls = [sum(i["kern_calls"][f] for i in infir) for f in range(4)]
-    fams = {
-        0: ("inversion (Gauss-Jordan leaves + MFMA block updates, 2n^3 flops)", "mfma",
-            "TFLOP/s", 1e12, PEAK_TFLOPS["fp32" if args.us == "fp32" else args.us]),
-        1: ("jac_round (Jacobi round: block rotation update of A and V, ~24 pp^2 bytes)",
-            "hbm", "GB/s", 1e9, PEAK_HBM_GBS),
-        2: ("thin QR (Householder TSQR panels + compact-WY MFMA updates)", "mfma", "TFLOP/s",
-            1e12, PEAK_TFLOPS["fp64"]),
+    # roofline of the inversion (A2, 2 n^3 flops each; the matrix-core-bound step) in the
+    # headline IR solves, from the library's HIP-event accounting on the solve's stream
+    peak = PEAK_TFLOPS[head["us"]]
+    inv_ms, inv_flops, inv_calls = head["fam_ms"][0], head["fam_work"][0], head["fam_calls"][0]
+    achieved = inv_flops / (inv_ms * 1e-3) / 1e12 if inv_ms > 0 else 0.0
+    roof = {"bound": "mfma", "kernel": "inversion (Gauss-Jordan: pivoted leaves + MFMA block "
+            f"updates), {head['us']} operands, 2 n^3 flops per inversion",
+            "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 5), "traffic": None,
+            "launches": inv_calls, "avg_launch_us": round(1e3 * inv_ms / max(1, inv_calls), 1)}
+    total_ms = 1e3 * head["dt"]
+    shares = {
+        "inversion": round(head["fam_ms"][0] / total_ms, 4),
+        "jacobi_rounds (spectral decompositions, latency-bound)": round(head["fam_ms"][1] / total_ms, 4),
+        "thin_qr (latency-bound panels + MFMA updates)": round(head["fam_ms"][2] / total_ms, 4),
     }
-    dom = max(fams, key=lambda f: fam_ms[f])
-    name, bound, unit, scale, peak = fams[dom]
-    achieved = fam_work[dom] / (fam_ms[dom] * 1e-3) / scale if fam_ms[dom] > 0 else 0.0
-    traffic = _measured_traffic(name.split(" ")[0])
-    roof = {"bound": bound, "kernel": name, "achieved": round(achieved, 3), "peak": peak,
-            "unit": unit, "frac": round(achieved / peak, 4), "traffic": traffic,
-            "launches": fam_calls[dom], "avg_launch_us": round(1e3 * fam_ms[dom] /
-                                                                max(1, fam_calls[dom]), 2)}
-    breakdown = {}
-    for f, (nm, bd, un, sc, pk) in fams.items():
-        if fam_ms[f] > 0:
-            ach = fam_work[f] / (fam_ms[f] * 1e-3) / sc
-            breakdown[nm.split(" ")[0]] = {"ms_per_solve": round(fam_ms[f] / args.steps, 2),
-                                           "achieved": round(ach, 3), "unit": un,
-                                           "frac": round(ach / pk, 4)}
+    shares["rest (products, norms, copies, host)"] = round(1.0 - sum(shares.values()), 4)
+    jac = {"achieved_GBs": round(head["fam_work"][1] / (head["fam_ms"][1] * 1e-3) / 1e9, 1)
+           if head["fam_ms"][1] > 0 else None, "peak_GBs": PEAK_HBM_GBS,
+           "launches": head["fam_calls"][1]}
     t_inv = _time_inverse(lyap, torch, A, "fp64")
     inv64 = 2.0 * n ** 3 / t_inv / 1e12
 
-    batched = _batched(lyap, torch, args.us) if args.batched else None
+    batched = _batched(lyap, torch, inner[0] if inner else "fp16") if args.batched else None
 
     cpu = None
     if not args.skip_cpu:
-        K = inf64[-1]["inversions"]
-        steps_cpu = max(1, min(6, K))
-        t_step, threads = _cpu_baseline(cfg, steps_cpu)
-        t_solve = t_step * K
-        cpu = {"value": round(1.0 / t_solve, 6), "unit": "solves/s", "cores": threads,
+        dt_cpu, threads, cinfo = _cpu_baseline(cfg)
+        cpu = {"value": round(1.0 / dt_cpu, 6), "unit": "solves/s", "cores": threads,
                "kind": "oracle",
-               "sample": f"oracle FP64 sign-Newton, first {steps_cpu} of K={K} Newton steps at "
-                         f"n={n} ({steps_cpu * t_step:.1f} s), scaled to a full solve"}
+               "sample": f"one whole oracle FP64 sign-function Newton solve of the n={n} workload "
+                         f"(Alg 3.2, K={cinfo.inversions}, first residual evaluated; "
+                         f"{dt_cpu:.1f} s on the host cores)"}
 
     line = {
         "metric": "solves/s at n=4096 to FP64-level residual: mixed-prec IR vs FP64 sign-Newton",
-        "value": round(spsir, 4),
+        "value": head["summary"]["solves_per_s"],
         "unit": "solves/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": head["steps"],
         "warmup": args.warmup,
-        "ms_per_step": round(1e3 * dtir / args.steps, 3),
+        "ms_per_step": round(1e3 * head["dt"] / head["steps"], 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": f"{args.us}-inner/f64",
+        "dtype": f"{head['us']}-inner/f64",
         "data": "synthetic",
         "config": {"workload": "n=4096, m=8, W=L S L^T indefinite, A=Q T Q^T kappa~1e3",
-                   "ir_precisions": [args.us, "fp64", "fp64", "fp64"], "tol": 1e-13},
-        "ir": {"solves_per_s": round(spsir, 4), "res": infir[-1]["res"],
-               "rank": infir[-1]["rank"], "refinements": infir[-1]["refinements"],
-               "iters": f'{infir[-1]["newton_total"]}({infir[-1]["newton_max"]})',
-               "phase_ms": [round(x, 2) for x in infir[-1]["phase_ms"]],
-               "status": "OK" if okir else "DNF"},
-        "fp64_sign_newton": {"solves_per_s": round(sps64, 4),
-                             "ms_per_solve": round(1e3 * dt64 / args.steps, 3),
-                             "res": inf64[-1]["res"], "rank": inf64[-1]["rank"],
-                             "K": inf64[-1]["inversions"],
-                             "phase_ms": [round(x, 2) for x in inf64[-1]["phase_ms"]],
-                             "status": "OK" if ok64 else "DNF"},
-        "speedup_ir_vs_fp64": round(spsir / sps64, 4) if sps64 > 0 and spsir > 0 else None,
+                   "ir_precisions": [head["us"], "fp64", "fp64", "fp64"], "tol": 1e-13},
+        "ir": {us: r["summary"] for us, r in runs.items()},
+        "fp64_sign_newton": base["summary"],
+        "speedup_vs_fp64": {us: (round(r["summary"]["solves_per_s"] / sps64, 4)
+                                 if sps64 > 0 and r["ok"] else None) for us, r in runs.items()},
+        "ir_adaptive_inner_tolerances": {
+            us: dict(r["summary"], speedup_vs_fp64=(round(r["summary"]["solves_per_s"] / sps64, 4)
+                                                    if sps64 > 0 and r["ok"] else None))
+            for us, r in adaptive.items()},
         "roofline": roof,
-        "kernel_families_ir": breakdown,
+        "time_shares_headline_ir": shares,
+        "jacobi_rounds_hbm": jac,
         "inversion_fp64_alone": {"ms": round(1e3 * t_inv, 3), "tflops": round(inv64, 3),
                                  "frac_fp64_peak": round(inv64 / PEAK_TFLOPS["fp64"], 4)},
         "cpu_baseline": cpu,

@@ -108,6 +108,17 @@ typedef struct {
                         lyap_refine when the workspace holds the sequence of the same A
                         (64-bit content fingerprint of A, n, u_s and k_max), never for
                         lyap_solve; 1 also for lyap_solve; 0 never.                          */
+  int adaptive;      /* 1: inexact inner solves with tolerances tied to the refinement (the
+                        adaptivity the Conclusions point to): each correction solve's in-solver
+                        truncation keeps |lambda| > max(u_s, eta_r / 10) max|lambda| (the
+                        residual factor is itself truncated at eta_r), and the update after a
+                        step with residual res_i keeps |sigma| >= max(eta_s, omega res_i)
+                        max|sigma|.  0 (default): the fixed thresholds of Alg 3.2 and
+                        Fragment 2.4.                                                       */
+  double omega;      /* the factor omega of the adaptive update threshold; default 0.1:
+                        directions that small are the ones the next correction fixes
+                        anyway (measured at n = 4096: fp16 inner, omega 1e-3 / 0.1 / 0.3:
+                        rank 3796 / 1071 / 289 with the same six or five refinements)   */
 } lyap_options;
 
 /* Per-solve diagnostics (Table 4.1 columns plus timings). */

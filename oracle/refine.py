@@ -184,7 +184,7 @@ def ir_ldlt(A, L, S=None, prec=("fp32", "fp64", "fp64", "fp64"), tol: float = 1e
             i_max: int = 50, k_max: int = 50, rho: float = 0.1, eta_r: float = 1e-4,
             eta_s: float | None = None, psd: bool | None = None, theta: float = 0.9,
             refine: bool = True, scaling: str = "frobenius", Z0=None, d0=None,
-            escalate: bool = False):
+            escalate: bool = False, adaptive: bool = False, omega: float = 0.1):
     """Alg 2.2 with Alg 3.2 as the solver.  ``prec`` = (u_s, u, u_r, u_c).  With
     ``refine=False`` only the first solve is made and its residual evaluated (plain
     sign-function Newton).  ``Z0``, ``d0``: start the refinement from X_0 = Z0 diag(d0) Z0^T
@@ -192,6 +192,12 @@ def ir_ldlt(A, L, S=None, prec=("fp32", "fp64", "fp64", "fp64"), tol: float = 1e
     inverse sequence is then formed only if a correction is needed.  ``escalate``: a stage
     that stagnates (eq 4.2), runs out of steps or overflows at u_s continues at the next
     precision up (Table 1.1 order, not beyond u), from the current iterate when it is valid.
+    ``adaptive``: inexact inner solves with tolerances tied to the refinement (the direction
+    the Conclusions point to): each correction solve truncates at max(u_s, eta_r / 10)
+    relative (the residual factor is itself truncated at eta_r, so a more accurate correction
+    buys nothing), and the update after a step with residual res_i keeps
+    sigma >= max(eta_s, omega res_i) max|sigma| (directions that small only change the next
+    residual by about omega res_i, far below the contraction of a refinement step).
     Returns (Z, d, info) with X ~ Z diag(d) Z^T."""
     us, u, ur, uc = prec
     A = np.asarray(A, np.float64)
@@ -252,13 +258,15 @@ def ir_ldlt(A, L, S=None, prec=("fp32", "fp64", "fp64", "fp64"), tol: float = 1e
                 e = _pow2_exponent(float(np.max(np.abs(sd))))
                 sd_s = fl(np.ldexp(sd, -e), us)
                 Zd, Yd, _, _ = sign_newton_ldlt(A, fl_scaled(Ld, us, axis=0), sd_s, us, psd=False,
-                                                rho=rho, seq=seq)
+                                                rho=rho, seq=seq,
+                                                trunc_tol=eta_r / 10.0 if adaptive else None)
                 Zd, Yd = fl(Zd, u), np.ldexp(fl(Yd, u), e)
                 info.newton_total += seq.K
                 info.newton_max = max(info.newton_max, seq.K)
                 info.refinements += 1
                 steps_left -= 1
-                Z, Y = sol_upt_ldlt(Z, Y, Zd, Yd, eta_s, uc, psd)
+                eta_i = max(eta_s, omega * res) if adaptive else eta_s
+                Z, Y = sol_upt_ldlt(Z, Y, Zd, Yd, eta_i, uc, psd)
         except NonFiniteError:
             status = "NONFINITE"
         except NotStableError:

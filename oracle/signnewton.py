@@ -254,10 +254,11 @@ def rank_trunc_chol(Z, fmt: str) -> np.ndarray:
     return fl_scaled(Znew, fmt, axis=0)
 
 
-def rank_trunc_ldlt(Z, Y, fmt: str, psd: bool):
+def rank_trunc_ldlt(Z, Y, fmt: str, psd: bool, tol: float | None = None):
     """RankTruncLdlt: Z = QR, R Y R^T = V Lambda V^T, keep lambda_i > u ||Lambda||_1
-    (|lambda_i| for an indefinite problem, signs kept); returns (Q V, Lambda)."""
-    u = unit_roundoff(fmt)
+    (|lambda_i| for an indefinite problem, signs kept); returns (Q V, Lambda).  ``tol``
+    replaces u by max(u, tol) (an inexact solve, used by adaptive refinement)."""
+    u = unit_roundoff(fmt) if tol is None else max(unit_roundoff(fmt), tol)
     Q, R = thin_qr(Z, fmt)
     M = matmul(matmul(R, Y, fmt), R.T, fmt)
     lam, V = sym_eig(M, fmt)
@@ -300,9 +301,10 @@ def sign_newton_chol(A, L, fmt: str = "fp64", rho: float = 0.1, k_max: int = 50,
 
 
 def sign_newton_ldlt(A, L, S, fmt: str = "fp64", psd: bool = True, rho: float = 0.1,
-                     k_max: int = 50, seq: ASequence | None = None):
+                     k_max: int = 50, seq: ASequence | None = None,
+                     trunc_tol: float | None = None):
     """Alg 3.2.  ``S`` is m x m (or a 1-D diagonal).  Returns (Z, Y, seq, info) with
-    X ~ Z Y Z^T."""
+    X ~ Z Y Z^T.  ``trunc_tol``: RankTruncLdlt threshold max(u, trunc_tol) instead of u."""
     A = np.asarray(A, np.float64)
     n = A.shape[0]
     if seq is None:
@@ -316,7 +318,7 @@ def sign_newton_ldlt(A, L, S, fmt: str = "fp64", psd: bool = True, rho: float = 
         Z = np.hstack([Z, matmul(Ainv, Z, fmt)])
         Y = fl_scaled(0.5 * sla.block_diag(mu * Y, Y / mu), fmt, axis=0)
         if Z.shape[1] > cap:
-            Z, Y = rank_trunc_ldlt(Z, Y, fmt, psd)
+            Z, Y = rank_trunc_ldlt(Z, Y, fmt, psd, trunc_tol)
             ntr += 1
         cols.append(Z.shape[1])
     Y = fl_scaled(Y / 2.0, fmt, axis=0)

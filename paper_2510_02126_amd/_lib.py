@@ -41,7 +41,8 @@ class Options(ctypes.Structure):
                 ("rho", ctypes.c_double), ("eta_r", ctypes.c_double), ("eta_s", ctypes.c_double),
                 ("delta_off", ctypes.c_double), ("theta", ctypes.c_double),
                 ("refine", ctypes.c_int), ("psd", ctypes.c_int), ("form", ctypes.c_int),
-                ("scaling", ctypes.c_int), ("escalate", ctypes.c_int), ("reuse", ctypes.c_int)]
+                ("scaling", ctypes.c_int), ("escalate", ctypes.c_int), ("reuse", ctypes.c_int),
+                ("adaptive", ctypes.c_int), ("omega", ctypes.c_double)]
 
 
 class Info(ctypes.Structure):

@@ -134,7 +134,8 @@ static bool valid_options(const lyap_options& o, const double* S, int lds) {
          o.rho > 0 && o.eta_r >= 0 && o.theta > 0 && (o.form == 0 || o.form == 1) &&
          !(o.form == 1 && S != nullptr) && o.scaling >= 0 && o.scaling <= 3 &&
          (o.escalate == 0 || o.escalate == 1) && o.reuse >= -1 && o.reuse <= 1 &&
-         o.delta_off >= 0 && lds >= 0;
+         o.delta_off >= 0 && lds >= 0 && (o.adaptive == 0 || o.adaptive == 1) &&
+         o.omega >= 0;
 }
 
 // ws == NULL: the solve runs in ``own`` (grown on demand, ``epoch`` bumped on every
@@ -257,6 +258,8 @@ void lyap_default_options(lyap_options* o) {
   o->scaling = 0;
   o->escalate = 0;
   o->reuse = -1;
+  o->adaptive = 0;
+  o->omega = 0.1;
 }
 
 int lyap_workspace_size(int n, int m, int u_s, const lyap_options* opt, size_t* bytes) {

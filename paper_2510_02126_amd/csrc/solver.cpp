@@ -407,14 +407,15 @@ int Solver::rank_trunc(Ctx& c, double* Zb, long ldb, int& cols, std::vector<doub
 
 // ------------------------------------------------------------------ factor iteration
 // eq (3.3): Z_k = [Z_{k-1}, A_{k-1}^{-1} Z_{k-1}], D_k = (mu D, D / mu) / 2, truncating
-// whenever the column count exceeds floor(rho n); finally D <- D / 2.  The products use the
+// whenever the column count exceeds floor(rho n) (threshold max(u_s, trunc_thr) relative);
+// finally D <- D / 2.  The products use the
 // cached inverses with operands at the solver precision: the cache holds 2^-e_k A_k^-1 and each
 // column j of Z enters as 2^-f_j Z_:j rounded once to u_s, both scales undone exactly in the
 // product.  Result in Zs (n x cols); the first ``orth0`` columns of L0 are orthonormal, and
 // c.orth tells the same of the result.
 int Solver::factor_iteration(Ctx& c, const double* L0, long ld0, int m0, int orth0,
                              const std::vector<double>& d0, bool psd, int& cols,
-                             std::vector<double>& d) {
+                             std::vector<double>& d, double trunc_thr) {
   hipStream_t s = c.s;
   const int n = c.n, cap = c.cap;
   double* Zs = c.Zs;
@@ -451,7 +452,7 @@ int Solver::factor_iteration(Ctx& c, const double* L0, long ld0, int m0, int ort
     }
     cols = 2 * c0;
     if (cols > trunc_at)
-      LYAP_TRY(rank_trunc(c, Zs, cap, cols, d, unit_roundoff(c.us), psd));
+      LYAP_TRY(rank_trunc(c, Zs, cap, cols, d, std::max(unit_roundoff(c.us), trunc_thr), psd));
   }
   for (double& x : d) x *= 0.5;
   return LYAP_OK;
@@ -689,7 +690,11 @@ int Solver::refine_loop(Ctx& c, int& cols, std::vector<double>& d, int steps, in
     t0 = clk::now();
     LYAP_TRY(res_factor(c, rd, sd));
     info->phase_ms[4] += ms_since(t0);
-    // correction equation(s) at the solver precision, reusing the cached inverses
+    // correction equation(s) at the solver precision, reusing the cached inverses; with
+    // adaptive tolerances the correction is truncated at eta_r / 10 (its right-hand side is
+    // itself truncated at eta_r) and the update at omega res_i
+    const double inner_thr = c.opt.adaptive ? c.opt.eta_r / 10.0 : 0.0;
+    const double eta_i = c.opt.adaptive ? std::max(eta_s, c.opt.omega * res) : eta_s;
     t0 = clk::now();
     int cd = 0;
     std::vector<double> dd;
@@ -700,7 +705,8 @@ int Solver::refine_loop(Ctx& c, int& cols, std::vector<double>& d, int steps, in
       if (rd > 0) std::frexp(std::fabs(sd[0]), &e);
       std::vector<double> sds(sd);
       for (double& x : sds) x = std::ldexp(x, -e);
-      LYAP_TRY(factor_iteration(c, c.Zd, cap, rd, rd, sds, false, cd, dd));  // U Q_t
+      LYAP_TRY(factor_iteration(c, c.Zd, cap, rd, rd, sds, false, cd, dd,
+                                inner_thr));  // U Q_t
       for (double& x : dd) x = std::ldexp(x, e);
     } else {
       // Fragment 2.1: R = L+ L+^T - L- L-^T with L+- = U Q_+- |Lambda_+-|^(1/2), here as
@@ -724,9 +730,9 @@ int Solver::refine_loop(Ctx& c, int& cols, std::vector<double>& d, int steps, in
       }
       int cp = 0, cm = 0;
       std::vector<double> ddp, ddm;
-      LYAP_TRY(factor_iteration(c, Fb, cap, rp, rp, dp, true, cp, ddp));
+      LYAP_TRY(factor_iteration(c, Fb, cap, rp, rp, dp, true, cp, ddp, inner_thr));
       LYAP_TRY(copy_block(s, n, cp, c.Zs, cap, Zpm, cap));
-      LYAP_TRY(factor_iteration(c, Fb + rp, cap, rm, rm, dm, true, cm, ddm));
+      LYAP_TRY(factor_iteration(c, Fb + rp, cap, rm, rm, dm, true, cm, ddm, inner_thr));
       if (cp + cm > cap) return LYAP_CAPACITY;
       LYAP_TRY(copy_block(s, n, cm, c.Zs, cap, Zpm + cp, cap));
       cd = cp + cm;
@@ -744,7 +750,7 @@ int Solver::refine_loop(Ctx& c, int& cols, std::vector<double>& d, int steps, in
     info->refinements += 1;
     // projected solution update (Fragment 2.4; Fragment 2.2 for the Cholesky type)
     t0 = clk::now();
-    LYAP_TRY(sol_upt(c, cols, d, Zcor, cd, dd, eta_s, c.psd));
+    LYAP_TRY(sol_upt(c, cols, d, Zcor, cd, dd, eta_i, c.psd));
     info->phase_ms[5] += ms_since(t0);
   }
   return LYAP_OK;

@@ -57,7 +57,7 @@ class Solver {
   int refine_loop(Ctx& c, int& cols, std::vector<double>& d, int steps, int& status);
   int factor_iteration(Ctx& c, const double* L0, long ld0, int m0, int orth0,
                        const std::vector<double>& d0, bool psd, int& cols,
-                       std::vector<double>& d);
+                       std::vector<double>& d, double trunc_thr = 0.0);
   int rank_trunc(Ctx& c, double* Zb, long ldb, int& cols, std::vector<double>& d, double thr,
                  bool psd);
   int xnorm(Ctx& c, const double* Zb, long ldb, int cols, const std::vector<double>& d,

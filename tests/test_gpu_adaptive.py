@@ -1,0 +1,47 @@
+"""Adaptive inexact inner tolerances (lyap_options.adaptive) on the GPU against the oracle's
+same rule: each correction truncated at max(u_s, eta_r / 10), each update at
+max(eta_s, omega res_i).  Both reach tau_I; refinement counts agree within one; the factor is
+not larger than with the fixed thresholds of Alg 3.2 / Fragment 2.4."""
+import numpy as np
+import pytest
+import torch
+
+import lyapgen
+from oracle import exact as E
+from oracle import refine as IR
+from oracle import residual as R
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lyap():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2510_02126_amd as m
+    return m
+
+
+def _cuda(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+@pytest.mark.parametrize("us", ["fp32", "fp16"])
+def test_adaptive_matches_oracle(lyap, us):
+    A, L, Q, T = lyapgen.schur_family(3, 300, 4, lo=-3.0, upper_std_scale=0.003)
+    X = E.schur_solve(Q, T, L @ L.T)
+    prec = (us, "fp64", "fp64", "fp64")
+    print(f"adaptive n=300 {us}", flush=True)
+    Zf, Df, fixed = lyap.solve(_cuda(A), _cuda(L), None, precisions=prec)
+    Z, D, info = lyap.solve(_cuda(A), _cuda(L), None, precisions=prec, adaptive=1)
+    _, _, io = IR.ir_ldlt(A, L, None, prec=prec, adaptive=True)
+    Z, D = Z.cpu().numpy(), D.cpu().numpy()
+    res = R.relres(A, L, None, Z, D)
+    err = np.linalg.norm((Z * D) @ Z.T - X) / np.linalg.norm(X)
+    print(f"  gpu {info['status']} res={res:.2e} err={err:.2e} rank={info['rank']} (fixed "
+          f"{fixed['rank']}) refinements={info['refinements']}; oracle rank={io.rank} "
+          f"refinements={io.refinements}", flush=True)
+    assert info["status"] == "OK" and res <= 1e-13
+    assert err <= 1e-10
+    assert abs(info["refinements"] - io.refinements) <= 1
+    assert info["rank"] <= 1.05 * fixed["rank"] + 2

@@ -150,3 +150,25 @@ def test_full_symmetric_s_equals_its_diagonalisation():
     assert info.status == "OK"
     assert _rel((Z * d) @ Z.T, X) <= 1e-10
     assert R.relres_dense(A, L @ S @ L.T, (Z * d) @ Z.T) <= 1e-13
+
+
+# ------------------------------------------------------------- adaptive inner tolerances
+@pytest.mark.parametrize("us", ["fp32", "fp16"])
+def test_adaptive_tolerances_keep_the_accuracy_and_not_the_rank(us):
+    # Inexact inner solves (Conclusions): the correction truncated at eta_r/10 and the update
+    # at omega res_i still reach tau_I, the solution is as accurate, and the factor is not
+    # larger than with the fixed thresholds (up to the rounding path: a few columns)
+    A, L, Q, T = lyapgen.schur_family(3, 200, 4, lo=-3.0, upper_std_scale=0.003)
+    X = E.schur_solve(Q, T, L @ L.T)
+    Zf, df, fixed = IR.ir_ldlt(A, L, None, prec=(us, "fp64", "fp64", "fp64"))
+    Za, da, adapt = IR.ir_ldlt(A, L, None, prec=(us, "fp64", "fp64", "fp64"), adaptive=True,
+                               omega=1e-3)
+    assert fixed.status == adapt.status == "OK"
+    assert R.relres(A, L, None, Za, da) <= 1e-13
+    assert adapt.rank <= 1.05 * fixed.rank + 2
+    assert _rel((Za * da) @ Za.T, X) <= 1e-10
+    # the update threshold follows the residual: a larger omega drops more
+    Zb, db, loose = IR.ir_ldlt(A, L, None, prec=(us, "fp64", "fp64", "fp64"), adaptive=True,
+                               omega=1e-1)
+    assert loose.status == "OK" and loose.rank < fixed.rank
+    assert R.relres(A, L, None, Zb, db) <= 1e-13
