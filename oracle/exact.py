@@ -59,13 +59,27 @@ def _triangular_recurrence(T, C, conj: bool):
     return Y
 
 
-def bartels_stewart(A, W) -> np.ndarray:
-    """Bartels-Stewart on the complex Schur form of A (general real A)."""
+def _triangular_sylvester(T, C):
+    """Solve T Y + Y T^H + C = 0 for upper triangular complex T with LAPACK's ztrsyl, which
+    runs the same back-substitution as ``_triangular_recurrence`` in blocked compiled code
+    (T Y + Y B = scale * (-C) with B = T^H, i.e. trana = 'N', tranb = 'C')."""
+    Y, scale, info = sla.lapack.ztrsyl(T, T, -C, trana="N", tranb="C", isgn=1)
+    if info < 0:
+        raise ValueError(f"ztrsyl argument {-info} invalid")
+    return Y / scale
+
+
+def bartels_stewart(A, W, recurrence: bool | None = None) -> np.ndarray:
+    """Bartels-Stewart on the complex Schur form of A (general real A).  The triangular
+    equation is solved column by column (``_triangular_recurrence``) for n <= 512, and by
+    LAPACK's ztrsyl (the same back-substitution) above that or with recurrence=False."""
     A = np.asarray(A, np.float64)
     W = np.asarray(W, np.float64)
     T, U = sla.schur(A, output="complex")
     C = U.conj().T @ W @ U
-    Y = _triangular_recurrence(T, C, conj=True)
+    if recurrence is None:
+        recurrence = A.shape[0] <= 512
+    Y = _triangular_recurrence(T, C, conj=True) if recurrence else _triangular_sylvester(T, C)
     X = (U @ Y @ U.conj().T).real
     return 0.5 * (X + X.T)
 

@@ -21,15 +21,34 @@ from __future__ import annotations
 
 import numpy as np
 
-FORMATS = ("fp64", "fp32", "fp16", "bf16")
+FORMATS = ("fp64", "fp32", "fp16", "bf16", "fp16x2")
+
+# The split-operand format "fp16x2" (not in the paper; the hi/lo operand splitting of
+# Markidis et al. 2018 and Ootomo and Yokota 2022): a value is held as a pair of binary16
+# numbers, x ~ hi + 2^-11 lo with hi = fl16(x) and lo = fl16(2^11 (x - hi)), so products
+# on binary16 matrix cores, hi*hi + 2^-11 (hi*lo + lo*hi) accumulated in binary32, approach
+# binary32 accuracy.  22 significand bits: unit roundoff 2^-22.
+SPLIT = 2.0 ** 11
 
 # (t, e) from Table 1.1: significand bits including the implicit bit, exponent bits.
 _BITS = {"bf16": (8, 8), "fp16": (11, 5), "fp32": (24, 8), "fp64": (53, 11)}
 
 
 def unit_roundoff(fmt: str) -> float:
-    """u = 2^-t (Table 1.1): bf16 3.91e-3, fp16 4.88e-4, fp32 5.96e-8, fp64 1.11e-16."""
+    """u = 2^-t (Table 1.1): bf16 3.91e-3, fp16 4.88e-4, fp32 5.96e-8, fp64 1.11e-16; the
+    split format fp16x2 2^-22."""
+    if fmt == "fp16x2":
+        return 2.0 ** -22
     return 2.0 ** (-_BITS[fmt][0])
+
+
+def split16(x):
+    """(hi, lo) with hi = fl16(x), lo = fl16(2^11 (x - hi)): x ~ hi + 2^-11 lo."""
+    x = np.asarray(x, dtype=np.float64)
+    with np.errstate(over="ignore", invalid="ignore"):
+        hi = x.astype(np.float16).astype(np.float64)
+        lo = (SPLIT * (x - hi)).astype(np.float16).astype(np.float64)
+    return hi, lo
 
 
 def x_max(fmt: str) -> float:
@@ -81,6 +100,9 @@ def fl(x, fmt: str) -> np.ndarray:
             return x.astype(np.float16).astype(np.float64)
     if fmt == "bf16":
         return _bf16_round(x)
+    if fmt == "fp16x2":
+        hi, lo = split16(x)
+        return hi + lo / SPLIT
     raise ValueError(f"unknown format {fmt!r}")
 
 
@@ -133,6 +155,14 @@ def matmul(a, b, fmt: str) -> np.ndarray:
             return fl(fl(a, fmt) @ fl(b, fmt), fmt)
     ea = _scale_exponents(a, None)
     eb = _scale_exponents(b, 0) if b.ndim == 2 else _scale_exponents(b[:, None], 0)[0]
+    if fmt == "fp16x2":
+        # three binary16 products, hi*hi and the two cross terms, each summed in binary32
+        ah, al = (v.astype(np.float32) for v in split16(np.ldexp(a, -ea)))
+        bh, bl = (v.astype(np.float32) for v in split16(np.ldexp(b, -eb)))
+        hh = (ah @ bh).astype(np.float64)
+        cross = (ah @ bl + al @ bh).astype(np.float64)
+        prod = np.ldexp(hh + cross / SPLIT, ea + eb)
+        return fl_scaled(prod, fmt, axis=0 if prod.ndim == 2 else None)
     a32 = fl(np.ldexp(a, -ea), fmt).astype(np.float32)
     b32 = fl(np.ldexp(b, -eb), fmt).astype(np.float32)
     prod = np.ldexp((a32 @ b32).astype(np.float64), ea + eb)

@@ -59,3 +59,16 @@ def test_loss_is_quadratic_form_of_solution():
     X = exact.kron_solve(A, exact.form_w(L, None))
     assert adjoint.trace_loss(A, L, None, C) == pytest.approx(
         sum(c @ X @ c for c in C), rel=1e-12)
+
+
+def test_gradient_golden_n2048_matches_central_differences():
+    # tests/golden/grad_n2048.json holds the oracle's adjoint gradient at the n = 2048
+    # gradient workload and central differences (step 1e-6) of its exact loss along four
+    # unit-Frobenius directions; they agree to the differences' error budget, normwise
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "grad_n2048.json")))
+    scale = np.hypot(g["dA_fro"], g["dL_fro"])
+    for dd, fd in zip(g["directional"], g["central_difference"]):
+        assert abs(dd - fd) <= 1e-8 * scale
+    assert g["n"] == 2048 and g["fd_step"] == 1e-6

@@ -94,3 +94,17 @@ def test_planted_transpose_mistake_is_caught():
     W = L @ L.T
     X_wrong = sla.solve_sylvester(A, A, -W)
     assert R.relres_dense(A, W, X_wrong) > 1e-6
+
+
+def test_bartels_stewart_lapack_triangular_step_equals_recurrence():
+    # the ztrsyl path (used above n = 512) and the column recurrence give the same solution
+    import lyapgen
+    from oracle import exact as E
+    A, L = lyapgen.random_shift(9, 150, 3)
+    W = L @ L.T
+    a = E.bartels_stewart(A, W, recurrence=True)
+    b = E.bartels_stewart(A, W, recurrence=False)
+    assert np.linalg.norm(a - b) <= 1e-13 * np.linalg.norm(a)
+    X = E.kron_solve(A[:40, :40], W[:40, :40])
+    assert np.linalg.norm(E.bartels_stewart(A[:40, :40], W[:40, :40], recurrence=False) - X) \
+        <= 1e-12 * np.linalg.norm(X)
