@@ -53,9 +53,15 @@ enum {
                              64 MiB device scratch                                          */
 };
 
-/* Arithmetic formats of Table 1.1.  Order of "precision" (larger unit roundoff first):
- * BF16 > F16 > F32 > F64. */
-typedef enum { LYAP_F64 = 0, LYAP_F32 = 1, LYAP_F16 = 2, LYAP_BF16 = 3 } lyap_dtype;
+/* Arithmetic formats of Table 1.1, and the split-operand binary16 format F16X2 (not in the
+ * paper: x ~ hi + 2^-11 lo with hi, lo binary16, products hi*hi + 2^-11 (hi*lo + lo*hi) on
+ * the binary16 matrix cores with binary32 sums; 22 significand bits, unit roundoff 2^-22;
+ * the operand splitting of Markidis et al. 2018 and Ootomo and Yokota 2022), usable as a
+ * solver precision u_s.  Order of "precision" (larger unit roundoff first):
+ * BF16 > F16 > F16X2 > F32 > F64. */
+typedef enum {
+  LYAP_F64 = 0, LYAP_F32 = 1, LYAP_F16 = 2, LYAP_BF16 = 3, LYAP_F16X2 = 4
+} lyap_dtype;
 
 /* Precisions of Alg 2.1/2.2: solver u_s, working u, residual factorisation u_r and solution
  * update u_c, with u_s >= u >= u_r, u_c in unit roundoff (Table 1.1).  Supported: u = F64

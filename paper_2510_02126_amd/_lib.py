@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblyap.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "lyap.h")
 
-DTYPES = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3}
+DTYPES = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3, "fp16x2": 4}
 
 STATUS = {
     0: "OK", 1: "NOT_CONVERGED", 2: "STAGNATED", 3: "NONFINITE", 4: "SINGULAR",

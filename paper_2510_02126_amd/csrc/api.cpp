@@ -114,7 +114,7 @@ struct lyap_handle_s {
   std::vector<std::unique_ptr<BatchWorker>> workers;  // batched solves
 };
 
-static bool valid_dtype(int d) { return d >= LYAP_F64 && d <= LYAP_BF16; }
+static bool valid_dtype(int d) { return d >= LYAP_F64 && d <= LYAP_F16X2; }
 
 static double uroff(int d) { return unit_roundoff((Prec)d); }
 

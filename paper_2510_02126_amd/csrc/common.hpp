@@ -40,7 +40,9 @@ template <> __device__ inline __bf16 rne_from_f64<__bf16>(double x) {
 }
 
 // Operand formats of the matrix-core products.
-enum class Prec : int { F64 = LYAP_F64, F32 = LYAP_F32, F16 = LYAP_F16, BF16 = LYAP_BF16 };
+enum class Prec : int {
+  F64 = LYAP_F64, F32 = LYAP_F32, F16 = LYAP_F16, BF16 = LYAP_BF16, F16X2 = LYAP_F16X2
+};
 
 inline double unit_roundoff(Prec p) {
   switch (p) {
@@ -48,6 +50,7 @@ inline double unit_roundoff(Prec p) {
     case Prec::F32: return 5.960464477539063e-08;    // 2^-24
     case Prec::F16: return 4.8828125e-04;            // 2^-11
     case Prec::BF16: return 3.90625e-03;             // 2^-8
+    case Prec::F16X2: return 2.384185791015625e-07;  // 2^-22: hi + 2^-11 lo, two binary16
   }
   return 0.0;
 }

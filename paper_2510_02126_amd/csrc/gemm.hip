@@ -11,6 +11,7 @@
 // zero-padded in LDS.  FP64 products can split K across blocks, with a deterministic
 // second pass that sums the partial products in a fixed order.
 #include <algorithm>
+#include <type_traits>
 
 #include "common.hpp"
 
@@ -383,6 +384,114 @@ __global__ __launch_bounds__(GNT, 1) void gemm_big(int M, int N, int K, double a
     }
 }
 
+// ------------------------------------------------------------------- split kernel
+// Split-operand binary16 products (the hi/lo operand splitting of Markidis et al. 2018 and
+// Ootomo and Yokota 2022): each operand element x is loaded as the pair hi = RNE16(x),
+// lo = RNE16(2^11 (x - hi)), so x ~ hi + 2^-11 lo with 22 significand bits, and
+// A B ~ Ah Bh + 2^-11 (Ah Bl + Al Bh): three 16x16x32 binary16 MFMAs per tile step, the
+// hi*hi and cross sums in separate binary32 accumulators.  Tiles as in gemm_k32.
+template <class S> __device__ inline void split16(S x, _Float16& hi, _Float16& lo);
+template <> __device__ inline void split16<double>(double x, _Float16& hi, _Float16& lo) {
+  hi = rne_from_f64<_Float16>(x);
+  lo = rne_from_f64<_Float16>((x - (double)(float)hi) * 2048.0);
+}
+template <> __device__ inline void split16<float>(float x, _Float16& hi, _Float16& lo) {
+  hi = (_Float16)x;
+  lo = (_Float16)((x - (float)hi) * 2048.0f);  // x - hi is exact in binary32
+}
+
+template <class TA, class TB, class TC, bool AK, bool BN_>
+__global__ __launch_bounds__(NT) void gemm_k32s(int M, int N, int K, double alpha, double beta,
+                                                const TA* __restrict__ A, long sar, long sac,
+                                                const TB* __restrict__ B, long sbr, long sbc,
+                                                TC* __restrict__ C, long ldc,
+                                                const int* __restrict__ aexp,
+                                                const int* __restrict__ bexp) {
+  constexpr int BK = 32, PK = BK + 8;
+  typedef _Float16 MF;
+  typedef f16x8 VT;
+  __shared__ __attribute__((aligned(16))) MF AsH[BM][PK];
+  __shared__ __attribute__((aligned(16))) MF AsL[BM][PK];
+  __shared__ __attribute__((aligned(16))) MF BsH[BN][PK];
+  __shared__ __attribute__((aligned(16))) MF BsL[BN][PK];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  f32x4 hh[2][2], xx[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      hh[i][j] = f32x4{0, 0, 0, 0};
+      xx[i][j] = f32x4{0, 0, 0, 0};
+    }
+  for (int k0 = 0; k0 < K; k0 += BK) {
+#pragma unroll
+    for (int r = 0; r < (BM * BK) / NT; ++r) {
+      int e = tid + NT * r;
+      int kk, mm;
+      if (AK) { kk = e % BK; mm = e / BK; } else { mm = e % BM; kk = e / BM; }
+      int gm = m0 + mm, gk = k0 + kk;
+      MF h = (MF)0.0f, l = (MF)0.0f;
+      if (gm < M && gk < K) split16<TA>(A[(long)gm * sar + (long)gk * sac], h, l);
+      AsH[mm][kk] = h;
+      AsL[mm][kk] = l;
+    }
+#pragma unroll
+    for (int r = 0; r < (BN * BK) / NT; ++r) {
+      int e = tid + NT * r;
+      int kk, nn;
+      if (BN_) { nn = e % BN; kk = e / BN; } else { kk = e % BK; nn = e / BK; }
+      int gn = n0 + nn, gk = k0 + kk;
+      MF h = (MF)0.0f, l = (MF)0.0f;
+      if (gn < N && gk < K) {
+        TB v = B[(long)gk * sbr + (long)gn * sbc];
+        if (bexp && bexp[gn] != 0) v = (TB)ldexp((double)v, -bexp[gn]);
+        split16<TB>(v, h, l);
+      }
+      BsH[nn][kk] = h;
+      BsL[nn][kk] = l;
+    }
+    __syncthreads();
+    const int kq = 8 * (lane >> 4);
+    VT ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      ah[i] = *reinterpret_cast<const VT*>(&AsH[wm + 16 * i + (lane & 15)][kq]);
+      al[i] = *reinterpret_cast<const VT*>(&AsL[wm + 16 * i + (lane & 15)][kq]);
+      bh[i] = *reinterpret_cast<const VT*>(&BsH[wn + 16 * i + (lane & 15)][kq]);
+      bl[i] = *reinterpret_cast<const VT*>(&BsL[wn + 16 * i + (lane & 15)][kq]);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        hh[i][j] = mfma32(ah[i], bh[j], hh[i][j]);
+        xx[i][j] = mfma32(ah[i], bl[j], xx[i][j]);
+        xx[i][j] = mfma32(al[i], bh[j], xx[i][j]);
+      }
+    __syncthreads();
+  }
+  const int ea = aexp ? *aexp : 0;
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        int gm = m0 + wm + ti * 16 + 4 * (lane >> 4) + i;
+        int gn = n0 + wn + tj * 16 + (lane & 15);
+        if (gm < M && gn < N) {
+          TC* cp = C + (long)gm * ldc + gn;
+          const int es = ea + (bexp ? bexp[gn] : 0);
+          const double v = (double)hh[ti][tj][i] + (double)xx[ti][tj][i] * (1.0 / 2048.0);
+          double out = (es == 0 ? alpha : ldexp(alpha, es)) * v;
+          if (beta != 0.0) out += beta * (double)(*cp);
+          *cp = (TC)out;
+        }
+      }
+}
+
 // Sum split-K partial products in a fixed order: C = sum_z part[z] + beta * C.
 __global__ void splitk_reduce(int M, int N, int splits, const double* __restrict__ part,
                               double beta, double* __restrict__ C, long ldc) {
@@ -466,6 +575,26 @@ int launch_k32(hipStream_t s, const GemmDesc& d) {
 }
 
 template <class TA, class TB, class TC>
+int launch_k32s(hipStream_t s, const GemmDesc& d) {
+  dim3 grid(ceil_div(d.N, BN), ceil_div(d.M, BM), 1);
+  bool ak = (d.sac == 1), bn = (d.sbc == 1);
+  auto A = static_cast<const TA*>(d.A);
+  auto B = static_cast<const TB*>(d.B);
+  auto C = static_cast<TC*>(d.C);
+#define KS(a, b)                                                                              \
+  hipLaunchKernelGGL((gemm_k32s<TA, TB, TC, a, b>), grid, dim3(NT), 0, s, d.M, d.N, d.K,      \
+                     d.alpha, d.beta, A, d.sar, d.sac, B, d.sbr, d.sbc, C, d.ldc, d.a_exp,    \
+                     d.b_colexp)
+  if (ak && bn) KS(true, true);
+  else if (ak) KS(true, false);
+  else if (bn) KS(false, true);
+  else KS(false, false);
+#undef KS
+  LYAP_HIP(hipGetLastError());
+  return LYAP_OK;
+}
+
+template <class TA, class TB, class TC>
 int dispatch_lp_op(hipStream_t s, Prec op, const GemmDesc& d) {
   switch (op) {
     case Prec::F32:
@@ -473,6 +602,11 @@ int dispatch_lp_op(hipStream_t s, Prec op, const GemmDesc& d) {
       return launch_k4<TA, TB, float, TC>(s, d, 1, nullptr);
     case Prec::F16: return launch_k32<TA, TB, _Float16, TC>(s, d);
     case Prec::BF16: return launch_k32<TA, TB, __bf16, TC>(s, d);
+    case Prec::F16X2:
+      if constexpr ((std::is_same<TA, double>::value || std::is_same<TA, float>::value) &&
+                    (std::is_same<TB, double>::value || std::is_same<TB, float>::value))
+        return launch_k32s<TA, TB, TC>(s, d);
+      return LYAP_BADARG;
     default: return LYAP_BADARG;
   }
 }

@@ -55,12 +55,15 @@ double ms_since(clk::time_point t0) {
   return std::chrono::duration<double, std::milli>(clk::now() - t0).count();
 }
 
+// Storage of values held at a precision (the split format keeps binary32 values and splits
+// them as they are loaded into a product).
 Store store_of(Prec p) {
   switch (p) {
     case Prec::F64: return Store::F64;
     case Prec::F32: return Store::F32;
     case Prec::F16: return Store::F16;
     case Prec::BF16: return Store::BF16;
+    case Prec::F16X2: return Store::F32;
   }
   return Store::F64;
 }
@@ -69,7 +72,8 @@ size_t store_bytes(Store s) {
   return s == Store::F64 ? 8 : (s == Store::F32 ? 4 : 2);
 }
 
-// Next precision up in unit roundoff (Table 1.1): bf16 -> fp16 -> fp32 -> fp64.
+// Next precision up for escalation (Table 1.1): bf16 -> fp16 -> fp32 -> fp64 (the split
+// format escalates to fp32).
 Prec next_up(Prec p) {
   switch (p) {
     case Prec::BF16: return Prec::F16;

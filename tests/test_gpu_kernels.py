@@ -53,6 +53,25 @@ def test_gemm_f64(lyap, M, N, K, ta, tb):
     assert np.abs(got - ref).max() <= 1e-14 * scale
 
 
+@pytest.mark.parametrize("M,N,K,ta,tb", [(67, 45, 33, False, False), (128, 96, 160, True, False),
+                                         (50, 130, 70, False, True), (300, 260, 1000, False, False)])
+def test_gemm_split_fp16(lyap, M, N, K, ta, tb):
+    # split binary16 operands (hi + 2^-11 lo): each operand is carried to 2^-22, the three
+    # products are summed in binary32
+    print(f"gemm_fp16x2 M={M} N={N} K={K} ta={ta} tb={tb}", flush=True)
+    rng = np.random.default_rng(K + 1)
+    A = rng.standard_normal((K, M) if ta else (M, K))
+    B = rng.standard_normal((N, K) if tb else (K, N))
+    opA = (lambda X: X.T) if ta else (lambda X: X)
+    opB = (lambda X: X.T) if tb else (lambda X: X)
+    got = lyap.gemm(_cuda(A), _cuda(B), transa=ta, transb=tb, dtype="fp16x2").cpu().numpy()
+    absprod = np.abs(opA(A)) @ np.abs(opB(B))
+    err = np.abs(got - opA(A) @ opB(B))
+    assert np.all(err <= (3 * 2.0 ** -22 + 4 * K * 2.0 ** -24) * absprod)
+    g16 = lyap.gemm(_cuda(A), _cuda(B), transa=ta, transb=tb, dtype="fp16").cpu().numpy()
+    assert np.median(err / absprod) * 100 < np.median(np.abs(g16 - opA(A) @ opB(B)) / absprod)
+
+
 @pytest.mark.parametrize("dtype", ["fp32", "fp16", "bf16"])
 @pytest.mark.parametrize("M,N,K,ta,tb", [(67, 45, 33, False, False), (128, 96, 160, True, False),
                                          (50, 130, 70, False, True)])
@@ -81,14 +100,15 @@ def test_gemm_reduced(lyap, dtype, M, N, K, ta, tb):
 
 
 @pytest.mark.parametrize("n", [1, 7, 37, 200, 1000])
-@pytest.mark.parametrize("dtype", ["fp64", "fp32", "fp16", "bf16"])
+@pytest.mark.parametrize("dtype", ["fp64", "fp32", "fp16", "bf16", "fp16x2"])
 def test_inverse_accuracy(lyap, n, dtype):
     print(f"inverse {dtype} n={n}", flush=True)
     A, _ = lyapgen.random_shift(100 + n, n, 1)
     X = lyap.inverse(_cuda(A), dtype).cpu().numpy()
     Xr = np.linalg.inv(A)
     kappa = np.linalg.cond(A, 1)
-    u = {"fp64": 2.0 ** -53, "fp32": 2.0 ** -24, "fp16": 2.0 ** -11, "bf16": 2.0 ** -8}[dtype]
+    u = {"fp64": 2.0 ** -53, "fp32": 2.0 ** -24, "fp16": 2.0 ** -11, "bf16": 2.0 ** -8,
+         "fp16x2": 2.0 ** -22}[dtype]
     err = np.linalg.norm(X - Xr, 1) / np.linalg.norm(Xr, 1)
     assert err <= 20 * n ** 0.5 * kappa * u, err
     res = np.linalg.norm(A @ X - np.eye(n), 1)

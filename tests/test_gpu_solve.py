@@ -46,7 +46,7 @@ def _check(A, L, S, Z, D, X, res_tol=1e-13, err_factor=None):
     return res, err
 
 
-@pytest.mark.parametrize("us", ["fp64", "fp32", "fp16", "bf16"])
+@pytest.mark.parametrize("us", ["fp64", "fp32", "fp16", "bf16", "fp16x2"])
 def test_small_all_precisions(lyap, us):
     cfg = lyapgen.config("small")
     A, L = cfg["A"], cfg["L"]
@@ -146,3 +146,21 @@ def test_repeat_is_deterministic(lyap):
     a = _run(lyap, A, L, None, "fp16")
     b = _run(lyap, A, L, None, "fp16")
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+@pytest.mark.parametrize("us", ["fp16x2"])
+def test_split_solver_matches_oracle(lyap, us):
+    # u_s = fp16x2 (split binary16 operands, unit roundoff 2^-22): the GPU and the oracle take
+    # the same number of Newton steps and refinements (within one) on a graded problem
+    A, L, Q, T = lyapgen.schur_family(7, 160, 3, lo=-2.0)
+    X = E.schur_solve(Q, T, L @ L.T)
+    Zo, do, io = IR.ir_ldlt(A, L, None, prec=(us, "fp64", "fp64", "fp64"))
+    print(f"split solver n=160 (oracle: K={io.inversions} refinements={io.refinements})", flush=True)
+    Z, D, info = _run(lyap, A, L, None, us)
+    res, err = _check(A, L, None, Z, D, X)
+    print(f"  gpu: status={info['status']} res={res:.2e} err={err:.2e} K={info['inversions']} "
+          f"refinements={info['refinements']} rank={info['rank']} (oracle rank {io.rank})",
+          flush=True)
+    assert info["status"] == "OK" and res <= 1e-13 and err <= 1e-9
+    assert abs(info["inversions"] - io.inversions) <= 1
+    assert abs(info["refinements"] - io.refinements) <= 1
