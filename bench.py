@@ -28,19 +28,19 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "fp16": 2500.0, "bf16": 2500.0}
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "fp16": 2500.0, "bf16": 2500.0, "fp16x2": 2500.0}
 PEAK_HBM_GBS = 8000.0
 
 
-def _time_inverse(lyap, torch, A, us, reps=3):
-    """Average duration of one inversion (the dominant kernel family, 2 n^3 flops) on the
-    current stream, measured with HIP events around the calls."""
-    lyap.inverse(A, us)
+def _time_inverse(lyap, torch, A, us, reps=3, pivot=True):
+    """Average duration of one inversion (2 n^3 flops) on the current stream, measured with
+    HIP events around the calls."""
+    lyap.inverse(A, us, pivot=pivot)
     stream = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for _ in range(reps):
-        lyap.inverse(A, us)
+        lyap.inverse(A, us, pivot=pivot)
     e1.record(stream)
     e1.synchronize()
     return e0.elapsed_time(e1) / reps / 1e3
@@ -187,6 +187,7 @@ def _run_path(lyap, torch, cfg, A, L, S, us, steps, warmup, **opts):
             "refinements": last["refinements"],
             "iters": f'{last["newton_total"]}({last["newton_max"]})',
             "inversions": last["inversions"],
+            "rbt_steps": last["rbt_steps"], "rbt_fallbacks": last["rbt_fallbacks"],
             "phase_ms": [round(x, 2) for x in last["phase_ms"]],
         },
     }
@@ -242,11 +243,18 @@ def main():
         st, wu = (1, 0) if us == "bf16" else (args.steps, args.warmup)
         runs[us] = _run_path(lyap, torch, cfg, A, L, S, us, st, wu)
         print(f"ir {us}: {runs[us]['summary']}", file=sys.stderr, flush=True)
-    adaptive = {}
+    adaptive, fast = {}, {}
     for us in [x.strip() for x in args.adaptive.split(",") if x.strip()]:
         adaptive[us] = _run_path(lyap, torch, cfg, A, L, S, us, args.steps, args.warmup,
                                  adaptive=1)
         print(f"ir {us} adaptive: {adaptive[us]['summary']}", file=sys.stderr, flush=True)
+    # the same paths with the random butterfly transformation in place of partial pivoting
+    base_rbt = _run_path(lyap, torch, cfg, A, L, S, "fp64", args.steps, args.warmup, pivoting=1)
+    print(f"fp64 rbt: {base_rbt['summary']}", file=sys.stderr, flush=True)
+    for us in [x.strip() for x in args.adaptive.split(",") if x.strip()]:
+        fast[us] = _run_path(lyap, torch, cfg, A, L, S, us, args.steps, args.warmup, adaptive=1,
+                             pivoting=1)
+        print(f"ir {us} adaptive rbt: {fast[us]['summary']}", file=sys.stderr, flush=True)
     head = runs[inner[0]] if inner else base
     sps64 = base["summary"]["solves_per_s"]
 
@@ -272,6 +280,8 @@ def main():
            "launches": head["fam_calls"][1]}
     t_inv = _time_inverse(lyap, torch, A, "fp64")
     inv64 = 2.0 * n ** 3 / t_inv / 1e12
+    t_inv_rbt = _time_inverse(lyap, torch, A, "fp64", pivot="rbt")
+    inv64_rbt = 2.0 * n ** 3 / t_inv_rbt / 1e12
 
     batched = _batched(lyap, torch, inner[0] if inner else "fp16") if args.batched else None
 
@@ -307,11 +317,20 @@ def main():
             us: dict(r["summary"], speedup_vs_fp64=(round(r["summary"]["solves_per_s"] / sps64, 4)
                                                     if sps64 > 0 and r["ok"] else None))
             for us, r in adaptive.items()},
+        "fp64_sign_newton_rbt": base_rbt["summary"],
+        "ir_adaptive_rbt": {
+            us: dict(r["summary"], speedup_vs_fp64_rbt=(
+                round(r["summary"]["solves_per_s"] / base_rbt["summary"]["solves_per_s"], 4)
+                if base_rbt["ok"] and r["ok"] else None))
+            for us, r in fast.items()},
         "roofline": roof,
         "time_shares_headline_ir": shares,
         "jacobi_rounds_hbm": jac,
         "inversion_fp64_alone": {"ms": round(1e3 * t_inv, 3), "tflops": round(inv64, 3),
                                  "frac_fp64_peak": round(inv64 / PEAK_TFLOPS["fp64"], 4)},
+        "inversion_fp64_rbt_alone": {"ms": round(1e3 * t_inv_rbt, 3),
+                                     "tflops": round(inv64_rbt, 3),
+                                     "frac_fp64_peak": round(inv64_rbt / PEAK_TFLOPS["fp64"], 4)},
         "cpu_baseline": cpu,
     }
     if batched is not None:

@@ -121,6 +121,14 @@ typedef struct {
                         step with residual res_i keeps |sigma| >= max(eta_s, omega res_i)
                         max|sigma|.  0 (default): the fixed thresholds of Alg 3.2 and
                         Fragment 2.4.                                                       */
+  int pivoting;      /* inversions of A_k while ||A_{k-1} + I||_1 >= 1 (afterwards A_k is
+                        strictly column diagonally dominant and no pivoting is needed):
+                        0 (default) Gauss-Jordan with partial pivoting; 1 random butterfly
+                        transformation (Parker's RBT, depth 2, seeded) and Gauss-Jordan
+                        without pivoting on U^T A_k V, checked by a residual probe
+                        ||A_k (A_k^-1 x) - x|| <= 8 sqrt(n) u_s ||A_k||_F ||A_k^-1||_F ||x||
+                        and redone with partial pivoting when the probe fails (needs
+                        n % 4 == 0, otherwise partial pivoting)                            */
   double omega;      /* the factor omega of the adaptive update threshold; default 0.1:
                         directions that small are the ones the next correction fixes
                         anyway (measured at n = 4096: fp16 inner, omega 1e-3 / 0.1 / 0.3:
@@ -156,6 +164,8 @@ typedef struct {
   int u_s_final;          /* solver precision (lyap_dtype) of the last stage (escalate)   */
   int escalations;        /* precision escalations performed                             */
   int cache_reused;       /* 1 when the inverse sequence was replayed from the workspace  */
+  int rbt_steps;          /* inversions done through the random butterfly transformation  */
+  int rbt_fallbacks;      /* butterfly inversions whose probe failed, redone with pivoting */
 } lyap_info;
 
 typedef struct lyap_handle_s* lyap_handle;
@@ -327,7 +337,9 @@ int lyap_solve_adjoint(lyap_handle h, void* stream, int n, int m, const double* 
 /*
  * lyap_inverse -- inverse of the n x n FP64 matrix A (row-major, lda) at solver precision
  * ``dtype`` (the inversion of Alg 3.1/3.2, first line of the loop): Gauss-Jordan
- * elimination.  pivot != 0: partial pivoting (ties to the lowest row index).  pivot == 0:
+ * elimination.  pivot == 1: partial pivoting (ties to the lowest row index).  pivot == 2:
+ * random butterfly transformation and no pivoting (lyap_options.pivoting = 1; n % 4 == 0,
+ * else LYAP_BADARG; no probe, no fallback).  pivot == 0:
  * no row interchanges, which is the same elimination whenever A is strictly column
  * diagonally dominant (partial pivoting then never interchanges rows); for other A the
  * unpivoted elimination may be unstable.  For F32/F16/BF16 the matrix is held in binary32,

@@ -21,7 +21,7 @@ from __future__ import annotations
 
 import numpy as np
 
-FORMATS = ("fp64", "fp32", "fp16", "bf16", "fp16x2")
+FORMATS = ("fp64", "fp32", "fp16", "bf16")  # Table 1.1 (the split format is separate)
 
 # The split-operand format "fp16x2" (not in the paper; the hi/lo operand splitting of
 # Markidis et al. 2018 and Ootomo and Yokota 2022): a value is held as a pair of binary16

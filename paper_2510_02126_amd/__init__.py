@@ -64,12 +64,15 @@ def version() -> str:
     return _lib.lib().lyap_version().decode()
 
 
-def inverse(A: torch.Tensor, dtype: str = "fp64", pivot: bool = True) -> torch.Tensor:
+def inverse(A: torch.Tensor, dtype: str = "fp64", pivot=True) -> torch.Tensor:
+    """A^{-1} at solver precision ``dtype``: pivot True (partial pivoting), False (none) or
+    "rbt" (random butterfly transformation, no pivoting)."""
     dev = _dev(A)
     n = A.shape[0]
     A, lda = _rowmajor(A)
     out = torch.empty((n, n), dtype=torch.float64, device=A.device)
-    code = _lib.lib().lyap_inverse(_lib.handle(dev), _stream(dev), DTYPES[dtype], int(bool(pivot)),
+    pv = 2 if pivot == "rbt" else int(bool(pivot))
+    code = _lib.lib().lyap_inverse(_lib.handle(dev), _stream(dev), DTYPES[dtype], pv,
                                    n, _ptr(A), lda, _ptr(out), n)
     _lib.check(code, "lyap_inverse")
     return out

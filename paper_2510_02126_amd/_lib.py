@@ -42,7 +42,8 @@ class Options(ctypes.Structure):
                 ("delta_off", ctypes.c_double), ("theta", ctypes.c_double),
                 ("refine", ctypes.c_int), ("psd", ctypes.c_int), ("form", ctypes.c_int),
                 ("scaling", ctypes.c_int), ("escalate", ctypes.c_int), ("reuse", ctypes.c_int),
-                ("adaptive", ctypes.c_int), ("omega", ctypes.c_double)]
+                ("adaptive", ctypes.c_int), ("pivoting", ctypes.c_int),
+                ("omega", ctypes.c_double)]
 
 
 class Info(ctypes.Structure):
@@ -54,7 +55,8 @@ class Info(ctypes.Structure):
                 ("phase_ms", ctypes.c_double * 8), ("kern_ms", ctypes.c_double * 4),
                 ("kern_work", ctypes.c_double * 4), ("kern_calls", ctypes.c_int * 4),
                 ("u_s_final", ctypes.c_int), ("escalations", ctypes.c_int),
-                ("cache_reused", ctypes.c_int)]
+                ("cache_reused", ctypes.c_int), ("rbt_steps", ctypes.c_int),
+                ("rbt_fallbacks", ctypes.c_int)]
 
     def as_dict(self) -> dict:
         return {
@@ -75,6 +77,8 @@ class Info(ctypes.Structure):
             "u_s_final": {v: k for k, v in DTYPES.items()}.get(self.u_s_final, self.u_s_final),
             "escalations": self.escalations,
             "cache_reused": bool(self.cache_reused),
+            "rbt_steps": self.rbt_steps,
+            "rbt_fallbacks": self.rbt_fallbacks,
         }
 
 

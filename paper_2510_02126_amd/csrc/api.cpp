@@ -135,7 +135,7 @@ static bool valid_options(const lyap_options& o, const double* S, int lds) {
          !(o.form == 1 && S != nullptr) && o.scaling >= 0 && o.scaling <= 3 &&
          (o.escalate == 0 || o.escalate == 1) && o.reuse >= -1 && o.reuse <= 1 &&
          o.delta_off >= 0 && lds >= 0 && (o.adaptive == 0 || o.adaptive == 1) &&
-         o.omega >= 0;
+         o.omega >= 0 && (o.pivoting == 0 || o.pivoting == 1);
 }
 
 // ws == NULL: the solve runs in ``own`` (grown on demand, ``epoch`` bumped on every
@@ -259,6 +259,7 @@ void lyap_default_options(lyap_options* o) {
   o->escalate = 0;
   o->reuse = -1;
   o->adaptive = 0;
+  o->pivoting = 0;
   o->omega = 0.1;
 }
 
@@ -345,10 +346,16 @@ int lyap_inverse(lyap_handle h, void* stream, int dtype, int pivot, int n, const
   if (n == 0) return LYAP_OK;
   if (n > 4096) return LYAP_BADARG;
   hipStream_t s = (hipStream_t)stream;
-  LYAP_TRY(h->ws.reserve(inverse_workspace_bytes((Prec)dtype, n) + (1 << 20)));
+  if (pivot == 2 && n % 4 != 0) return LYAP_BADARG;
+  LYAP_TRY(h->ws.reserve(inverse_workspace_bytes((Prec)dtype, n) + rbt_workspace_bytes(n) +
+                         (1 << 20)));
   h->ws.reset();
   LYAP_TRY(fill_int(s, h->flags, 2, 0));
-  LYAP_TRY(invert(s, (Prec)dtype, n, A, lda, Ainv, ldi, h->ws, h->flags, pivot != 0));
+  if (pivot == 2)
+    LYAP_TRY(rbt_invert(s, (Prec)dtype, n, A, lda, Ainv, ldi, h->ws, h->flags, nullptr, nullptr,
+                        0x4c59415055ull, nullptr));
+  else
+    LYAP_TRY(invert(s, (Prec)dtype, n, A, lda, Ainv, ldi, h->ws, h->flags, pivot != 0));
   int f[2] = {0, 0};
   LYAP_HIP(hipMemcpyAsync(f, h->flags, sizeof(f), hipMemcpyDeviceToHost, s));
   LYAP_HIP(hipStreamSynchronize(s));

@@ -16,6 +16,19 @@ int invert(hipStream_t s, Prec op, int n, const double* A, long lda, double* out
            Arena& ws, int* flags_dev, bool pivot = true, KernTimer* kt = nullptr,
            double* logdet_dev = nullptr);
 
+// ---- rbt.hip
+size_t rbt_workspace_bytes(int n);
+// A^{-1} = V (U^T A V)^{-1} U^T with random depth-2 butterflies U, V (seeded) and Gauss-Jordan
+// without pivoting on the transformed matrix; n must be a multiple of 4.  With probe, the
+// residual ||A (A^{-1} x) - x||_2 / ||x||_2 for a seeded random x is written to probe[0]; with
+// logdet, log|det A|.  Timed as one inversion (family 0) when kt is given.
+int rbt_invert(hipStream_t s, Prec op, int n, const double* A, long lda, double* out, long ldo,
+               Arena& ws, int* flags_dev, KernTimer* kt, double* logdet,
+               unsigned long long seed, double* probe);
+// The same residual probe for any computed inverse.
+int probe_inverse(hipStream_t s, int n, const double* A, long lda, const double* Ainv, long ldi,
+                  Arena& ws, unsigned long long seed, double* probe);
+
 // ---- elem.hip
 int fill_int(hipStream_t s, int* p, int count, int value);
 int fill_f64(hipStream_t s, double* p, long count, double value);

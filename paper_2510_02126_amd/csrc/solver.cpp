@@ -146,7 +146,7 @@ Layout solver_layout(int n, int m, Prec us, const lyap_options& opt) {
   const size_t lead = ((nn / 4) + std::min(2 * nn, (size_t)1 << 22)) * 8 + ((size_t)1 << 16);
   L.arena_bytes = std::max(std::max(qr_workspace_bytes(n, L.cap), syev_workspace_bytes(n)),
                            syev_workspace_bytes(std::max(m, 1))) +
-                  std::max(inverse_workspace_bytes(inv_prec, n), lead);
+                  std::max(inverse_workspace_bytes(inv_prec, n) + rbt_workspace_bytes(n), lead);
   L.arena = take(L.arena_bytes);
   L.total = off;
   return L;
@@ -253,30 +253,58 @@ int Solver::a_iteration(Ctx& c) {
   const int kmax = std::min(c.opt.k_max, c.lay.slots);
   for (int k = 1; k <= kmax; ++k) {
     double* out = (c.us == Prec::F64) ? static_cast<double*>(c.slot(k - 1)) : c.Ainv;
-    LYAP_TRY(fill_int(s, c.flags, 2, 0));
-    c.arena.reset();
     // ||A_{k-1} + I||_1 < 1 makes A_{k-1} strictly column diagonally dominant: partial
-    // pivoting would pick the diagonal, so the pivot search is skipped (same result)
+    // pivoting would pick the diagonal, so the pivot search is skipped (same result).
+    // Otherwise, with opt.pivoting = 1, the random butterfly transformation removes the need
+    // for pivoting; its residual probe decides whether the step is redone with partial
+    // pivoting.
     const bool pivot = !(last_onenorm < 1.0);
     const bool want_det = scaling && c.opt.scaling == 1;
-    LYAP_TRY(invert(s, c.us, n, Ak, n, out, n, c.arena, c.flags, pivot, c.kt,
-                    want_det ? scal + 6 : nullptr));
-    if (c.us != Prec::F64) {
-      // cached copy 2^-e A_k^-1 rounded once to u_s (e from its largest entry)
-      LYAP_TRY(absmax_exp(s, n, n, out, n, c.cexp + (k - 1), c.flags + 1, c.part));
-      LYAP_TRY(cast_scaled(s, c.cstore, n, n, out, n, c.slot(k - 1), c.cexp + (k - 1)));
-    } else {
-      LYAP_TRY(fill_int(s, c.cexp + (k - 1), 1, 0));
-    }
-    LYAP_TRY(sumsq(s, n, n, out, n, scal + 1, c.part));
-    LYAP_TRY(scaling_mu(c, Ak, out, a_ss, scal + 6, scaling, scal + 2));
-    LYAP_TRY(newton_update(s, n, Ak, n, out, n, scal + 2, An, n, scal + 3, c.colsum, c.part));
+    bool rbt = pivot && c.opt.pivoting == 1 && n % 4 == 0;
     double h[6];
+    double probe = 0.0;
     int fl[2];
-    LYAP_HIP(hipMemcpyAsync(h, scal, sizeof(h), hipMemcpyDeviceToHost, s));
-    LYAP_HIP(hipMemcpyAsync(fl, c.flags, sizeof(fl), hipMemcpyDeviceToHost, s));
-    LYAP_HIP(hipStreamSynchronize(s));
-    c.info->inversions += 1;
+    for (;;) {
+      LYAP_TRY(fill_int(s, c.flags, 2, 0));
+      c.arena.reset();
+      if (rbt) {
+        LYAP_TRY(rbt_invert(s, c.us, n, Ak, n, out, n, c.arena, c.flags, c.kt,
+                            want_det ? scal + 6 : nullptr, 0x4c59415055ull + (unsigned)k,
+                            scal + 13));
+      } else {
+        LYAP_TRY(invert(s, c.us, n, Ak, n, out, n, c.arena, c.flags, pivot, c.kt,
+                        want_det ? scal + 6 : nullptr));
+      }
+      if (c.us != Prec::F64) {
+        // cached copy 2^-e A_k^-1 rounded once to u_s (e from its largest entry)
+        LYAP_TRY(absmax_exp(s, n, n, out, n, c.cexp + (k - 1), c.flags + 1, c.part));
+        LYAP_TRY(cast_scaled(s, c.cstore, n, n, out, n, c.slot(k - 1), c.cexp + (k - 1)));
+      } else {
+        LYAP_TRY(fill_int(s, c.cexp + (k - 1), 1, 0));
+      }
+      LYAP_TRY(sumsq(s, n, n, out, n, scal + 1, c.part));
+      LYAP_TRY(scaling_mu(c, Ak, out, a_ss, scal + 6, scaling, scal + 2));
+      LYAP_TRY(copy_block(s, 1, 1, a_ss, 1, scal + 14, 1));  // ||A_{k-1}||_F^2, kept
+      LYAP_TRY(newton_update(s, n, Ak, n, out, n, scal + 2, An, n, scal + 3, c.colsum, c.part));
+      double a2 = 0.0;
+      LYAP_HIP(hipMemcpyAsync(h, scal, sizeof(h), hipMemcpyDeviceToHost, s));
+      LYAP_HIP(hipMemcpyAsync(&a2, scal + 14, sizeof(double), hipMemcpyDeviceToHost, s));
+      LYAP_HIP(hipMemcpyAsync(&probe, scal + 13, sizeof(double), hipMemcpyDeviceToHost, s));
+      LYAP_HIP(hipMemcpyAsync(fl, c.flags, sizeof(fl), hipMemcpyDeviceToHost, s));
+      LYAP_HIP(hipStreamSynchronize(s));
+      c.info->inversions += 1;
+      if (!rbt) break;
+      // accept when ||A (A^-1 x) - x|| <= 8 sqrt(n) u_s ||A||_F ||A^-1||_F ||x|| (a backward
+      // stable inversion's residual is of order u_s kappa); otherwise partial pivoting
+      const double bound = 8.0 * std::sqrt((double)n) * unit_roundoff(c.us) *
+                           std::sqrt(a2) * std::sqrt(h[1]);
+      if (!fl[0] && !fl[1] && std::isfinite(probe) && probe <= bound) {
+        c.info->rbt_steps += 1;
+        break;
+      }
+      c.info->rbt_fallbacks += 1;
+      rbt = false;
+    }
     if (fl[0]) return LYAP_SINGULAR;
     const double mu = h[2], dsq = h[3], anew = h[4], onenorm = h[5];
     if (fl[1] || !std::isfinite(mu) || !(mu > 0.0) || !std::isfinite(anew) ||

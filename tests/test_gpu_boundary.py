@@ -318,3 +318,31 @@ def test_status_nonfinite_and_badarg(lyap):
     with pytest.raises(lyap.LyapError) as e:  # u_s finer than u
         lyap.solve(_cuda(_small()[0]), _cuda(L), None, precisions=("fp64", "fp32", "fp32", "fp32"))
     assert e.value.status == "BADARG"
+
+
+# ----------------------------------------------------------- random butterfly pivoting
+@pytest.mark.parametrize("us", ["fp64", "fp32", "fp16"])
+def test_butterfly_pivoting_solve(lyap, us):
+    # opt.pivoting = 1: the pivoted inversions go through the random butterfly
+    # transformation (probe-checked); the solve reaches the same accuracy and the FP64
+    # Newton count is unchanged
+    A, L, Q, T = lyapgen.schur_family(7, 300, 3, lo=-2.0)
+    X = E.schur_solve(Q, T, L @ L.T)
+    print(f"butterfly pivoting n=300 {us}", flush=True)
+    _, _, ref = lyap.solve(_cuda(A), _cuda(L), None, precisions=(us, "fp64", "fp64", "fp64"))
+    Z, D, info = lyap.solve(_cuda(A), _cuda(L), None, precisions=(us, "fp64", "fp64", "fp64"),
+                            pivoting=1)
+    Z, D = _np(Z, D)
+    print(f"  {info['status']} res={info['res']:.2e} rbt={info['rbt_steps']} "
+          f"fallbacks={info['rbt_fallbacks']} K={info['inversions']} (pivoted K={ref['inversions']})",
+          flush=True)
+    assert info["status"] == "OK" and info["res"] <= 1e-13
+    assert info["rbt_steps"] >= 1 and info["rbt_fallbacks"] == 0
+    assert _rel((Z * D) @ Z.T, X) <= 1e-9
+    if us == "fp64":
+        assert info["inversions"] == ref["inversions"]
+    # n % 4 != 0: partial pivoting throughout
+    A2, L2 = lyapgen.random_shift(8, 65, 2)
+    _, _, i2 = lyap.solve(_cuda(A2), _cuda(L2), None, precisions=(us, "fp64", "fp64", "fp64"),
+                          pivoting=1)
+    assert i2["status"] == "OK" and i2["rbt_steps"] == 0

@@ -191,3 +191,25 @@ def test_inverse_unpivoted_zero_pivot_reports(lyap):
     assert e.value.status == "SINGULAR"
     X = lyap.inverse(_cuda(A), "fp64", pivot=True).cpu().numpy()
     assert np.array_equal(X, A)
+
+
+@pytest.mark.parametrize("n", [4, 200, 1000, 4096])
+@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
+def test_inverse_random_butterfly(lyap, n, dtype):
+    # A^{-1} = V (U^T A V)^{-1} U^T with random depth-2 butterflies and no pivoting: as
+    # accurate as the pivoted inversion on the same matrix
+    print(f"inverse rbt {dtype} n={n}", flush=True)
+    A, _ = lyapgen.random_shift(100 + n, n, 1)
+    X = lyap.inverse(_cuda(A), dtype, pivot="rbt").cpu().numpy()
+    Xp = lyap.inverse(_cuda(A), dtype, pivot=True).cpu().numpy()
+    u = {"fp64": 2.0 ** -53, "fp32": 2.0 ** -24}[dtype]
+    kappa = np.linalg.cond(A, 1)
+    res = np.linalg.norm(A @ X - np.eye(n), 1)
+    resp = np.linalg.norm(A @ Xp - np.eye(n), 1)
+    print(f"  ||AX - I||_1 rbt {res:.2e} pivoted {resp:.2e}", flush=True)
+    assert res <= 20 * n ** 0.5 * kappa * u
+    assert res <= 10 * resp + 10 * n * u
+    # the same seeded transformation every call
+    assert torch.equal(lyap.inverse(_cuda(A), dtype, pivot="rbt"), _cuda(X))
+    with pytest.raises(lyap.LyapError):
+        lyap.inverse(_cuda(A[:3, :3] - 3 * np.eye(3)), dtype, pivot="rbt")  # n % 4 != 0
