@@ -101,7 +101,9 @@ typedef struct {
                         Section 4 uses), 1 determinantal |det A_k|^(-1/n) (log|det| from the
                         pivots of the inversion), 2 2-norm sqrt(||A_k^-1||_2 / ||A_k||_2) and
                         3 spectral sqrt(rho(A_k^-1) / rho(A_k)), the last two from power-
-                        iteration estimates (12 steps on A^T A; 24 steps on A).  Scaling is
+                        iteration estimates (12 steps on A^T A; 24 steps on A), and 4 the
+                        combined Frobenius + determinantal scaling Section 4 mentions:
+                        determinantal for the first step, Frobenius afterwards.  Scaling is
                         switched off once delta_k < delta_off in every case.               */
   int escalate;      /* 1: when a refinement at reduced u_s stagnates (eq 4.2), runs out of
                         steps, overflows or meets an exact zero pivot, continue it at the next

@@ -154,7 +154,7 @@ class ASequence:
         return len(self.inverses)
 
 
-SCALINGS = ("frobenius", "det", "2norm", "spectral")
+SCALINGS = ("frobenius", "det", "2norm", "spectral", "combined")
 
 
 def scaling_mu(Ak, Ainv, kind: str = "frobenius") -> float:
@@ -198,7 +198,13 @@ def a_sequence(A, fmt: str = "fp64", k_max: int = 50, delta_off: float = 1e-2,
             raise np.linalg.LinAlgError(f"singular A_k at k={_k}") from exc
         if not np.all(np.isfinite(Ainv)):
             raise NonFiniteError(f"non-finite inverse at k={_k}")
-        mu = scaling_mu(Ak, Ainv, scaling_kind) if scaling else 1.0
+        # combined Frobenius + determinantal scaling (the combination Section 4 reports trying,
+        # which the paper does not spell out; read here as the determinantal scaling for the
+        # first step, where the eigenvalues are furthest from +-1, then the Frobenius scaling)
+        kind = scaling_kind
+        if scaling_kind == "combined":
+            kind = "det" if _k == 1 else "frobenius"
+        mu = scaling_mu(Ak, Ainv, kind) if scaling else 1.0
         if not (np.isfinite(mu) and mu > 0.0):
             raise NonFiniteError(f"scaling parameter out of range at k={_k}")
         Anew = fl_scaled(0.5 * (mu * Ak + Ainv / mu), fmt)

@@ -132,7 +132,7 @@ static bool valid_precisions(const lyap_precisions& p) {
 static bool valid_options(const lyap_options& o, const double* S, int lds) {
   return o.tol >= 0 && o.i_max >= 0 && o.i_max <= 63 && o.k_max >= 1 && o.k_max <= 64 &&
          o.rho > 0 && o.eta_r >= 0 && o.theta > 0 && (o.form == 0 || o.form == 1) &&
-         !(o.form == 1 && S != nullptr) && o.scaling >= 0 && o.scaling <= 3 &&
+         !(o.form == 1 && S != nullptr) && o.scaling >= 0 && o.scaling <= 4 &&
          (o.escalate == 0 || o.escalate == 1) && o.reuse >= -1 && o.reuse <= 1 &&
          o.delta_off >= 0 && lds >= 0 && (o.adaptive == 0 || o.adaptive == 1) &&
          o.omega >= 0 && (o.pivoting == 0 || o.pivoting == 1);

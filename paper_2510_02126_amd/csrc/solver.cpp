@@ -207,12 +207,12 @@ int Solver::upload_d(Ctx& c, const std::vector<double>& d, double* dst) {
 // determinantal |det A|^(-1/n), 2-norm sqrt(||A^-1||_2 / ||A||_2), spectral
 // sqrt(rho(A^-1) / rho(A)); 1 once scaling is switched off.  The 2-norms and spectral radii
 // are power-iteration estimates.  Result on the device in mu_dev.
-int Solver::scaling_mu(Ctx& c, const double* Ak, const double* Ainv, const double* a_ss,
-                       const double* logdet, bool scaling, double* mu_dev) {
+int Solver::scaling_mu(Ctx& c, int mode, const double* Ak, const double* Ainv,
+                       const double* a_ss, const double* logdet, bool scaling, double* mu_dev) {
   hipStream_t s = c.s;
   const int n = c.n;
   double* sc = c.scal;
-  switch (scaling ? c.opt.scaling : 0) {
+  switch (scaling ? mode : 0) {
     case 1:
       return newton_mu(s, 1, logdet, nullptr, n, scaling ? 1 : 0, mu_dev);
     case 2:
@@ -259,7 +259,9 @@ int Solver::a_iteration(Ctx& c) {
     // for pivoting; its residual probe decides whether the step is redone with partial
     // pivoting.
     const bool pivot = !(last_onenorm < 1.0);
-    const bool want_det = scaling && c.opt.scaling == 1;
+    // opt.scaling 4 (combined): determinantal for the first step, Frobenius afterwards
+    const int mode = c.opt.scaling == 4 ? (k == 1 ? 1 : 0) : c.opt.scaling;
+    const bool want_det = scaling && mode == 1;
     bool rbt = pivot && c.opt.pivoting == 1 && n % 4 == 0;
     double h[6];
     double probe = 0.0;
@@ -283,7 +285,7 @@ int Solver::a_iteration(Ctx& c) {
         LYAP_TRY(fill_int(s, c.cexp + (k - 1), 1, 0));
       }
       LYAP_TRY(sumsq(s, n, n, out, n, scal + 1, c.part));
-      LYAP_TRY(scaling_mu(c, Ak, out, a_ss, scal + 6, scaling, scal + 2));
+      LYAP_TRY(scaling_mu(c, mode, Ak, out, a_ss, scal + 6, scaling, scal + 2));
       LYAP_TRY(copy_block(s, 1, 1, a_ss, 1, scal + 14, 1));  // ||A_{k-1}||_F^2, kept
       LYAP_TRY(newton_update(s, n, Ak, n, out, n, scal + 2, An, n, scal + 3, c.colsum, c.part));
       double a2 = 0.0;

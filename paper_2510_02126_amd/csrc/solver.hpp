@@ -68,7 +68,7 @@ class Solver {
   int sol_upt(Ctx& c, int& cols, std::vector<double>& d, const double* Zcor, int cd,
               const std::vector<double>& dd, double eta_s, bool psd);
   int upload_d(Ctx& c, const std::vector<double>& d, double* dst);
-  int scaling_mu(Ctx& c, const double* Ak, const double* Ainv, const double* a_ss,
+  int scaling_mu(Ctx& c, int mode, const double* Ak, const double* Ainv, const double* a_ss,
                  const double* logdet, bool scaling, double* mu_dev);
 
   int last_k_ = 0;

@@ -221,7 +221,8 @@ def test_working_precision_fp32_stagnates(lyap):
 
 
 # --------------------------------------------------------------------------- scalings
-@pytest.mark.parametrize("kind,code", [("det", 1), ("2norm", 2), ("spectral", 3)])
+@pytest.mark.parametrize("kind,code", [("det", 1), ("2norm", 2), ("spectral", 3),
+                                       ("combined", 4)])
 def test_alternative_scalings(lyap, kind, code):
     A, L = _small()
     X = E.kron_solve(A, L @ L.T)
@@ -234,9 +235,13 @@ def test_alternative_scalings(lyap, kind, code):
     assert _rel((Z * D) @ Z.T, X) <= 1e-11
     # determinantal: from the pivots, exact up to rounding; the others are power-iteration
     # estimates of norms / spectral radii
-    tol = 1e-9 if kind == "det" else 0.05
+    exact = kind in ("det", "combined")
+    tol = 1e-9 if exact else 0.05
     assert info["mus"][0] == pytest.approx(seq.mus[0], rel=tol)
-    assert abs(info["inversions"] - seq.K) <= (0 if kind == "det" else 1)
+    assert abs(info["inversions"] - seq.K) <= (0 if exact else 1)
+    if kind == "combined":
+        # determinantal first, then the Frobenius scaling of the iterates it produced
+        assert np.allclose(info["mus"][:seq.K], seq.mus, rtol=1e-8)
 
 
 def test_determinantal_scaling_of_scaled_identity(lyap):

@@ -41,6 +41,22 @@ def test_determinantal_scaling_of_a_diagonal_matrix():
     assert mu == pytest.approx(float(np.prod(np.abs(a))) ** (-1.0 / a.size), rel=1e-14)
 
 
+def test_combined_scaling_of_a_diagonal_matrix():
+    # combined scaling: mu_0 determinantal, later steps Frobenius.  For diagonal A every
+    # iterate is diagonal, b -> (mu b + 1/(mu b)) / 2 entrywise, so both scalings have closed
+    # forms: mu_0 = (prod |a_i|)^(-1/n), mu_1 = sqrt(||1/b||_2 / ||b||_2)
+    a = -np.array([0.5, 2.0, 7.0, 0.01, 3.0, 40.0, 0.2, 9.0])
+    seq = SN.a_sequence(np.diag(a), "fp64", scaling_kind="combined")
+    mu0 = float(np.prod(np.abs(a))) ** (-1.0 / a.size)
+    b = 0.5 * (mu0 * a + 1.0 / (mu0 * a))
+    mu1 = math.sqrt(np.linalg.norm(1.0 / b) / np.linalg.norm(b))
+    assert seq.mus[0] == pytest.approx(mu0, rel=1e-13)
+    assert seq.mus[1] == pytest.approx(mu1, rel=1e-12)
+    # and not the determinantal value at step 1 (it differs for this spectrum)
+    mu1_det = float(np.prod(np.abs(b))) ** (-1.0 / b.size)
+    assert abs(mu1 - mu1_det) > 1e-3 * mu1
+
+
 @pytest.mark.parametrize("kind", ["2norm", "spectral"])
 def test_norm_and_spectral_scaling_of_a_symmetric_matrix(kind):
     # symmetric negative definite A with spectrum in [-b, -a]: ||A||_2 = rho(A) = b and
