@@ -39,6 +39,7 @@ import numpy as np
 import scipy.linalg as sla
 
 from .precision import fl, fl_scaled, unit_roundoff
+from .adi import adi_sequence, lr_adi_ldlt
 from .signnewton import NonFiniteError, NotStableError, a_sequence, sign_newton_chol, sign_newton_ldlt
 
 
@@ -184,8 +185,10 @@ def ir_ldlt(A, L, S=None, prec=("fp32", "fp64", "fp64", "fp64"), tol: float = 1e
             i_max: int = 50, k_max: int = 50, rho: float = 0.1, eta_r: float = 1e-4,
             eta_s: float | None = None, psd: bool | None = None, theta: float = 0.9,
             refine: bool = True, scaling: str = "frobenius", Z0=None, d0=None,
-            escalate: bool = False, adaptive: bool = False, omega: float = 0.1):
-    """Alg 2.2 with Alg 3.2 as the solver.  ``prec`` = (u_s, u, u_r, u_c).  With
+            escalate: bool = False, adaptive: bool = False, omega: float = 0.1,
+            solver: str = "newton", adi_shifts: int = 0, adi_max: int = 100):
+    """Alg 2.2 with Alg 3.2 as the solver (``solver="adi"``: the LDL^T low-rank ADI solver of
+    ``oracle.adi`` on its cached shifted inverses instead).  ``prec`` = (u_s, u, u_r, u_c).  With
     ``refine=False`` only the first solve is made and its residual evaluated (plain
     sign-function Newton).  ``Z0``, ``d0``: start the refinement from X_0 = Z0 diag(d0) Z0^T
     instead of a first solve (the first line of Alg 2.2 accepts any starting factor); the
@@ -213,6 +216,27 @@ def ir_ldlt(A, L, S=None, prec=("fp32", "fp64", "fp64", "fp64"), tol: float = 1e
     normW = _norm_ldlt(L, Sm)
     seq = None
     steps_left = i_max
+
+    def make_sequence(us_):
+        if solver == "adi":
+            sq = adi_sequence(A, us_, adi_shifts)
+            info.inversions += sq.J + 1
+            info.mus = list(sq.shifts)
+        else:
+            sq = a_sequence(A, us_, k_max, scaling_kind=scaling)
+            info.inversions += sq.K
+            info.mus = list(sq.mus)
+        return sq
+
+    def inner(us_, sq, G, sv, psd_, tol_in):
+        """One solve at u_s on the sequence; returns (Z, Y, inner iteration count)."""
+        if solver == "adi":
+            Zi, di, ai = lr_adi_ldlt(A, G, sv, us_, sq, psd_, rho, tol_in or 0.0, adi_max)
+            return Zi, np.diag(di), ai.steps
+        Zi, Yi, _, _ = sign_newton_ldlt(A, fl_scaled(G, us_, axis=0), sv, us_, psd=psd_,
+                                        rho=rho, seq=sq, trunc_tol=tol_in)
+        return Zi, Yi, sq.K
+
     if Z0 is not None:
         Z, Y = fl(np.asarray(Z0, np.float64), u), fl(np.diag(np.asarray(d0, np.float64)), u)
         fresh = False
@@ -223,13 +247,11 @@ def ir_ldlt(A, L, S=None, prec=("fp32", "fp64", "fp64", "fp64"), tol: float = 1e
         status = "OK"
         try:
             if fresh:
-                seq = a_sequence(A, us, k_max, scaling_kind=scaling)
-                info.inversions += seq.K
-                info.mus = list(seq.mus)
-                Z, Y, _, _ = sign_newton_ldlt(A, L, Sm, us, psd=psd, rho=rho, seq=seq)
+                seq = make_sequence(us)
+                Z, Y, its = inner(us, seq, L, s if solver == "adi" else Sm, psd, None)
                 Z, Y = fl(Z, u), fl(Y, u)
-                info.newton_total += seq.K
-                info.newton_max = max(info.newton_max, seq.K)
+                info.newton_total += its
+                info.newton_max = max(info.newton_max, its)
             hist = []
             budget = steps_left
             for i in range(1, budget + 1):
@@ -251,18 +273,14 @@ def ir_ldlt(A, L, S=None, prec=("fp32", "fp64", "fp64", "fp64"), tol: float = 1e
                     status = "NOT_CONVERGED"
                     break
                 if seq is None:
-                    seq = a_sequence(A, us, k_max, scaling_kind=scaling)
-                    info.inversions += seq.K
-                    info.mus = list(seq.mus)
+                    seq = make_sequence(us)
                 # scale the correction's right-hand side by a power of two (linearity)
                 e = _pow2_exponent(float(np.max(np.abs(sd))))
                 sd_s = fl(np.ldexp(sd, -e), us)
-                Zd, Yd, _, _ = sign_newton_ldlt(A, fl_scaled(Ld, us, axis=0), sd_s, us, psd=False,
-                                                rho=rho, seq=seq,
-                                                trunc_tol=eta_r / 10.0 if adaptive else None)
+                Zd, Yd, its = inner(us, seq, Ld, sd_s, False, eta_r / 10.0 if adaptive else None)
                 Zd, Yd = fl(Zd, u), np.ldexp(fl(Yd, u), e)
-                info.newton_total += seq.K
-                info.newton_max = max(info.newton_max, seq.K)
+                info.newton_total += its
+                info.newton_max = max(info.newton_max, its)
                 info.refinements += 1
                 steps_left -= 1
                 eta_i = max(eta_s, omega * res) if adaptive else eta_s
