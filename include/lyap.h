@@ -135,6 +135,27 @@ typedef struct {
                         directions that small are the ones the next correction fixes
                         anyway (measured at n = 4096: fp16 inner, omega 1e-3 / 0.1 / 0.3:
                         rank 3796 / 1071 / 289 with the same six or five refinements)   */
+  int solver;        /* inner solver of the first solve and of every correction: 0 (default)
+                        the sign-function Newton iteration (Alg 3.2 / 3.1); 1 the low-rank
+                        ADI method in LDL^T form, the other solver Section 3 says the
+                        refinement's precision settings carry over to.  Residual-factor
+                        recurrence with real shifts p_j < 0: V_j = (A + p_j I)^{-1} W_{j-1},
+                        W_j = W_{j-1} - 2 p_j V_j, Z_j = [Z_{j-1}, V_j], D_j = blkdiag(D_{j-1},
+                        -2 p_j S); the residual of Z_j D_j Z_j^T is W_j S W_j^T.  Shifts:
+                        Wachspress's optimal real shifts for [a, b], b = rho(A) and
+                        a = 1 / rho(A^{-1}) estimated by 24 power-iteration steps (A^{-1} at
+                        u_s, binary32 for fp16 / bf16 / split fp16), J of them for a
+                        reduction of sqrt(u_s) per cycle.  The J shifted inverses are formed
+                        at u_s once (J + 1 inversions with the interval's) and cached like
+                        the Newton sequence; the shifts are used cyclically until
+                        ||W_j S W_j^T||_F <= max(10 u_s, inner) ||W_0 S W_0^T||_F (inner =
+                        eta_r / 10 with ``adaptive``, else 0) or adi_max steps.  Z is
+                        truncated by RankTruncLdlt past rho n columns as in the Newton
+                        solver.  With solver = 1, info.mus holds the shifts and
+                        newton_total / newton_max count ADI steps.                          */
+  int adi_shifts;    /* number J of ADI shifts; 0 (default): from the bound above; at most
+                        min(k_max, 64)                                                      */
+  int adi_max;       /* ADI steps per solve; default 100                                    */
 } lyap_options;
 
 /* Per-solve diagnostics (Table 4.1 columns plus timings). */
@@ -149,7 +170,7 @@ typedef struct {
   int refinements;        /* correction solves performed                                 */
   int rank;               /* columns of the returned Z                                   */
   int n_mu;               /* entries used in mus                                         */
-  double mus[64];         /* Frobenius scalings mu_0 .. mu_{K-1}                         */
+  double mus[64];         /* scalings mu_0 .. mu_{K-1} (ADI solver: the shifts p_1 .. p_J) */
   double onenorm[64];     /* ||A_k + I||_1 after each Newton step                        */
   double phase_ms[8];     /* 0 inversions, 1 Newton update+norms, 2 factor products,
                              3 in-solver truncation, 4 residual factorisation,
@@ -179,7 +200,8 @@ int lyap_create(lyap_handle* h, int device);
 int lyap_destroy(lyap_handle h);
 /* Section 4.1 defaults: tol 1e-13, i_max 50, k_max 50, rho 0.1, eta_r 1e-4, eta_s 10u,
  * delta_off 1e-2, theta 0.9, refine 1, psd -1, form 0, scaling 0 (Frobenius), escalate 0,
- * reuse -1. */
+ * reuse -1, adaptive 0, pivoting 0, omega 0.1, solver 0 (Newton), adi_shifts 0 (automatic),
+ * adi_max 100. */
 void lyap_default_options(lyap_options* opt);
 /* Human-readable text of a status code (static string). */
 const char* lyap_strerror(int code);

@@ -43,7 +43,8 @@ class Options(ctypes.Structure):
                 ("refine", ctypes.c_int), ("psd", ctypes.c_int), ("form", ctypes.c_int),
                 ("scaling", ctypes.c_int), ("escalate", ctypes.c_int), ("reuse", ctypes.c_int),
                 ("adaptive", ctypes.c_int), ("pivoting", ctypes.c_int),
-                ("omega", ctypes.c_double)]
+                ("omega", ctypes.c_double), ("solver", ctypes.c_int),
+                ("adi_shifts", ctypes.c_int), ("adi_max", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):

@@ -135,7 +135,8 @@ static bool valid_options(const lyap_options& o, const double* S, int lds) {
          !(o.form == 1 && S != nullptr) && o.scaling >= 0 && o.scaling <= 4 &&
          (o.escalate == 0 || o.escalate == 1) && o.reuse >= -1 && o.reuse <= 1 &&
          o.delta_off >= 0 && lds >= 0 && (o.adaptive == 0 || o.adaptive == 1) &&
-         o.omega >= 0 && (o.pivoting == 0 || o.pivoting == 1);
+         o.omega >= 0 && (o.pivoting == 0 || o.pivoting == 1) && (o.solver == 0 || o.solver == 1) &&
+         o.adi_shifts >= 0 && o.adi_shifts <= 64 && o.adi_max >= 1;
 }
 
 // ws == NULL: the solve runs in ``own`` (grown on demand, ``epoch`` bumped on every
@@ -261,6 +262,9 @@ void lyap_default_options(lyap_options* o) {
   o->adaptive = 0;
   o->pivoting = 0;
   o->omega = 0.1;
+  o->solver = 0;
+  o->adi_shifts = 0;
+  o->adi_max = 100;
 }
 
 int lyap_workspace_size(int n, int m, int u_s, const lyap_options* opt, size_t* bytes) {

@@ -42,6 +42,22 @@ __global__ void k_copy_block(int rows, int cols, const double* __restrict__ src,
   dst[(long)i * ldd + j] = v;
 }
 
+// dst += alpha src (rows x cols blocks).
+__global__ void k_add_block(int rows, int cols, double alpha, const double* __restrict__ src,
+                            long lds, double* __restrict__ dst, long ldd) {
+  long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  long total = (long)rows * cols;
+  if (idx >= total) return;
+  int i = (int)(idx / cols), j = (int)(idx % cols);
+  dst[(long)i * ldd + j] += alpha * src[(long)i * lds + j];
+}
+
+// M_ii += p.
+__global__ void k_add_diag(int n, double* __restrict__ M, long ld, double p) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) M[(long)i * ld + i] += p;
+}
+
 template <class T>
 __global__ void k_cast(int rows, int cols, const double* __restrict__ src, long lds,
                        T* __restrict__ dst) {
@@ -465,6 +481,23 @@ int copy_block(hipStream_t s, int rows, int cols, const double* src, long lds, d
   if (total <= 0) return LYAP_OK;
   hipLaunchKernelGGL(k_copy_block, dim3(nblk(total)), dim3(256), 0, s, rows, cols, src, lds, dst,
                      ldd, colscale, scale);
+  LYAP_HIP(hipGetLastError());
+  return LYAP_OK;
+}
+
+int add_block(hipStream_t s, int rows, int cols, double alpha, const double* src, long lds,
+              double* dst, long ldd) {
+  long total = (long)rows * cols;
+  if (total <= 0) return LYAP_OK;
+  hipLaunchKernelGGL(k_add_block, dim3(nblk(total)), dim3(256), 0, s, rows, cols, alpha, src, lds,
+                     dst, ldd);
+  LYAP_HIP(hipGetLastError());
+  return LYAP_OK;
+}
+
+int add_diag(hipStream_t s, int n, double* M, long ld, double p) {
+  if (n <= 0) return LYAP_OK;
+  hipLaunchKernelGGL(k_add_diag, dim3(nblk(n)), dim3(256), 0, s, n, M, ld, p);
   LYAP_HIP(hipGetLastError());
   return LYAP_OK;
 }

@@ -36,6 +36,11 @@ int fill_f64(hipStream_t s, double* p, long count, double value);
 // and global scale.
 int copy_block(hipStream_t s, int rows, int cols, const double* src, long lds, double* dst,
                long ldd, const double* colscale = nullptr, double scale = 1.0);
+// dst += alpha src over a rows x cols block.
+int add_block(hipStream_t s, int rows, int cols, double alpha, const double* src, long lds,
+              double* dst, long ldd);
+// M_ii += p for i < n.
+int add_diag(hipStream_t s, int n, double* M, long ld, double p);
 // Round an FP64 rows x cols block to storage ``st`` (F64/F32/F16/BF16) into dst (ld = cols).
 int cast_store(hipStream_t s, Store st, int rows, int cols, const double* src, long lds,
                void* dst);

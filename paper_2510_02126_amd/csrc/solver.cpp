@@ -88,8 +88,65 @@ double round_host(double x, Prec p) {
 }
 
 // power-iteration steps of the 2-norm and spectral-radius estimates of the optional scalings
+// and of the ADI solver's spectral interval
 constexpr int NORM_ITERS = 12;
 constexpr int RHO_ITERS = 24;
+
+// ------------------------------------------------- elliptic functions for the ADI shifts
+// Arithmetic-geometric mean of x >= y > 0.
+double agm(double x, double y) {
+  for (int i = 0; i < 64 && x - y > 1e-16 * x; ++i) {
+    const double t = 0.5 * (x + y);
+    y = std::sqrt(x * y);
+    x = t;
+  }
+  return x;
+}
+
+// Complete elliptic integral K of modulus k with complementary modulus kp:
+// K = pi / (2 AGM(1, kp)) (Gauss).
+double ellip_k(double kp) { return 1.5707963267948966 / agm(1.0, kp); }
+
+// Jacobi dn(u | k) by the descending Landen (AGM) scheme of Abramowitz and Stegun 16.4:
+// a_0 = 1, b_0 = kp, c_0 = k; a_{i+1} = (a_i + b_i) / 2, b_{i+1} = sqrt(a_i b_i),
+// c_{i+1} = (a_i - b_i) / 2 until c_N is negligible; phi_N = 2^N a_N u,
+// phi_{i-1} = (phi_i + asin(c_i sin(phi_i) / a_i)) / 2; dn = cos(phi_0) / cos(phi_1 - phi_0).
+double jacobi_dn(double u, double k, double kp) {
+  double a[40], c[40];
+  a[0] = 1.0;
+  c[0] = k;
+  double b = kp;
+  int N = 0;
+  while (N < 38 && std::fabs(c[N]) > 1e-17 * a[N]) {
+    a[N + 1] = 0.5 * (a[N] + b);
+    c[N + 1] = 0.5 * (a[N] - b);
+    b = std::sqrt(a[N] * b);
+    ++N;
+  }
+  if (N == 0) return 1.0;  // k = 0
+  double phi = std::ldexp(a[N] * u, N);
+  double phi1 = phi;
+  for (int i = N; i >= 1; --i) {
+    phi1 = phi;
+    phi = 0.5 * (phi + std::asin(c[i] * std::sin(phi) / a[i]));
+  }
+  return std::cos(phi) / std::cos(phi1 - phi);
+}
+
+// Wachspress's optimal real ADI shifts for a spectrum of -A inside [a, b]: with kp = a / b,
+// k = sqrt(1 - kp^2), K = K(k), the shifts are p_i = -b dn((2i - 1) K / (2J) | k), i <= J.
+// J = 0 asks for the count that brings the ADI error function below eps over [a, b]:
+// J = ceil(K ln(4 / eps) / (pi K(kp))).
+std::vector<double> adi_shifts(double a, double b, int J, double eps) {
+  if (!(a < b)) return std::vector<double>(std::max(J, 1), -b);
+  const double kp = a / b;
+  const double k = std::sqrt((1.0 - kp) * (1.0 + kp));
+  const double K = ellip_k(kp), Kp = ellip_k(k);
+  if (J <= 0) J = std::max(1, (int)std::ceil(K * std::log(4.0 / eps) / (3.141592653589793 * Kp)));
+  std::vector<double> p(J);
+  for (int i = 0; i < J; ++i) p[i] = -b * jacobi_dn((2.0 * i + 1.0) * K / (2.0 * J), k, kp);
+  return p;
+}
 
 }  // namespace
 
@@ -170,6 +227,7 @@ struct Solver::Ctx {
   std::vector<double> svec;
   int cap;
   int K = 0;
+  int iters = 0;  // steps of the last inner solve (Newton steps or ADI steps)
   std::vector<double> mus;
   double normA = 0.0, normW = 0.0;
   unsigned long long fp = 0;
@@ -344,6 +402,95 @@ int Solver::a_iteration(Ctx& c) {
   return LYAP_NOT_STABLE;
 }
 
+// ------------------------------------------------------------------- ADI sequence
+// (A + p I)^{-1} at u_s into slot j (A^T's with the same shifts is its transpose).  With
+// opt.pivoting = 1 the butterfly inversion is tried first and checked by its probe, as in the
+// A-iteration.
+int Solver::shifted_inverse(Ctx& c, int j, double p) {
+  const int n = c.n;
+  hipStream_t s = c.s;
+  double* scal = c.scal;
+  double* out = (c.us == Prec::F64) ? static_cast<double*>(c.slot(j)) : c.Ainv;
+  LYAP_TRY(copy_block(s, n, n, c.A, c.lda, c.Ak, n));
+  LYAP_TRY(add_diag(s, n, c.Ak, n, p));
+  bool rbt = c.opt.pivoting == 1 && n % 4 == 0;
+  int fl[2];
+  for (;;) {
+    LYAP_TRY(fill_int(s, c.flags, 2, 0));
+    c.arena.reset();
+    if (rbt) {
+      LYAP_TRY(rbt_invert(s, c.us, n, c.Ak, n, out, n, c.arena, c.flags, c.kt, nullptr,
+                          0x4144495348ull + (unsigned)j, scal + 13));
+      LYAP_TRY(sumsq(s, n, n, c.Ak, n, scal + 18, c.part));
+      LYAP_TRY(sumsq(s, n, n, out, n, scal + 19, c.part));
+    } else {
+      LYAP_TRY(invert(s, c.us, n, c.Ak, n, out, n, c.arena, c.flags, true, c.kt, nullptr));
+    }
+    double h[7];
+    LYAP_HIP(hipMemcpyAsync(h, scal + 13, sizeof(h), hipMemcpyDeviceToHost, s));
+    LYAP_HIP(hipMemcpyAsync(fl, c.flags, sizeof(fl), hipMemcpyDeviceToHost, s));
+    LYAP_HIP(hipStreamSynchronize(s));
+    c.info->inversions += 1;
+    if (!rbt) break;
+    const double bound = 8.0 * std::sqrt((double)n) * unit_roundoff(c.us) * std::sqrt(h[5]) *
+                         std::sqrt(h[6]);
+    if (!fl[0] && !fl[1] && std::isfinite(h[0]) && h[0] <= bound) {
+      c.info->rbt_steps += 1;
+      break;
+    }
+    c.info->rbt_fallbacks += 1;
+    rbt = false;
+  }
+  if (fl[0]) return LYAP_SINGULAR;
+  if (fl[1]) return LYAP_NONFINITE;
+  if (c.us != Prec::F64) {
+    LYAP_TRY(absmax_exp(s, n, n, out, n, c.cexp + j, c.flags + 1, c.part));
+    LYAP_TRY(cast_scaled(s, c.cstore, n, n, out, n, c.slot(j), c.cexp + j));
+  } else {
+    LYAP_TRY(fill_int(s, c.cexp + j, 1, 0));
+  }
+  return LYAP_OK;
+}
+
+// Spectral interval [a, b] of -A by power iteration (b = rho(A), a = 1 / rho(A^{-1}) with
+// A^{-1} at u_s, or binary32 for the half-precision solvers), the Wachspress shifts for it
+// and the cached shifted inverses.
+int Solver::adi_sequence(Ctx& c) {
+  const int n = c.n;
+  hipStream_t s = c.s;
+  double* scal = c.scal;
+  c.mus.clear();
+  c.K = 0;
+  LYAP_TRY(specrad_est(s, n, c.A, c.lda, RHO_ITERS, scal + 15, c.vecs));
+  const Prec iop = (c.us == Prec::F64) ? Prec::F64 : Prec::F32;
+  LYAP_TRY(fill_int(s, c.flags, 2, 0));
+  c.arena.reset();
+  LYAP_TRY(invert(s, iop, n, c.A, c.lda, c.Ainv, n, c.arena, c.flags, true, c.kt, nullptr));
+  c.info->inversions += 1;
+  LYAP_TRY(specrad_est(s, n, c.Ainv, n, RHO_ITERS, scal + 16, c.vecs));
+  double h[2];
+  int fl[2];
+  LYAP_HIP(hipMemcpyAsync(h, scal + 15, sizeof(h), hipMemcpyDeviceToHost, s));
+  LYAP_HIP(hipMemcpyAsync(fl, c.flags, sizeof(fl), hipMemcpyDeviceToHost, s));
+  LYAP_HIP(hipStreamSynchronize(s));
+  if (fl[0]) return LYAP_SINGULAR;
+  const double b = h[0], a = 1.0 / h[1];
+  if (fl[1] || !std::isfinite(a) || !std::isfinite(b) || !(a > 0.0) || !(b > 0.0))
+    return LYAP_NONFINITE;
+  std::vector<double> p = adi_shifts(std::min(a, b), b, c.opt.adi_shifts,
+                                     std::sqrt(unit_roundoff(c.us)));
+  if ((int)p.size() > c.lay.slots) p = adi_shifts(std::min(a, b), b, c.lay.slots, 0.0);
+  for (int j = 0; j < (int)p.size(); ++j) LYAP_TRY(shifted_inverse(c, j, p[j]));
+  c.mus = p;
+  c.K = (int)p.size();
+  c.info->n_mu = std::min(c.K, 64);
+  for (int j = 0; j < c.info->n_mu; ++j) {
+    c.info->mus[j] = p[j];
+    c.info->onenorm[j] = 0.0;
+  }
+  return LYAP_OK;
+}
+
 // The inverse sequence of A at u_s: replayed from the workspace when it holds the sequence of
 // this A (content fingerprint, n, u_s, same workspace) and the call allows it, else computed.
 int Solver::ensure_sequence(Ctx& c) {
@@ -351,7 +498,8 @@ int Solver::ensure_sequence(Ctx& c) {
   auto t0 = clk::now();
   const bool match = key_.K > 0 && key_.ws == c.base && key_.epoch == c.epoch &&
                      key_.fp == c.fp && key_.n == c.n && key_.us == c.us &&
-                     key_.slots == c.lay.slots;
+                     key_.slots == c.lay.slots && key_.solver == c.opt.solver &&
+                     key_.adi_shifts == c.opt.adi_shifts;
   if (c.may_reuse && match) {
     c.K = key_.K;
     c.mus = key_.mus;
@@ -363,7 +511,7 @@ int Solver::ensure_sequence(Ctx& c) {
     }
   } else {
     key_ = CacheKey();
-    const int code = a_iteration(c);
+    const int code = c.opt.solver == 1 ? adi_sequence(c) : a_iteration(c);
     c.info->phase_ms[0] += ms_since(t0);
     if (code != LYAP_OK) {
       c.K = 0;
@@ -375,6 +523,8 @@ int Solver::ensure_sequence(Ctx& c) {
     key_.n = c.n;
     key_.us = c.us;
     key_.slots = c.lay.slots;
+    key_.solver = c.opt.solver;
+    key_.adi_shifts = c.opt.adi_shifts;
     key_.mus = c.mus;
     key_.onenorm.assign(c.info->onenorm, c.info->onenorm + std::min(c.K, 64));
     key_.K = c.K;
@@ -490,6 +640,100 @@ int Solver::factor_iteration(Ctx& c, const double* L0, long ld0, int m0, int ort
   }
   for (double& x : d) x *= 0.5;
   return LYAP_OK;
+}
+
+// ------------------------------------------------------------------ ADI iteration
+// Low-rank ADI in LDL^T form with real shifts on the cached (A + p_j I)^{-1}: W_0 = L0,
+// V = (A + p I)^{-1} W (operands at u_s, as in the Newton products), W <- W - 2 p V,
+// Z <- [Z, V], d <- [d, -2 p d0], until ||W diag(d0) W^T||_F <= tol ||L0 diag(d0) L0^T||_F
+// with tol = max(10 u_s, trunc_thr), or opt.adi_max steps.  W is kept in FP64 in Gm
+// (n x m0, leading dimension m0); its Gram matrix W^T W (in Hm) gives the residual norm.
+// Result in Zs (n x cols); c.iters receives the step count.
+int Solver::adi_iteration(Ctx& c, const double* L0, long ld0, int m0,
+                          const std::vector<double>& d0, bool psd, int& cols,
+                          std::vector<double>& d, double trunc_thr) {
+  hipStream_t s = c.s;
+  const int n = c.n, cap = c.cap;
+  double* Zs = c.Zs;
+  double* W = c.Gm;
+  cols = 0;
+  d.clear();
+  c.orth = 0;
+  c.iters = 0;
+  if (m0 == 0) return LYAP_OK;
+  if (m0 > n) return LYAP_CAPACITY;
+  LYAP_TRY(copy_block(s, n, m0, L0, ld0, W, m0));
+  LYAP_TRY(upload_d(c, d0, c.dvec2));
+  auto wnorm = [&](double& out) -> int {
+    GemmDesc g;
+    g.M = m0; g.N = m0; g.K = n;
+    g.A = W; g.sar = 1; g.sac = m0;
+    g.B = W; g.sbr = m0; g.sbc = 1;
+    g.C = c.Hm; g.ldc = m0;
+    c.arena.reset();
+    size_t welems = std::min((size_t)64 * m0 * m0, (c.arena.cap - 4096) / sizeof(double));
+    double* part = c.arena.take<double>(welems);
+    LYAP_TRY(gemm_f64(s, g, part, part ? welems : 0));
+    LYAP_TRY(wsumsq(s, m0, c.Hm, m0, c.dvec2, c.scal + 17, c.part));
+    double v[2];
+    int fl = 0;
+    LYAP_HIP(hipMemcpyAsync(v, c.scal + 17, sizeof(double), hipMemcpyDeviceToHost, s));
+    LYAP_HIP(hipMemcpyAsync(&fl, c.flags + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+    LYAP_HIP(hipStreamSynchronize(s));
+    if (fl) return LYAP_NONFINITE;
+    out = std::sqrt(std::max(v[0], 0.0));
+    return LYAP_OK;
+  };
+  LYAP_TRY(fill_int(s, c.flags + 1, 1, 0));
+  double nrm0 = 0.0;
+  LYAP_TRY(wnorm(nrm0));
+  if (!std::isfinite(nrm0)) return LYAP_NONFINITE;
+  if (nrm0 == 0.0) return LYAP_OK;
+  const double tol = std::max(10.0 * unit_roundoff(c.us), trunc_thr);
+  const double thr = std::max(unit_roundoff(c.us), trunc_thr);
+  const int trunc_at = (int)std::floor(c.opt.rho * n);
+  const int J = c.K;
+  for (int t = 0; t < c.opt.adi_max; ++t) {
+    const int j = t % J;
+    const double p = c.mus[j];
+    if (cols + m0 > cap) {
+      LYAP_TRY(rank_trunc(c, Zs, cap, cols, d, thr, psd));
+      if (cols + m0 > cap) return LYAP_CAPACITY;
+    }
+    GemmDesc g;
+    g.M = n; g.N = m0; g.K = n;
+    g.A = c.slot(j);
+    if (c.trans) { g.sar = 1; g.sac = n; }  // (A + p I)^{-T} = (A^T + p I)^{-1}
+    else { g.sar = n; g.sac = 1; }
+    g.B = W; g.sbr = m0; g.sbc = 1;
+    g.C = Zs + cols; g.ldc = cap;
+    if (c.us == Prec::F64) {
+      LYAP_TRY(gemm_f64(s, g));
+    } else {
+      LYAP_TRY(col_exponents(s, n, m0, W, m0, c.colexp, c.flags + 1, c.bits));
+      g.a_exp = c.cexp + j;
+      g.b_colexp = c.colexp;
+      LYAP_TRY(gemm_lp(s, c.us, c.cstore, Store::F64, Store::F64, g));
+    }
+    LYAP_TRY(add_block(s, n, m0, -2.0 * p, Zs + cols, cap, W, m0));
+    for (int k = 0; k < m0; ++k) d.push_back(-2.0 * p * d0[k]);
+    cols += m0;
+    if (cols > trunc_at) LYAP_TRY(rank_trunc(c, Zs, cap, cols, d, thr, psd));
+    c.iters = t + 1;
+    double nrm = 0.0;
+    LYAP_TRY(wnorm(nrm));
+    if (!std::isfinite(nrm)) return LYAP_NONFINITE;
+    if (nrm <= tol * nrm0) break;
+  }
+  return LYAP_OK;
+}
+
+int Solver::inner_solve(Ctx& c, const double* L0, long ld0, int m0, int orth0,
+                        const std::vector<double>& d0, bool psd, int& cols,
+                        std::vector<double>& d, double trunc_thr) {
+  if (c.opt.solver == 1) return adi_iteration(c, L0, ld0, m0, d0, psd, cols, d, trunc_thr);
+  c.iters = c.K;
+  return factor_iteration(c, L0, ld0, m0, orth0, d0, psd, cols, d, trunc_thr);
 }
 
 // ||Z diag(d) Z^T||_F = sqrt(sum_ij d_i d_j (Z^T Z)_ij^2)
@@ -739,8 +983,7 @@ int Solver::refine_loop(Ctx& c, int& cols, std::vector<double>& d, int steps, in
       if (rd > 0) std::frexp(std::fabs(sd[0]), &e);
       std::vector<double> sds(sd);
       for (double& x : sds) x = std::ldexp(x, -e);
-      LYAP_TRY(factor_iteration(c, c.Zd, cap, rd, rd, sds, false, cd, dd,
-                                inner_thr));  // U Q_t
+      LYAP_TRY(inner_solve(c, c.Zd, cap, rd, rd, sds, false, cd, dd, inner_thr));  // U Q_t
       for (double& x : dd) x = std::ldexp(x, e);
     } else {
       // Fragment 2.1: R = L+ L+^T - L- L-^T with L+- = U Q_+- |Lambda_+-|^(1/2), here as
@@ -764,9 +1007,11 @@ int Solver::refine_loop(Ctx& c, int& cols, std::vector<double>& d, int steps, in
       }
       int cp = 0, cm = 0;
       std::vector<double> ddp, ddm;
-      LYAP_TRY(factor_iteration(c, Fb, cap, rp, rp, dp, true, cp, ddp, inner_thr));
+      LYAP_TRY(inner_solve(c, Fb, cap, rp, rp, dp, true, cp, ddp, inner_thr));
+      const int iters_p = c.iters;
       LYAP_TRY(copy_block(s, n, cp, c.Zs, cap, Zpm, cap));
-      LYAP_TRY(factor_iteration(c, Fb + rp, cap, rm, rm, dm, true, cm, ddm, inner_thr));
+      LYAP_TRY(inner_solve(c, Fb + rp, cap, rm, rm, dm, true, cm, ddm, inner_thr));
+      c.iters = std::max(c.iters, iters_p);
       if (cp + cm > cap) return LYAP_CAPACITY;
       LYAP_TRY(copy_block(s, n, cm, c.Zs, cap, Zpm + cp, cap));
       cd = cp + cm;
@@ -779,8 +1024,8 @@ int Solver::refine_loop(Ctx& c, int& cols, std::vector<double>& d, int steps, in
     for (double& x : dd) x = round_host(x, c.u);
     LYAP_HIP(hipStreamSynchronize(s));
     info->phase_ms[2] += ms_since(t0);
-    info->newton_total += c.K;
-    info->newton_max = std::max(info->newton_max, c.K);
+    info->newton_total += c.iters;
+    info->newton_max = std::max(info->newton_max, c.iters);
     info->refinements += 1;
     // projected solution update (Fragment 2.4; Fragment 2.2 for the Cholesky type)
     t0 = clk::now();
@@ -939,15 +1184,15 @@ int Solver::solve(hipStream_t s, char* ws, size_t ws_bytes, unsigned long ws_epo
       code = ensure_sequence(c);
       if (code == LYAP_OK) {
         auto t0 = clk::now();
-        LYAP_TRY(factor_iteration(c, c.L, c.ldl, m, 0, c.svec, c.psd, cols, d));
+        LYAP_TRY(inner_solve(c, c.L, c.ldl, m, 0, c.svec, c.psd, cols, d));
         c.zc_orth = cols > 0 && c.orth >= cols && c.u == Prec::F64;
         LYAP_TRY(copy_block(s, n, cols, c.Zs, cap, c.Zc, cap));
         LYAP_TRY(round_block(s, store_of(c.u), n, cols, c.Zc, cap));
         for (double& x : d) x = round_host(x, c.u);
         LYAP_HIP(hipStreamSynchronize(s));
         info->phase_ms[2] += ms_since(t0);
-        info->newton_total += c.K;
-        info->newton_max = std::max(info->newton_max, c.K);
+        info->newton_total += c.iters;
+        info->newton_max = std::max(info->newton_max, c.iters);
       }
     }
     if (code == LYAP_OK) {

@@ -53,11 +53,19 @@ class Solver {
  private:
   struct Ctx;
   int a_iteration(Ctx& c);
+  int adi_sequence(Ctx& c);
+  int shifted_inverse(Ctx& c, int j, double p);
   int ensure_sequence(Ctx& c);
   int refine_loop(Ctx& c, int& cols, std::vector<double>& d, int steps, int& status);
   int factor_iteration(Ctx& c, const double* L0, long ld0, int m0, int orth0,
                        const std::vector<double>& d0, bool psd, int& cols,
                        std::vector<double>& d, double trunc_thr = 0.0);
+  int adi_iteration(Ctx& c, const double* L0, long ld0, int m0, const std::vector<double>& d0,
+                    bool psd, int& cols, std::vector<double>& d, double trunc_thr);
+  // the chosen inner solver on the cached sequence; c.iters receives its step count
+  int inner_solve(Ctx& c, const double* L0, long ld0, int m0, int orth0,
+                  const std::vector<double>& d0, bool psd, int& cols, std::vector<double>& d,
+                  double trunc_thr = 0.0);
   int rank_trunc(Ctx& c, double* Zb, long ldb, int& cols, std::vector<double>& d, double thr,
                  bool psd);
   int xnorm(Ctx& c, const double* Zb, long ldb, int cols, const std::vector<double>& d,
@@ -78,7 +86,7 @@ class Solver {
     const char* ws = nullptr;
     unsigned long epoch = 0;
     unsigned long long fp = 0;
-    int n = 0, slots = 0;
+    int n = 0, slots = 0, solver = 0, adi_shifts = 0;
     Prec us = Prec::F64;
     std::vector<double> mus, onenorm;
     int K = 0;
