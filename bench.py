@@ -100,6 +100,17 @@ def _traffic_run(lyap, torch, A, L, S, us):
     print("calibration copy bytes", x.numel() * 8, flush=True)
 
 
+def _inverse_run(lyap, torch, A, spec):
+    """Untimed: three inversions of the n = 4096 matrix at ``dtype[:pivot]`` (pivot "partial",
+    "none" or "rbt"), for per-kernel profiles of the inversion alone."""
+    dt, _, pv = spec.partition(":")
+    pivot = {"": True, "partial": True, "none": False, "rbt": "rbt"}[pv]
+    for _ in range(3):
+        lyap.inverse(A, dt, pivot=pivot)
+    torch.cuda.synchronize()
+    print("inversions done", dt, pv or "partial", flush=True)
+
+
 def _mfma_run(lyap, torch, A, L, S, us):
     """Untimed: one solve at inner precision ``us``, then one FP64 and one FP32 product of
     4096^3 (torch.matmul, 137.4 GFLOP each) whose MFMA op counters give the counters' unit.
@@ -204,12 +215,16 @@ def main():
     ap.add_argument("--adaptive", default="fp16,fp32",
                     help="inner precisions also timed with adaptive inexact inner tolerances")
     ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--skip-adi", action="store_true",
+                    help="skip the low-rank ADI inner-solver comparison")
     ap.add_argument("--batched", action="store_true",
                     help="also time 256 independent equations, n in [64, 512] (batched mode)")
     ap.add_argument("--traffic-run", action="store_true",
                     help="one untimed IR solve and a calibration copy (for HBM counters)")
     ap.add_argument("--mfma-run", action="store_true",
                     help="one untimed solve and calibration products (for MFMA counters)")
+    ap.add_argument("--inverse-run", default=None, metavar="DTYPE[:PIVOT]",
+                    help="three untimed inversions of the workload matrix (for kernel profiles)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the solver has no multi-GPU path; --gpus must be 1.",
@@ -233,6 +248,9 @@ def main():
     if args.mfma_run:
         _mfma_run(lyap, torch, A, L, S, args.us or "fp32")
         return
+    if args.inverse_run:
+        _inverse_run(lyap, torch, A, args.inverse_run)
+        return
 
     inner = [x.strip() for x in args.inner.split(",") if x.strip()]
     base = _run_path(lyap, torch, cfg, A, L, S, "fp64", args.steps, args.warmup)
@@ -255,6 +273,22 @@ def main():
         fast[us] = _run_path(lyap, torch, cfg, A, L, S, us, args.steps, args.warmup, adaptive=1,
                              pivoting=1)
         print(f"ir {us} adaptive rbt: {fast[us]['summary']}", file=sys.stderr, flush=True)
+    # the second inner solver (low-rank ADI): FP64 ADI against IR with an fp32 ADI inner solve,
+    # both with butterfly inversions
+    adi = None
+    if not args.skip_adi:
+        adi64 = _run_path(lyap, torch, cfg, A, L, S, "fp64", args.steps, args.warmup, solver=1,
+                          pivoting=1)
+        print(f"adi fp64 rbt: {adi64['summary']}", file=sys.stderr, flush=True)
+        adi32 = _run_path(lyap, torch, cfg, A, L, S, "fp32", args.steps, args.warmup, solver=1,
+                          pivoting=1, adaptive=1)
+        print(f"adi ir fp32 adaptive rbt: {adi32['summary']}", file=sys.stderr, flush=True)
+        a64 = adi64["summary"]["solves_per_s"]
+        adi = {"fp64_adi_rbt": adi64["summary"],
+               "ir_fp32_adi_adaptive_rbt": dict(
+                   adi32["summary"],
+                   speedup_vs_fp64_adi=(round(adi32["summary"]["solves_per_s"] / a64, 4)
+                                        if adi64["ok"] and adi32["ok"] else None))}
     head = runs[inner[0]] if inner else base
     sps64 = base["summary"]["solves_per_s"]
 
@@ -318,6 +352,7 @@ def main():
                                                     if sps64 > 0 and r["ok"] else None))
             for us, r in adaptive.items()},
         "fp64_sign_newton_rbt": base_rbt["summary"],
+        "low_rank_adi": adi,
         "ir_adaptive_rbt": {
             us: dict(r["summary"], speedup_vs_fp64_rbt=(
                 round(r["summary"]["solves_per_s"] / base_rbt["summary"]["solves_per_s"], 4)

@@ -1,11 +1,16 @@
 // Matrix-core products for gfx950.
 //
-// Two kernel families:
+// Kernel families:
 //  * gemm_k4   -- 16x16x4 MFMA with one operand element per lane (FP64: v_mfma_f64_16x16x4f64,
 //                 binary32: v_mfma_f32_16x16x4f32).  Block tile 64x64, k-tile 16, 4 waves in
 //                 a 2x2 grid, each wave 32x32 (2x2 MFMA tiles).
+//  * gemm_big  -- the same MFMA shapes on a 128x128 block tile with eight waves (2x4, each
+//                 64x32), a double-buffered 128-byte k-slice in LDS and register prefetch of
+//                 the next slice; chosen for products with enough tiles and a long k-loop.
 //  * gemm_k32  -- 16x16x32 MFMA with eight operand elements per lane (fp16 / bf16 operands,
 //                 binary32 accumulation).  Block tile 64x64, k-tile 32.
+//  * gemm_k32s -- split fp16 operands x = hi + 2^-11 lo: three 16x16x32 MFMAs per step
+//                 (hi*hi and the two cross terms) in binary32 accumulation.
 // Operands are read through generic strides so that transposed views need no copies; the
 // loader picks a coalesced thread mapping from whichever stride is unit.  Ragged M, N, K are
 // zero-padded in LDS.  FP64 products can split K across blocks, with a deterministic

@@ -1,7 +1,7 @@
 """Parity at the full size of the n = 4096 workload (lyapgen.config("large"): A = Q T Q^T with
-kappa ~ 1e3, W = L S L^T indefinite, m = 8), in the configuration bench.py times (the
-fp32-inner mixed-precision IR solve and the FP64 sign-function Newton solve) and with the
-fp16 and bf16 inner solvers.
+kappa ~ 1e3, W = L S L^T indefinite, m = 8), in every configuration bench.py times: IR with
+fp16, bf16 and fp32 inner solvers, the FP64 sign-function Newton solve, the adaptive inner
+tolerances, the butterfly inversion, and the low-rank ADI inner solver.
 
   * The relative residual of eq (4.1), recomputed on the host in float64 by the oracle from
     the returned factors, is <= 1e-13 and agrees with the one the library reports.
@@ -44,17 +44,32 @@ def large():
     return cfg, gold
 
 
-@pytest.mark.parametrize("prec", [("fp32", "fp64", "fp64", "fp64"), ("fp64",) * 4,
-                                  ("fp16", "fp64", "fp64", "fp64"),
-                                  ("bf16", "fp64", "fp64", "fp64")],
-                         ids=["ir_fp32_inner", "fp64_sign_newton", "ir_fp16_inner",
-                              "ir_bf16_inner"])
-def test_large_workload_parity(lyap, large, prec):
+IR = ("fp64", "fp64", "fp64")
+# every configuration bench.py times at this size
+CONFIGS = {
+    "ir_fp32_inner": (("fp32",) + IR, {}),
+    "fp64_sign_newton": (("fp64",) * 4, {}),
+    "ir_fp16_inner": (("fp16",) + IR, {}),
+    "ir_bf16_inner": (("bf16",) + IR, {}),
+    "ir_fp16_adaptive": (("fp16",) + IR, {"adaptive": 1}),
+    "ir_fp32_adaptive": (("fp32",) + IR, {"adaptive": 1}),
+    "fp64_butterfly": (("fp64",) * 4, {"pivoting": 1}),
+    "ir_fp16_adaptive_butterfly": (("fp16",) + IR, {"adaptive": 1, "pivoting": 1}),
+    "ir_fp32_adaptive_butterfly": (("fp32",) + IR, {"adaptive": 1, "pivoting": 1}),
+    "fp64_adi_butterfly": (("fp64",) * 4, {"solver": 1, "pivoting": 1}),
+    "ir_fp32_adi_adaptive_butterfly": (("fp32",) + IR, {"solver": 1, "adaptive": 1,
+                                                        "pivoting": 1}),
+}
+
+
+@pytest.mark.parametrize("name", list(CONFIGS))
+def test_large_workload_parity(lyap, large, name):
     cfg, gold = large
+    prec, opts = CONFIGS[name]
     A, L, S = cfg["A"], cfg["L"], cfg["S"]
-    print(f"large workload n=4096 m=8 precisions={prec}", flush=True)
+    print(f"large workload n=4096 m=8 {name}: precisions={prec} options={opts}", flush=True)
     Ad, Ld, Sd = (torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in (A, L, S))
-    Z, D, info = lyap.solve(Ad, Ld, Sd, precisions=prec)
+    Z, D, info = lyap.solve(Ad, Ld, Sd, precisions=prec, **opts)
     Z, D = Z.cpu().numpy(), D.cpu().numpy()
     res = R.relres(A, L, S, Z, D)
     ii, jj = np.array(gold["i"]), np.array(gold["j"])
