@@ -9,13 +9,18 @@ One step = one complete lyap_solve call (inversions, factor iteration, residual
 factorisations, corrections and updates) that must end with res <= 1e-13; a run whose solves
 do not reach it is reported as DNF with its attained residual.  The plain FP64 solve and IR
 with fp16, bf16 and fp32 inner solvers are timed; ``value`` is the IR with the fp16 inner
-solver (the inner precision the workload names), the others are reported beside it.  The
-first timed solve of each path is re-checked on the host: its residual (eq 4.1) recomputed
-in float64 NumPy from the returned factors.  Prints one JSON line.
+solver (the inner precision the workload names), the others are reported beside it: the
+same paths with adaptive inner tolerances and with the butterfly inversion, the low-rank ADI
+inner solver against FP64 ADI, and 256 independent equations of n in [64, 512] (a loop of
+FP64 solves against the batched entry point).  The first timed solve of each path is
+re-checked on the host: its residual (eq 4.1) recomputed in float64 NumPy from the returned
+factors.  Prints one JSON line.
 
-  python bench.py [--steps K] [--warmup W] [--inner fp16,bf16,fp32] [--skip-cpu] [--batched]
+  python bench.py [--steps K] [--warmup W] [--inner fp16,bf16,fp32] [--adaptive fp16,fp32]
+                  [--skip-cpu] [--skip-adi] [--skip-batched]
   python bench.py --traffic-run   (one IR solve and a calibration copy, for HBM counters)
   python bench.py --mfma-run [--us fp64]   (one solve and calibration products, for MFMA counters)
+  python bench.py --inverse-run fp64:rbt   (three inversions, for kernel profiles)
 """
 from __future__ import annotations
 
@@ -46,9 +51,10 @@ def _time_inverse(lyap, torch, A, us, reps=3, pivot=True):
     return e0.elapsed_time(e1) / reps / 1e3
 
 
-def _batched(lyap, torch, us):
+def _batched(lyap, torch):
     """256 independent equations (n ~ U{64..512}, m ~ U{1..8}): a host loop of FP64 solves
-    against the batched entry point (FP64 and IR at ``us``).  One warm-up pass each."""
+    against the batched entry point (FP64, and IR with fp16 / fp32 inner solves, with fixed
+    and adaptive inner tolerances).  One warm-up pass each."""
     import lyapgen
 
     batch = lyapgen.batch_family()
@@ -60,13 +66,17 @@ def _batched(lyap, torch, us):
         return [lyap.solve(a, l, None, precisions=("fp64",) * 4, raise_on_error=False)[2]
                 for a, l in zip(As, Ls)]
 
-    def batched(p):
+    def batched(p, **opts):
         return [o[2] for o in lyap.solve_batched(As, Ls, None, precisions=p,
-                                                 raise_on_error=False)]
+                                                 raise_on_error=False, **opts)]
 
+    ir = ("fp64", "fp64", "fp64")
     for label, fn in (("loop_fp64", loop),
                       ("batched_fp64", lambda: batched(("fp64",) * 4)),
-                      (f"batched_{us}_ir", lambda: batched((us, "fp64", "fp64", "fp64")))):
+                      ("batched_fp16_ir", lambda: batched(("fp16",) + ir)),
+                      ("batched_fp16_ir_adaptive", lambda: batched(("fp16",) + ir, adaptive=1)),
+                      ("batched_fp32_ir", lambda: batched(("fp32",) + ir)),
+                      ("batched_fp32_ir_adaptive", lambda: batched(("fp32",) + ir, adaptive=1))):
         fn()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -77,6 +87,7 @@ def _batched(lyap, torch, us):
         out[label] = {"solves_per_s": round(len(infos) / dt, 2) if ok else 0.0,
                       "max_res": max(i["res"] for i in infos),
                       "status": "OK" if ok else "DNF"}
+        print(f"batched {label}: {out[label]}", file=sys.stderr, flush=True)
     return out
 
 
@@ -217,8 +228,8 @@ def main():
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-adi", action="store_true",
                     help="skip the low-rank ADI inner-solver comparison")
-    ap.add_argument("--batched", action="store_true",
-                    help="also time 256 independent equations, n in [64, 512] (batched mode)")
+    ap.add_argument("--skip-batched", action="store_true",
+                    help="skip the 256 independent equations, n in [64, 512] (batched mode)")
     ap.add_argument("--traffic-run", action="store_true",
                     help="one untimed IR solve and a calibration copy (for HBM counters)")
     ap.add_argument("--mfma-run", action="store_true",
@@ -317,7 +328,7 @@ def main():
     t_inv_rbt = _time_inverse(lyap, torch, A, "fp64", pivot="rbt")
     inv64_rbt = 2.0 * n ** 3 / t_inv_rbt / 1e12
 
-    batched = _batched(lyap, torch, inner[0] if inner else "fp16") if args.batched else None
+    batched = None if args.skip_batched else _batched(lyap, torch)
 
     cpu = None
     if not args.skip_cpu:

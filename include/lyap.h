@@ -121,8 +121,10 @@ typedef struct {
                         truncation keeps |lambda| > max(u_s, eta_r / 10) max|lambda| (the
                         residual factor is itself truncated at eta_r), and the update after a
                         step with residual res_i keeps |sigma| >= max(eta_s, omega res_i)
-                        max|sigma|.  0 (default): the fixed thresholds of Alg 3.2 and
-                        Fragment 2.4.                                                       */
+                        max|sigma|; a step that contracts the residual by less than half
+                        (res_i > res_{i-1} / 2) switches both back to the fixed thresholds
+                        for the rest of the refinement.  0 (default): the fixed thresholds
+                        of Alg 3.2 and Fragment 2.4.                                        */
   int pivoting;      /* inversions of A_k while ||A_{k-1} + I||_1 >= 1 (afterwards A_k is
                         strictly column diagonally dominant and no pivoting is needed):
                         0 (default) Gauss-Jordan with partial pivoting; 1 random butterfly

@@ -200,7 +200,10 @@ def ir_ldlt(A, L, S=None, prec=("fp32", "fp64", "fp64", "fp64"), tol: float = 1e
     relative (the residual factor is itself truncated at eta_r, so a more accurate correction
     buys nothing), and the update after a step with residual res_i keeps
     sigma >= max(eta_s, omega res_i) max|sigma| (directions that small only change the next
-    residual by about omega res_i, far below the contraction of a refinement step).
+    residual by about omega res_i, far below the contraction of a refinement step).  Because
+    that holds only for directions the next correction fixes, a step that contracts the
+    residual by less than half (res_i > res_{i-1} / 2) switches both inexact thresholds off
+    for the rest of the refinement.
     Returns (Z, d, info) with X ~ Z diag(d) Z^T."""
     us, u, ur, uc = prec
     A = np.asarray(A, np.float64)
@@ -254,11 +257,14 @@ def ir_ldlt(A, L, S=None, prec=("fp32", "fp64", "fp64", "fp64"), tol: float = 1e
                 info.newton_max = max(info.newton_max, its)
             hist = []
             budget = steps_left
+            inexact = adaptive
             for i in range(1, budget + 1):
                 Ld, sd, normR = res_fac_ldlt(A, L, Sm, Z, Y, eta_r, ur)
                 res = normR / (normW + 2.0 * _norm_ldlt(Z, Y) * normA)
                 info.res_hist.append(res)
                 hist.append(res)
+                if inexact and len(hist) >= 2 and hist[-1] > 0.5 * hist[-2]:
+                    inexact = False
                 if not np.isfinite(res):
                     raise NonFiniteError("non-finite residual")
                 if res <= tol:
@@ -277,13 +283,13 @@ def ir_ldlt(A, L, S=None, prec=("fp32", "fp64", "fp64", "fp64"), tol: float = 1e
                 # scale the correction's right-hand side by a power of two (linearity)
                 e = _pow2_exponent(float(np.max(np.abs(sd))))
                 sd_s = fl(np.ldexp(sd, -e), us)
-                Zd, Yd, its = inner(us, seq, Ld, sd_s, False, eta_r / 10.0 if adaptive else None)
+                Zd, Yd, its = inner(us, seq, Ld, sd_s, False, eta_r / 10.0 if inexact else None)
                 Zd, Yd = fl(Zd, u), np.ldexp(fl(Yd, u), e)
                 info.newton_total += its
                 info.newton_max = max(info.newton_max, its)
                 info.refinements += 1
                 steps_left -= 1
-                eta_i = max(eta_s, omega * res) if adaptive else eta_s
+                eta_i = max(eta_s, omega * res) if inexact else eta_s
                 Z, Y = sol_upt_ldlt(Z, Y, Zd, Yd, eta_i, uc, psd)
         except NonFiniteError:
             status = "NONFINITE"

@@ -927,6 +927,7 @@ int Solver::refine_loop(Ctx& c, int& cols, std::vector<double>& d, int steps, in
   lyap_info* info = c.info;
   const double eta_s = c.opt.eta_s > 0.0 ? c.opt.eta_s : 10.0 * unit_roundoff(c.u);
   std::vector<double> hist;  // residuals of this stage (the eq (4.2) test looks at these)
+  bool inexact = c.opt.adaptive != 0;
   status = LYAP_NOT_CONVERGED;
   for (int i = 1; i <= steps; ++i) {
     auto t0 = clk::now();
@@ -939,6 +940,9 @@ int Solver::refine_loop(Ctx& c, int& cols, std::vector<double>& d, int steps, in
     if (info->n_res < 64) info->res_hist[info->n_res++] = res;
     info->res = res;
     hist.push_back(res);
+    // the inexact thresholds only drop what the next correction fixes: a step that contracts
+    // the residual by less than half switches them off for the rest of the refinement
+    if (inexact && hist.size() >= 2 && res > 0.5 * hist[hist.size() - 2]) inexact = false;
     info->phase_ms[4] += ms_since(t0);
     if (!std::isfinite(res)) {
       status = LYAP_NONFINITE;
@@ -971,8 +975,8 @@ int Solver::refine_loop(Ctx& c, int& cols, std::vector<double>& d, int steps, in
     // correction equation(s) at the solver precision, reusing the cached inverses; with
     // adaptive tolerances the correction is truncated at eta_r / 10 (its right-hand side is
     // itself truncated at eta_r) and the update at omega res_i
-    const double inner_thr = c.opt.adaptive ? c.opt.eta_r / 10.0 : 0.0;
-    const double eta_i = c.opt.adaptive ? std::max(eta_s, c.opt.omega * res) : eta_s;
+    const double inner_thr = inexact ? c.opt.eta_r / 10.0 : 0.0;
+    const double eta_i = inexact ? std::max(eta_s, c.opt.omega * res) : eta_s;
     t0 = clk::now();
     int cd = 0;
     std::vector<double> dd;
@@ -1185,7 +1189,12 @@ int Solver::solve(hipStream_t s, char* ws, size_t ws_bytes, unsigned long ws_epo
       if (code == LYAP_OK) {
         auto t0 = clk::now();
         LYAP_TRY(inner_solve(c, c.L, c.ldl, m, 0, c.svec, c.psd, cols, d));
-        c.zc_orth = cols > 0 && c.orth >= cols && c.u == Prec::F64;
+        // the factor counts as orthonormal for the FP64 steps only when the truncation that
+        // made it rotated in FP64: binary32 rotations (fp16 / bf16 solvers) leave it
+        // orthonormal to about 1e-6, and the residual factorisation's QR would then assume
+        // an orthonormal leading block that is not one
+        const bool f64_rotations = !(c.us == Prec::F16 || c.us == Prec::BF16);
+        c.zc_orth = cols > 0 && c.orth >= cols && c.u == Prec::F64 && f64_rotations;
         LYAP_TRY(copy_block(s, n, cols, c.Zs, cap, c.Zc, cap));
         LYAP_TRY(round_block(s, store_of(c.u), n, cols, c.Zc, cap));
         for (double& x : d) x = round_host(x, c.u);

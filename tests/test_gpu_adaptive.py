@@ -52,3 +52,25 @@ def test_adaptive_matches_oracle(lyap, us):
     else:
         assert info["refinements"] <= io.refinements
     assert info["rank"] <= 1.05 * fixed["rank"] + 2
+
+
+@pytest.mark.parametrize("k", [5, 14, 24])
+@pytest.mark.parametrize("opts", [{}, {"adaptive": 1}])
+def test_fp16_solves_of_batch_instances_report_their_true_residual(lyap, k, opts):
+    # Regression: the factor of an fp16 solve was marked orthonormal after a truncation with
+    # binary32 rotations (orthonormal to ~1e-6 only); the residual factorisation then took it
+    # as an exact orthonormal block and over-reported res (7e-13 against a true 1e-15), so
+    # refinement stagnated.  The library's res must match the host's recomputation.
+    A, L = lyapgen.batch_family()[k]
+    print(f"batch instance {k} n={A.shape[0]} m={L.shape[1]} fp16 {opts}", flush=True)
+    Z, D, info = lyap.solve(_cuda(A), _cuda(L), None, precisions=("fp16", "fp64", "fp64", "fp64"),
+                            **opts)
+    Z, D = Z.cpu().numpy(), D.cpu().numpy()
+    host = R.relres(A, L, None, Z, D)
+    print(f"  {info['status']} res lib={info['res']:.2e} host={host:.2e} "
+          f"hist={[f'{r:.1e}' for r in info['res_hist']]}", flush=True)
+    assert info["status"] == "OK" and host <= 1e-13
+    assert info["res"] == pytest.approx(host, rel=0.05, abs=2e-16)
+    # the returned factor of an FP64-updated solve is orthonormal to working precision
+    if info["refinements"] > 0:
+        assert np.abs(Z.T @ Z - np.eye(Z.shape[1])).max() <= 1e-12

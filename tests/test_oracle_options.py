@@ -188,3 +188,18 @@ def test_adaptive_tolerances_keep_the_accuracy_and_not_the_rank(us):
                                omega=1e-1)
     assert loose.status == "OK" and loose.rank < fixed.rank
     assert R.relres(A, L, None, Zb, db) <= 1e-13
+
+
+
+def test_adaptive_thresholds_fall_back_when_a_step_does_not_contract():
+    # an update threshold far too loose (omega = 1e4 drops nearly everything) makes a step fail
+    # to halve the residual; the inexact thresholds are then switched off and the refinement
+    # still reaches tau_I (without the fallback it stagnates: eq 4.2)
+    A, L, Q, T = lyapgen.schur_family(3, 120, 3, lo=-2.0, upper_std_scale=0.003)
+    X = E.schur_solve(Q, T, L @ L.T)
+    Z, d, info = IR.ir_ldlt(A, L, None, prec=("fp32", "fp64", "fp64", "fp64"), adaptive=True,
+                            omega=1e4)
+    h = info.res_hist
+    assert any(h[i] > 0.5 * h[i - 1] for i in range(1, len(h)))
+    assert info.status == "OK" and info.res_hist[-1] <= 1e-13
+    assert _rel((Z * d) @ Z.T, X) <= 1e-10
