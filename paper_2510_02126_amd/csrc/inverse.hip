@@ -322,60 +322,71 @@ __global__ __launch_bounds__(LEAF_THREADS) void gj_leaf(int n, T* __restrict__ W
 // -------------------------------------------------------------- non-pivoted leaf kernels
 // Invert the w x w diagonal block D = W[c0.., c0..] (w <= WN) by Gauss-Jordan without
 // pivoting; Dinv (w x w, row-major) to global; the pivots are the diagonal rows.  Thread t
-// holds row i = t % 64 of D at columns g + 4q (g = t / 64, q < 16) in registers, so the loads
-// from WT are coalesced; step k publishes the pivot row and the multiplier column in LDS
-// (double-buffered, one barrier per step).
+// holds row i = t % 64 of D at the ND contiguous columns ND g + q (g = t / 64, q < ND) in
+// registers, so the loads from WT are coalesced and the pivot row comes back from LDS as
+// contiguous vectors; two waves per SIMD let one wave's barrier and LDS latency overlap the
+// other's arithmetic, and the step loop is fully unrolled so that every register index is a
+// constant.  Step k publishes the pivot row and the multiplier column in LDS
+// (double-buffered, one barrier per step); a non-pivot row takes one FMA per entry,
+// d <- d - (f / p) r.
+constexpr int ND_THREADS = 512;
 template <class T>
-__global__ __launch_bounds__(256) void nop_diag(int n, const T* __restrict__ WT, int c0, int w,
-                                                T* __restrict__ Dinv, int* __restrict__ used,
-                                                int* __restrict__ piv, int* __restrict__ sing,
-                                                T* __restrict__ pv) {
-  __shared__ T rowk[2][WN];
+__global__ __launch_bounds__(ND_THREADS) void nop_diag(int n, const T* __restrict__ WT, int c0,
+                                                       int w, T* __restrict__ Dinv,
+                                                       int* __restrict__ used,
+                                                       int* __restrict__ piv,
+                                                       int* __restrict__ sing,
+                                                       T* __restrict__ pv) {
+  constexpr int NG = ND_THREADS / 64, ND = WN / NG;
+  static_assert(WN == 64 && ND * NG == WN, "groups of ND columns");
+  __shared__ __align__(16) T rowk[2][WN];
   __shared__ T colk[2][WN];
   const int t = threadIdx.x, i = t & 63, g = t >> 6;
-  T d[WN / 4];
+  T d[ND];
 #pragma unroll
-  for (int q = 0; q < WN / 4; ++q) {
-    const int j = g + 4 * q;
+  for (int q = 0; q < ND; ++q) {
+    const int j = ND * g + q;
     d[q] = (i < w && j < w) ? WT[(long)(c0 + j) * n + c0 + i] : (T)(i == j ? 1 : 0);
   }
   if (t < w) {
     used[c0 + t] = 1;
     piv[c0 + t] = c0 + t;
   }
-  for (int k = 0; k < w; ++k) {
+  // all WN steps run: past w the block is padded with the identity (block diagonal), whose
+  // steps change nothing in the leading w x w block
+#pragma unroll
+  for (int k = 0; k < WN; ++k) {
     const int buf = k & 1;
     if (i == k) {
 #pragma unroll
-      for (int q = 0; q < WN / 4; ++q) rowk[buf][g + 4 * q] = d[q];
+      for (int q = 0; q < ND; ++q) rowk[buf][ND * g + q] = d[q];
     }
-    if (g == (k & 3)) {
-      T x = (T)0;
-#pragma unroll
-      for (int q = 0; q < WN / 4; ++q)
-        if (q == (k >> 2)) x = d[q];
-      colk[buf][i] = x;
-    }
+    if (g == k / ND) colk[buf][i] = d[k % ND];
     __syncthreads();
+    T r[ND];
+#pragma unroll
+    for (int q = 0; q < ND; ++q) r[q] = rowk[buf][ND * g + q];
     T p = rowk[buf][k];
-    if (t == 0) pv[c0 + k] = p;
+    const T f = colk[buf][i];
+    if (t == 0 && k < w) pv[c0 + k] = p;
     if (!(fabs(p) > (T)0)) {
       if (t == 0) *sing = 1;
       p = (T)1;
     }
     const T inv = (T)1 / p;
-    const T f = colk[buf][i];
+    const T fi = f * inv;
+    if (i == k) {
 #pragma unroll
-    for (int q = 0; q < WN / 4; ++q) {
-      const int j = g + 4 * q;
-      const T pr = rowk[buf][j] * inv;
-      if (i == k) d[q] = (j == k) ? inv : pr;
-      else d[q] = (j == k) ? -f * inv : d[q] - f * pr;
+      for (int q = 0; q < ND; ++q) d[q] = r[q] * inv;
+    } else {
+#pragma unroll
+      for (int q = 0; q < ND; ++q) d[q] = fma(-fi, r[q], d[q]);
     }
+    if (g == k / ND) d[k % ND] = (i == k) ? inv : -fi;
   }
 #pragma unroll
-  for (int q = 0; q < WN / 4; ++q) {
-    const int j = g + 4 * q;
+  for (int q = 0; q < ND; ++q) {
+    const int j = ND * g + q;
     if (i < w && j < w) Dinv[i * w + j] = d[q];
   }
 }
@@ -503,7 +514,7 @@ template <class T> struct Inv {
   // gc / gv: columns of the update that follows, whose gather the pivoted leaf does itself
   int leaf(int c0, int wc, int gc = 0, int gv = 0) {
     if (!pivot) {
-      hipLaunchKernelGGL((nop_diag<T>), dim3(1), dim3(256), 0, s, n, WT, c0, wc, Dinv, used, piv,
+      hipLaunchKernelGGL((nop_diag<T>), dim3(1), dim3(ND_THREADS), 0, s, n, WT, c0, wc, Dinv, used, piv,
                          sing, pv);
       hipLaunchKernelGGL((nop_apply<T>), dim3((unsigned)ceil_div(n, AR)), dim3(256), 0, s, n, WT,
                          c0, wc, Dinv);

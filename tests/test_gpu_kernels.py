@@ -74,7 +74,12 @@ def test_gemm_split_fp16(lyap, M, N, K, ta, tb):
 
 @pytest.mark.parametrize("dtype", ["fp32", "fp16", "bf16"])
 @pytest.mark.parametrize("M,N,K,ta,tb", [(67, 45, 33, False, False), (128, 96, 160, True, False),
-                                         (50, 130, 70, False, True)])
+                                         (50, 130, 70, False, True),
+                                         # 128 x 128 tiles (>= 48 of them), ragged M, N, K
+                                         (1000, 900, 200, False, False),
+                                         (1000, 900, 200, True, False),
+                                         (1000, 900, 200, False, True),
+                                         (1000, 900, 200, True, True)])
 def test_gemm_reduced(lyap, dtype, M, N, K, ta, tb):
     print(f"gemm_{dtype} M={M} N={N} K={K} ta={ta} tb={tb}", flush=True)
     rng = np.random.default_rng(K)
