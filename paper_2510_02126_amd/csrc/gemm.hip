@@ -82,10 +82,13 @@ __global__ __launch_bounds__(NT) void gemm_k4(int M, int N, int K, int kchunk, d
                                               const int* __restrict__ aexp,
                                               const int* __restrict__ bexp) {
   constexpr int BK = 16;
+  constexpr int PA = (BM * BK) / NT, PB = (BN * BK) / NT;
   typedef typename Acc<MF>::V AV;
   typedef typename Acc<MF>::S AS;
-  __shared__ MF As[BK][BM + 1];
-  __shared__ MF Bs[BK][BN + 1];
+  // double-buffered k-tiles; the next tile is loaded into registers while the current one
+  // feeds the matrix cores, so each k-step waits for the global loads at most once
+  __shared__ MF As[2][BK][BM + 1];
+  __shared__ MF Bs[2][BK][BN + 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
@@ -97,42 +100,68 @@ __global__ __launch_bounds__(NT) void gemm_k4(int M, int N, int K, int kchunk, d
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = AV{0, 0, 0, 0};
 
-  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+  MF ra[PA], rb[PB];
+  auto load = [&](int k0) {
 #pragma unroll
-    for (int r = 0; r < (BM * BK) / NT; ++r) {
+    for (int r = 0; r < PA; ++r) {
       int e = tid + NT * r;
       int kk, mm;
       if (AK) { kk = e % BK; mm = e / BK; } else { mm = e % BM; kk = e / BM; }
       int gm = m0 + mm, gk = k0 + kk;
-      MF v = (MF)0;
-      if (gm < M && gk < kend) v = Cvt<MF>::f(A[(long)gm * sar + (long)gk * sac]);
-      As[kk][mm] = v;
+      ra[r] = (gm < M && gk < kend) ? Cvt<MF>::f(A[(long)gm * sar + (long)gk * sac]) : (MF)0;
     }
 #pragma unroll
-    for (int r = 0; r < (BN * BK) / NT; ++r) {
+    for (int r = 0; r < PB; ++r) {
       int e = tid + NT * r;
       int kk, nn;
       if (BN_) { nn = e % BN; kk = e / BN; } else { kk = e % BK; nn = e / BK; }
       int gn = n0 + nn, gk = k0 + kk;
-      MF v = (MF)0;
-      if (gn < N && gk < kend)
-        v = cvt_scaled<MF>(B[(long)gk * sbr + (long)gn * sbc], bexp ? bexp[gn] : 0);
-      Bs[kk][nn] = v;
+      rb[r] = (gn < N && gk < kend)
+                  ? cvt_scaled<MF>(B[(long)gk * sbr + (long)gn * sbc], bexp ? bexp[gn] : 0)
+                  : (MF)0;
     }
-    __syncthreads();
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int r = 0; r < PA; ++r) {
+      int e = tid + NT * r;
+      int kk, mm;
+      if (AK) { kk = e % BK; mm = e / BK; } else { mm = e % BM; kk = e / BM; }
+      As[buf][kk][mm] = ra[r];
+    }
+#pragma unroll
+    for (int r = 0; r < PB; ++r) {
+      int e = tid + NT * r;
+      int kk, nn;
+      if (BN_) { nn = e % BN; kk = e / BN; } else { kk = e % BK; nn = e / BK; }
+      Bs[buf][kk][nn] = rb[r];
+    }
+  };
+
+  if (kbeg < kend) {
+    load(kbeg);
+    store(0);
+  }
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+    const bool more = k0 + BK < kend;
+    if (more) load(k0 + BK);
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 4) {
       const int kq = ks + (lane >> 4);
-      MF a0 = As[kq][wm + (lane & 15)];
-      MF a1 = As[kq][wm + 16 + (lane & 15)];
-      MF b0 = Bs[kq][wn + (lane & 15)];
-      MF b1 = Bs[kq][wn + 16 + (lane & 15)];
+      MF a0 = As[buf][kq][wm + (lane & 15)];
+      MF a1 = As[buf][kq][wm + 16 + (lane & 15)];
+      MF b0 = Bs[buf][kq][wn + (lane & 15)];
+      MF b1 = Bs[buf][kq][wn + 16 + (lane & 15)];
       acc[0][0] = mfma4(a0, b0, acc[0][0]);
       acc[0][1] = mfma4(a0, b1, acc[0][1]);
       acc[1][0] = mfma4(a1, b0, acc[1][0]);
       acc[1][1] = mfma4(a1, b1, acc[1][1]);
     }
+    if (more) store(buf ^ 1);
     __syncthreads();
+    buf ^= 1;
   }
   // D layout of the 16x16 tile, lane l, register i: column l % 16; row 4*i + l/16 for the
   // FP64 instruction and 4*(l/16) + i for the binary32 one.
