@@ -113,13 +113,51 @@ def _traffic_run(lyap, torch, A, L, S, us):
 
 def _inverse_run(lyap, torch, A, spec):
     """Untimed: three inversions of the n = 4096 matrix at ``dtype[:pivot]`` (pivot "partial",
-    "none" or "rbt"), for per-kernel profiles of the inversion alone."""
+    "none" or "rbt"), for per-kernel profiles of the inversion alone; then the calibration
+    steps of the counter runs: one FP64, one FP32 and one FP16 library product of 4096^3
+    (137.4 GFLOP each, the MFMA op counters' unit) and a plain copy of 256 MiB evicted from
+    the MALL first (the HBM counters' scale)."""
     dt, _, pv = spec.partition(":")
     pivot = {"": True, "partial": True, "none": False, "rbt": "rbt"}[pv]
     for _ in range(3):
         lyap.inverse(A, dt, pivot=pivot)
     torch.cuda.synchronize()
     print("inversions done", dt, pv or "partial", flush=True)
+    for t in (torch.float64, torch.float32, torch.float16):
+        a = torch.ones((4096, 4096), dtype=t, device="cuda")
+        c = torch.matmul(a, a)
+        torch.cuda.synchronize()
+        print("calibration matmul", t, "flops", 2 * 4096 ** 3, float(c[0, 0]), flush=True)
+    x = torch.empty(32 * 1024 * 1024, dtype=torch.float64, device="cuda").fill_(1.0)
+    torch.cuda.synchronize()
+    big = torch.empty(96 * 1024 * 1024, dtype=torch.float64, device="cuda").fill_(2.0)
+    torch.cuda.synchronize()
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    del big
+    print("calibration copy bytes", x.numel() * 8, flush=True)
+
+
+def _profile_value(name, key, hash_key, sources):
+    """``key`` from the machine-readable tail of profiles/``name``, or None: the counters
+    describe the code they were taken on, so the value is used only while the listed kernel
+    sources (paper_2510_02126_amd/csrc) still have the recorded combined sha256."""
+    import hashlib
+    import re
+
+    try:
+        with open(os.path.join(ROOT, "profiles", name)) as f:
+            vals = dict(re.findall(r"^(\w+): (\S+)$", f.read(), re.M))
+    except OSError:
+        return None
+    h = hashlib.sha256()
+    for src in sources:
+        with open(os.path.join(ROOT, "paper_2510_02126_amd", "csrc", src), "rb") as f:
+            h.update(f.read())
+    if vals.get(hash_key) != h.hexdigest() or key not in vals:
+        return None
+    return float(vals[key])
 
 
 def _mfma_run(lyap, torch, A, L, S, us):
@@ -311,7 +349,11 @@ def main():
     roof = {"bound": "mfma", "kernel": "inversion (Gauss-Jordan: pivoted leaves + MFMA block "
             f"updates), {head['us']} operands, 2 n^3 flops per inversion",
             "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-            "frac": round(achieved / peak, 5), "traffic": None,
+            "frac": round(achieved / peak, 5),
+            "traffic": (_profile_value("inversion_fp16_n4096_hbm_traffic.md",
+                                       "traffic_bytes_per_inversion", "sources_sha256",
+                                       ["inverse.hip", "gemm.hip"])
+                        if head["us"] == "fp16" else None),
             "launches": inv_calls, "avg_launch_us": round(1e3 * inv_ms / max(1, inv_calls), 1)}
     total_ms = 1e3 * head["dt"]
     shares = {
@@ -322,7 +364,10 @@ def main():
     shares["rest (products, norms, copies, host)"] = round(1.0 - sum(shares.values()), 4)
     jac = {"achieved_GBs": round(head["fam_work"][1] / (head["fam_ms"][1] * 1e-3) / 1e9, 1)
            if head["fam_ms"][1] > 0 else None, "peak_GBs": PEAK_HBM_GBS,
-           "launches": head["fam_calls"][1]}
+           "launches": head["fam_calls"][1],
+           "traffic_bytes_per_launch_fp32_ir": _profile_value(
+               "jac_round_n4096_ir_fp32_hbm_traffic.md", "traffic_bytes_per_launch",
+               "eig_hip_sha256", ["eig.hip"])}
     t_inv = _time_inverse(lyap, torch, A, "fp64")
     inv64 = 2.0 * n ** 3 / t_inv / 1e12
     t_inv_rbt = _time_inverse(lyap, torch, A, "fp64", pivot="rbt")
