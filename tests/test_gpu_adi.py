@@ -150,3 +150,58 @@ def test_adi_metric_workload_n1024(lyap):
           f"J={len(info['mus'])} inv={info['inversions']}", flush=True)
     assert info["status"] == "OK" and info["res"] <= 1e-13
     assert R.relres(A, L, None, Z, D) <= 1e-13
+
+
+def test_adi_cholesky_form(lyap):
+    # Alg 2.1 with the ADI solver: the two correction equations (L+ and L-) each run ADI
+    A, L = CASES["shift64"]()
+    X = E.kron_solve(A, L @ L.T)
+    print("ADI Cholesky form n=64 fp32", flush=True)
+    Z, D, info = lyap.solve(_cuda(A), _cuda(L), None, precisions=("fp32", "fp64", "fp64", "fp64"),
+                            solver=1, form=1)
+    Z = Z.cpu().numpy()
+    assert info["status"] == "OK" and info["res"] <= 1e-13
+    assert _rel(Z @ Z.T, X) <= 1e-11
+
+
+def test_adi_shift_count_override_and_step_cap(lyap):
+    A, L = CASES["schur300"]()
+    prec = ("fp32", "fp64", "fp64", "fp64")
+    print("ADI J=4 and adi_max=3 n=300 fp32", flush=True)
+    _, _, base = lyap.solve(_cuda(A), _cuda(L), None, precisions=prec, solver=1)
+    # four shifts (oracle shifts for J = 4 on the same interval; binary32 interval inverse)
+    seq = AD.adi_sequence(A, "fp32", shifts=4)
+    Z, D, i4 = lyap.solve(_cuda(A), _cuda(L), None, precisions=prec, solver=1, adi_shifts=4)
+    assert len(i4["mus"]) == 4 and i4["inversions"] == 5
+    np.testing.assert_allclose(i4["mus"], seq.shifts, rtol=2e-2)
+    assert i4["status"] == "OK" and i4["res"] <= 1e-13
+    # three ADI steps per solve use only the three largest of the 13 shifts, so the
+    # corrections barely touch the small eigenvalues' components: the refinement stops by
+    # eq (4.2) with a valid factor
+    Z, D, i3 = lyap.solve(_cuda(A), _cuda(L), None, precisions=prec, solver=1, adi_max=3,
+                          raise_on_error=False)
+    print(f"  base ref={base['refinements']} J=4 ref={i4['refinements']} "
+          f"adi_max=3 {i3['status']} ref={i3['refinements']} hist={i3['res_hist']}", flush=True)
+    assert i3["newton_max"] <= 3
+    assert i3["status"] in ("STAGNATED", "NOT_CONVERGED") and i3["res"] > 1e-13
+    assert torch.isfinite(Z).all() and torch.isfinite(D).all()
+    # one cycle of shifts and two more steps per solve: inexact corrections that still
+    # contract, so the refinement converges (with more steps than the full inner solve)
+    J = len(base["mus"])
+    _, _, ic = lyap.solve(_cuda(A), _cuda(L), None, precisions=prec, solver=1, adi_max=J + 2)
+    print(f"  adi_max={J + 2}: {ic['status']} ref={ic['refinements']} res={ic['res']:.1e}",
+          flush=True)
+    assert ic["status"] == "OK" and ic["res"] <= 1e-13
+    assert ic["newton_max"] <= J + 2 and ic["refinements"] >= base["refinements"]
+
+
+def test_adi_escalation_rescues_bf16(lyap):
+    A, L = lyapgen.paper_family(60, 6.0, seed=3)
+    print("ADI escalate bf16 paper family n=60 q=6", flush=True)
+    Z, D, info = lyap.solve(_cuda(A), _cuda(L), None, precisions=("bf16", "fp64", "fp64", "fp64"),
+                            solver=1, escalate=1)
+    Z, D = Z.cpu().numpy(), D.cpu().numpy()
+    print(f"  {info['status']} u_s_final={info['u_s_final']} escalations={info['escalations']} "
+          f"res={info['res']:.1e}", flush=True)
+    assert info["status"] == "OK" and info["res"] <= 1e-13
+    assert R.relres(A, L, None, Z, D) <= 1e-13
