@@ -560,11 +560,13 @@ int launch_big(hipStream_t s, const GemmDesc& d) {
   return LYAP_OK;
 }
 
-// The 128 x 128 kernel pays off once the grid has a few waves of workgroups and the k-loop a
-// few slices; smaller products keep the 64 x 64 kernel.
+// The 128 x 128 kernel (one workgroup per CU) pays off once its grid covers every CU and the
+// k-loop has a few slices; below that the 64 x 64 kernel's four times as many workgroups keep
+// more of the GPU busy (measured on the inversion's updates at n = 4096: a threshold of 256
+// tiles instead of 48 made the FP64 butterfly inversion 10.5 -> 9.7 ms).
 inline bool use_big(const GemmDesc& d) {
   const long tiles = (long)ceil_div(d.M, GBM) * ceil_div(d.N, GBN);
-  return d.M >= 96 && d.N >= 96 && d.K >= 32 && tiles >= 48;
+  return d.M >= 96 && d.N >= 96 && d.K >= 32 && tiles >= 256;
 }
 
 template <class TA, class TB, class MF, class TC>
