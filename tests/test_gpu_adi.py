@@ -205,3 +205,36 @@ def test_adi_escalation_rescues_bf16(lyap):
           f"res={info['res']:.1e}", flush=True)
     assert info["status"] == "OK" and info["res"] <= 1e-13
     assert R.relres(A, L, None, Z, D) <= 1e-13
+
+
+def test_adi_through_the_other_entry_points(lyap):
+    # batched, allocation-free, warm-started refinement and a fresh adjoint solve, each with
+    # the ADI inner solver, against exact solutions
+    prec = ("fp32", "fp64", "fp64", "fp64")
+    batch = lyapgen.batch_family(count=6, seed=77)
+    print("ADI batched 6 instances", flush=True)
+    out = lyap.solve_batched([_cuda(a) for a, _ in batch], [_cuda(l) for _, l in batch], None,
+                             precisions=prec, solver=1)
+    for (a, l), (Z, D, info) in zip(batch, out):
+        assert info["status"] == "OK" and info["res"] <= 1e-13
+        assert R.relres(a, l, None, Z.cpu().numpy(), D.cpu().numpy()) <= 1e-13
+    A, L = CASES["shift64"]()
+    X = E.kron_solve(A, L @ L.T)
+    print("ADI static n=64", flush=True)
+    Z, D, info = lyap.solve_static(_cuda(A), _cuda(L), None, precisions=prec, solver=1)
+    Zs, Ds = Z.cpu().numpy(), D.cpu().numpy()
+    assert info["status"] == "OK" and _rel((Zs * Ds) @ Zs.T, X) <= 1e-11
+    print("ADI refine from a perturbed factor n=64", flush=True)
+    Zp = Zs + 1e-6 * np.random.default_rng(3).standard_normal(Zs.shape)
+    Z, D, info = lyap.refine(_cuda(A), _cuda(L), None, _cuda(Zp), _cuda(Ds), precisions=prec,
+                             solver=1)
+    Z, D = Z.cpu().numpy(), D.cpu().numpy()
+    assert info["status"] == "OK" and info["refinements"] >= 1
+    assert _rel((Z * D) @ Z.T, X) <= 1e-11
+    print("ADI fresh adjoint n=64", flush=True)
+    C = np.random.default_rng(9).standard_normal((2, 64))
+    Y, DY, info = lyap.solve_adjoint(_cuda(A), _cuda(C.T), None, precisions=prec, solver=1,
+                                     reuse=0)
+    Y, DY = Y.cpu().numpy(), DY.cpu().numpy()
+    assert info["status"] == "OK" and not info["cache_reused"] and info["inversions"] > 0
+    assert _rel((Y * DY) @ Y.T, E.kron_solve(A.T, C.T @ C)) <= 1e-11
