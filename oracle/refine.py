@@ -260,7 +260,9 @@ def ir_ldlt(A, L, S=None, prec=("fp32", "fp64", "fp64", "fp64"), tol: float = 1e
             inexact = adaptive
             for i in range(1, budget + 1):
                 Ld, sd, normR = res_fac_ldlt(A, L, Sm, Z, Y, eta_r, ur)
-                res = normR / (normW + 2.0 * _norm_ldlt(Z, Y) * normA)
+                den = normW + 2.0 * _norm_ldlt(Z, Y) * normA
+                # W = 0 and X = 0: the exact solution, R = 0 (eq 4.1 read as 0, not 0/0)
+                res = normR / den if den > 0.0 else (0.0 if normR == 0.0 else math.inf)
                 info.res_hist.append(res)
                 hist.append(res)
                 if inexact and len(hist) >= 2 and hist[-1] > 0.5 * hist[-2]:
@@ -338,7 +340,8 @@ def ir_chol(A, L, prec=("fp32", "fp64", "fp64", "fp64"), tol: float = 1e-13,
     for i in range(1, i_max + 1):
         Lp, Lm, normR = res_fac_chol(A, L, Z, eta_r, ur)
         Gz = Z.T @ Z
-        res = normR / (normW + 2.0 * math.sqrt(float(np.trace(Gz @ Gz))) * normA)
+        den = normW + 2.0 * math.sqrt(float(np.trace(Gz @ Gz))) * normA
+        res = normR / den if den > 0.0 else (0.0 if normR == 0.0 else math.inf)
         info.res_hist.append(res)
         if res <= tol:
             break

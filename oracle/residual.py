@@ -3,7 +3,9 @@
 R(Z)   = A Z Z^T + Z Z^T A^T + L L^T            (eq 2.2)
 R(Z,Y) = A Z Y Z^T + Z Y Z^T A^T + L S L^T      (eq 2.17)
 res    = ||R||_F / (||W||_F + 2 ||X_hat||_F ||A||_F)   (eq 4.1), all in float64, formed
-densely.  Y (or D) may be a matrix or the diagonal as a 1-D array.
+densely.  Y (or D) may be a matrix or the diagonal as a 1-D array.  With W = 0 and X_hat = 0
+the denominator vanishes together with R; that exact solution (X = 0 solves the equation with
+W = 0) is given res = 0.
 """
 from __future__ import annotations
 
@@ -31,6 +33,12 @@ def residual_matrix(A, L, S, Z, Y=None) -> np.ndarray:
     return AX + AX.T + form_w(L, S)
 
 
+def _ratio(num: float, den: float) -> float:
+    if den == 0.0:
+        return 0.0 if num == 0.0 else float("inf")
+    return num / den
+
+
 def relres(A, L, S, Z, Y=None) -> float:
     """Normwise relative residual of eq (4.1)."""
     A = np.asarray(A, np.float64)
@@ -39,7 +47,7 @@ def relres(A, L, S, Z, Y=None) -> float:
     W = form_w(L, S)
     R = AX + AX.T + W
     den = np.linalg.norm(W, "fro") + 2.0 * np.linalg.norm(X, "fro") * np.linalg.norm(A, "fro")
-    return float(np.linalg.norm(R, "fro") / den)
+    return _ratio(float(np.linalg.norm(R, "fro")), float(den))
 
 
 def relres_dense(A, W, X) -> float:
@@ -50,4 +58,4 @@ def relres_dense(A, W, X) -> float:
     AX = A @ X
     R = AX + AX.T + W
     den = np.linalg.norm(W, "fro") + 2.0 * np.linalg.norm(X, "fro") * np.linalg.norm(A, "fro")
-    return float(np.linalg.norm(R, "fro") / den)
+    return _ratio(float(np.linalg.norm(R, "fro")), float(den))

@@ -936,7 +936,9 @@ int Solver::refine_loop(Ctx& c, int& cols, std::vector<double>& d, int steps, in
     std::vector<double> sd;
     LYAP_TRY(res_fac(c, c.Zc, cap, cols, d, false, normR, rd, sd));
     LYAP_TRY(xnorm(c, c.Zc, cap, cols, d, nx));
-    const double res = normR / (c.normW + 2.0 * nx * c.normA);
+    // eq (4.1); W = 0 with X = 0 is the exact solution (R = 0): res 0, not 0 / 0
+    const double den = c.normW + 2.0 * nx * c.normA;
+    const double res = den > 0.0 ? normR / den : (normR == 0.0 ? 0.0 : INFINITY);
     if (info->n_res < 64) info->res_hist[info->n_res++] = res;
     info->res = res;
     hist.push_back(res);

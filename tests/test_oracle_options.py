@@ -203,3 +203,21 @@ def test_adaptive_thresholds_fall_back_when_a_step_does_not_contract():
     assert any(h[i] > 0.5 * h[i - 1] for i in range(1, len(h)))
     assert info.status == "OK" and info.res_hist[-1] <= 1e-13
     assert _rel((Z * d) @ Z.T, X) <= 1e-10
+
+
+@pytest.mark.parametrize("us", ["fp64", "fp16"])
+def test_zero_right_hand_side_gives_the_zero_solution(us):
+    # W = 0: X = 0 solves the equation exactly; eq (4.1) is 0/0 there and is read as 0
+    A, _ = lyapgen.random_shift(1, 32, 2)
+    Z, d, info = IR.ir_ldlt(A, np.zeros((32, 2)), None, prec=(us, "fp64", "fp64", "fp64"))
+    assert info.status == "OK" and info.rank == 0 and info.res_hist == [0.0]
+    assert R.relres(A, np.zeros((32, 2)), None, Z, d) == 0.0
+
+
+@pytest.mark.parametrize("us", ["fp64", "fp32", "fp16", "bf16"])
+def test_order_one_equation(us):
+    # n = 1: a x + x a + l^2 s = 0, x = -l^2 s / (2 a)
+    Z, d, info = IR.ir_ldlt(np.array([[-3.0]]), np.array([[2.0, 1.0]]), np.array([1.0, -2.0]),
+                            prec=(us, "fp64", "fp64", "fp64"))
+    assert info.status == "OK"
+    assert float(((Z * d) @ Z.T)[0, 0]) == pytest.approx((4.0 - 2.0) / 6.0, rel=1e-13)
