@@ -381,7 +381,11 @@ int lyap_inverse(lyap_handle h, void* stream, int dtype, int pivot, int n, const
  * lyap_gemm -- C = alpha * op(A) * op(B) + beta * C in FP64 on the FP64 matrix cores, or
  * with operands rounded to ``dtype`` (F32/F16/BF16) and binary32 accumulation.  op(X) is
  * X or X^T (transa/transb = 0/1).  All matrices FP64 row-major.  op(A) is M x K, op(B) is
- * K x N, C is M x N.
+ * K x N, C is M x N.  A product with few 64 x 64 output tiles (fewer than 256) and K >= 512
+ * splits K over several workgroups (as the solver's tall-skinny products do): the partial
+ * products are summed in FP64 in a fixed order, so for reduced-precision operands the
+ * accumulation is binary32 within each k-chunk (at least 256 long) and FP64 across chunks.
+ * The handle keeps a workspace for the partial products.
  */
 int lyap_gemm(lyap_handle h, void* stream, int dtype, int transa, int transb, int M, int N,
               int K, double alpha, const double* A, int lda, const double* B, int ldb,

@@ -386,16 +386,14 @@ int lyap_gemm(lyap_handle h, void* stream, int dtype, int transa, int transb, in
   g.B = B;
   if (!transb) { g.sbr = ldb; g.sbc = 1; } else { g.sbr = 1; g.sbc = ldb; }
   g.C = C; g.ldc = ldc;
-  if (dtype == LYAP_F64) {
-    size_t ws_elems = (size_t)64 * M * N;
-    ws_elems = std::min(ws_elems, (size_t)1 << 26);
-    LYAP_TRY(h->ws.reserve(ws_elems * sizeof(double) + (1 << 20)));
-    h->ws.reset();
-    double* part = h->ws.take<double>(ws_elems);
-    LYAP_TRY(gemm_f64(s, g, part, ws_elems));
-  } else {
-    LYAP_TRY(gemm_lp(s, (Prec)dtype, Store::F64, Store::F64, Store::F64, g));
-  }
+  // split-K partial products (used for products with few output tiles and a long k-loop)
+  size_t ws_elems = (size_t)64 * M * N;
+  ws_elems = std::min(ws_elems, (size_t)1 << 26);
+  LYAP_TRY(h->ws.reserve(ws_elems * sizeof(double) + (1 << 20)));
+  h->ws.reset();
+  double* part = h->ws.take<double>(ws_elems);
+  if (dtype == LYAP_F64) LYAP_TRY(gemm_f64(s, g, part, ws_elems));
+  else LYAP_TRY(gemm_lp(s, (Prec)dtype, Store::F64, Store::F64, Store::F64, g, part, ws_elems));
   LYAP_HIP(hipStreamSynchronize(s));
   return LYAP_OK;
 }

@@ -146,10 +146,13 @@ struct GemmDesc {
 // Storage type codes for operands/results.
 enum class Store : int { F64 = 0, F32 = 1, F16 = 2, BF16 = 3 };
 
-// Product with FP64 matrix cores (all storage F64).
+// Product with FP64 matrix cores (all storage F64).  With a workspace (splitk_ws, ws_elems
+// doubles) a product with few output tiles and a long k-loop splits K across workgroups.
 int gemm_f64(hipStream_t s, const GemmDesc& d, double* splitk_ws = nullptr, size_t ws_elems = 0);
 // Product with operands rounded to ``op`` (F32/F16/BF16), binary32 accumulation.  A and B
-// stored as ``sa``/``sb``, C stored as ``sc`` (F32 or F64).
-int gemm_lp(hipStream_t s, Prec op, Store sa, Store sb, Store sc, const GemmDesc& d);
+// stored as ``sa``/``sb``, C stored as ``sc`` (F32 or F64).  For an F64 C a workspace allows
+// the same split of K (binary32 accumulation within each k-chunk, FP64 across chunks).
+int gemm_lp(hipStream_t s, Prec op, Store sa, Store sb, Store sc, const GemmDesc& d,
+            double* splitk_ws = nullptr, size_t ws_elems = 0);
 
 }  // namespace lyap

@@ -13,8 +13,11 @@
 //                 (hi*hi and the two cross terms) in binary32 accumulation.
 // Operands are read through generic strides so that transposed views need no copies; the
 // loader picks a coalesced thread mapping from whichever stride is unit.  Ragged M, N, K are
-// zero-padded in LDS.  FP64 products can split K across blocks, with a deterministic
-// second pass that sums the partial products in a fixed order.
+// zero-padded in LDS.  Products with few output tiles and a long k-loop (the tall-skinny
+// products of the factor iterations and the Gram matrices) split K across blocks when the
+// caller gives a workspace: each block writes its scaled partial product in FP64 and a
+// deterministic second pass sums them in a fixed order (for reduced-precision operands the
+// accumulation is binary32 within a k-chunk and FP64 across chunks).
 #include <algorithm>
 #include <type_traits>
 
@@ -205,10 +208,11 @@ __device__ inline f32x4 mfma32(bf16x8 a, bf16x8 b, f32x4 c) {
 }
 
 template <class TA, class TB, class MF, class TC, bool AK, bool BN_>
-__global__ __launch_bounds__(NT) void gemm_k32(int M, int N, int K, double alpha, double beta,
-                                               const TA* __restrict__ A, long sar, long sac,
-                                               const TB* __restrict__ B, long sbr, long sbc,
-                                               TC* __restrict__ C, long ldc,
+__global__ __launch_bounds__(NT) void gemm_k32(int M, int N, int K, int kchunk, double alpha,
+                                               double beta, const TA* __restrict__ A, long sar,
+                                               long sac, const TB* __restrict__ B, long sbr,
+                                               long sbc, TC* __restrict__ C, long ldc,
+                                               TC* __restrict__ part,
                                                const int* __restrict__ aexp,
                                                const int* __restrict__ bexp) {
   constexpr int BK = 32, PK = BK + 8;
@@ -218,13 +222,15 @@ __global__ __launch_bounds__(NT) void gemm_k32(int M, int N, int K, double alpha
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int kbeg = blockIdx.z * kchunk;
+  const int kend = min(K, kbeg + kchunk);
   f32x4 acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
 
-  for (int k0 = 0; k0 < K; k0 += BK) {
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
 #pragma unroll
     for (int r = 0; r < (BM * BK) / NT; ++r) {
       int e = tid + NT * r;
@@ -232,7 +238,7 @@ __global__ __launch_bounds__(NT) void gemm_k32(int M, int N, int K, double alpha
       if (AK) { kk = e % BK; mm = e / BK; } else { mm = e % BM; kk = e / BM; }
       int gm = m0 + mm, gk = k0 + kk;
       MF v = Cvt<MF>::f(0.0f);
-      if (gm < M && gk < K) v = Cvt<MF>::f(A[(long)gm * sar + (long)gk * sac]);
+      if (gm < M && gk < kend) v = Cvt<MF>::f(A[(long)gm * sar + (long)gk * sac]);
       As[mm][kk] = v;
     }
 #pragma unroll
@@ -242,7 +248,7 @@ __global__ __launch_bounds__(NT) void gemm_k32(int M, int N, int K, double alpha
       if (BN_) { nn = e % BN; kk = e / BN; } else { kk = e % BK; nn = e / BK; }
       int gn = n0 + nn, gk = k0 + kk;
       MF v = Cvt<MF>::f(0.0f);
-      if (gn < N && gk < K)
+      if (gn < N && gk < kend)
         v = cvt_scaled<MF>(B[(long)gk * sbr + (long)gn * sbc], bexp ? bexp[gn] : 0);
       Bs[nn][kk] = v;
     }
@@ -269,11 +275,15 @@ __global__ __launch_bounds__(NT) void gemm_k32(int M, int N, int K, double alpha
         int gm = m0 + wm + ti * 16 + 4 * (lane >> 4) + i;
         int gn = n0 + wn + tj * 16 + (lane & 15);
         if (gm < M && gn < N) {
-          TC* cp = C + (long)gm * ldc + gn;
           const int es = ea + (bexp ? bexp[gn] : 0);
           double out = (es == 0 ? alpha : ldexp(alpha, es)) * (double)acc[ti][tj][i];
-          if (beta != 0.0) out += beta * (double)(*cp);
-          *cp = (TC)out;
+          if (part) {
+            part[((long)blockIdx.z * M + gm) * N + gn] = (TC)out;
+          } else {
+            TC* cp = C + (long)gm * ldc + gn;
+            if (beta != 0.0) out += beta * (double)(*cp);
+            *cp = (TC)out;
+          }
         }
       }
 }
@@ -435,10 +445,11 @@ template <> __device__ inline void split16<float>(float x, _Float16& hi, _Float1
 }
 
 template <class TA, class TB, class TC, bool AK, bool BN_>
-__global__ __launch_bounds__(NT) void gemm_k32s(int M, int N, int K, double alpha, double beta,
-                                                const TA* __restrict__ A, long sar, long sac,
-                                                const TB* __restrict__ B, long sbr, long sbc,
-                                                TC* __restrict__ C, long ldc,
+__global__ __launch_bounds__(NT) void gemm_k32s(int M, int N, int K, int kchunk, double alpha,
+                                                double beta, const TA* __restrict__ A, long sar,
+                                                long sac, const TB* __restrict__ B, long sbr,
+                                                long sbc, TC* __restrict__ C, long ldc,
+                                                TC* __restrict__ part,
                                                 const int* __restrict__ aexp,
                                                 const int* __restrict__ bexp) {
   constexpr int BK = 32, PK = BK + 8;
@@ -459,7 +470,9 @@ __global__ __launch_bounds__(NT) void gemm_k32s(int M, int N, int K, double alph
       hh[i][j] = f32x4{0, 0, 0, 0};
       xx[i][j] = f32x4{0, 0, 0, 0};
     }
-  for (int k0 = 0; k0 < K; k0 += BK) {
+  const int kbeg = blockIdx.z * kchunk;
+  const int kend = min(K, kbeg + kchunk);
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
 #pragma unroll
     for (int r = 0; r < (BM * BK) / NT; ++r) {
       int e = tid + NT * r;
@@ -467,7 +480,7 @@ __global__ __launch_bounds__(NT) void gemm_k32s(int M, int N, int K, double alph
       if (AK) { kk = e % BK; mm = e / BK; } else { mm = e % BM; kk = e / BM; }
       int gm = m0 + mm, gk = k0 + kk;
       MF h = (MF)0.0f, l = (MF)0.0f;
-      if (gm < M && gk < K) split16<TA>(A[(long)gm * sar + (long)gk * sac], h, l);
+      if (gm < M && gk < kend) split16<TA>(A[(long)gm * sar + (long)gk * sac], h, l);
       AsH[mm][kk] = h;
       AsL[mm][kk] = l;
     }
@@ -478,7 +491,7 @@ __global__ __launch_bounds__(NT) void gemm_k32s(int M, int N, int K, double alph
       if (BN_) { nn = e % BN; kk = e / BN; } else { kk = e % BK; nn = e / BK; }
       int gn = n0 + nn, gk = k0 + kk;
       MF h = (MF)0.0f, l = (MF)0.0f;
-      if (gn < N && gk < K) {
+      if (gn < N && gk < kend) {
         TB v = B[(long)gk * sbr + (long)gn * sbc];
         if (bexp && bexp[gn] != 0) v = (TB)ldexp((double)v, -bexp[gn]);
         split16<TB>(v, h, l);
@@ -516,12 +529,16 @@ __global__ __launch_bounds__(NT) void gemm_k32s(int M, int N, int K, double alph
         int gm = m0 + wm + ti * 16 + 4 * (lane >> 4) + i;
         int gn = n0 + wn + tj * 16 + (lane & 15);
         if (gm < M && gn < N) {
-          TC* cp = C + (long)gm * ldc + gn;
           const int es = ea + (bexp ? bexp[gn] : 0);
           const double v = (double)hh[ti][tj][i] + (double)xx[ti][tj][i] * (1.0 / 2048.0);
           double out = (es == 0 ? alpha : ldexp(alpha, es)) * v;
-          if (beta != 0.0) out += beta * (double)(*cp);
-          *cp = (TC)out;
+          if (part) {
+            part[((long)blockIdx.z * M + gm) * N + gn] = (TC)out;
+          } else {
+            TC* cp = C + (long)gm * ldc + gn;
+            if (beta != 0.0) out += beta * (double)(*cp);
+            *cp = (TC)out;
+          }
         }
       }
 }
@@ -538,6 +555,12 @@ __global__ void splitk_reduce(int M, int N, int splits, const double* __restrict
   double* cp = C + (long)gm * ldc + gn;
   if (beta != 0.0) s += beta * (*cp);
   *cp = s;
+}
+
+// k-chunk of a split product: a multiple of the kernel's k-tile (a chunk past K is empty and
+// contributes a zero partial product)
+inline int chunk_of(int K, int splits, int bk) {
+  return splits > 1 ? ceil_div(ceil_div(K, splits), bk) * bk : K;
 }
 
 template <class TA, class TB, class MF, class TC>
@@ -572,7 +595,7 @@ inline bool use_big(const GemmDesc& d) {
 template <class TA, class TB, class MF, class TC>
 int launch_k4(hipStream_t s, const GemmDesc& d, int splits, TC* part) {
   dim3 grid(ceil_div(d.N, BN), ceil_div(d.M, BM), splits);
-  int kchunk = splits > 1 ? ceil_div(ceil_div(d.K, splits), 16) * 16 : d.K;
+  const int kchunk = chunk_of(d.K, splits, 16);
   bool ak = (d.sac == 1), bn = (d.sbc == 1);
   auto A = static_cast<const TA*>(d.A);
   auto B = static_cast<const TB*>(d.B);
@@ -591,16 +614,17 @@ int launch_k4(hipStream_t s, const GemmDesc& d, int splits, TC* part) {
 }
 
 template <class TA, class TB, class MF, class TC>
-int launch_k32(hipStream_t s, const GemmDesc& d) {
-  dim3 grid(ceil_div(d.N, BN), ceil_div(d.M, BM), 1);
+int launch_k32(hipStream_t s, const GemmDesc& d, int splits, TC* part) {
+  dim3 grid(ceil_div(d.N, BN), ceil_div(d.M, BM), splits);
+  const int kchunk = chunk_of(d.K, splits, 32);
   bool ak = (d.sac == 1), bn = (d.sbc == 1);
   auto A = static_cast<const TA*>(d.A);
   auto B = static_cast<const TB*>(d.B);
   auto C = static_cast<TC*>(d.C);
 #define K32(a, b)                                                                             \
   hipLaunchKernelGGL((gemm_k32<TA, TB, MF, TC, a, b>), grid, dim3(NT), 0, s, d.M, d.N, d.K,  \
-                     d.alpha, d.beta, A, d.sar, d.sac, B, d.sbr, d.sbc, C, d.ldc, d.a_exp,     \
-                     d.b_colexp)
+                     kchunk, d.alpha, d.beta, A, d.sar, d.sac, B, d.sbr, d.sbc, C, d.ldc,   \
+                     part, d.a_exp, d.b_colexp)
   if (ak && bn) K32(true, true);
   else if (ak) K32(true, false);
   else if (bn) K32(false, true);
@@ -611,16 +635,17 @@ int launch_k32(hipStream_t s, const GemmDesc& d) {
 }
 
 template <class TA, class TB, class TC>
-int launch_k32s(hipStream_t s, const GemmDesc& d) {
-  dim3 grid(ceil_div(d.N, BN), ceil_div(d.M, BM), 1);
+int launch_k32s(hipStream_t s, const GemmDesc& d, int splits, TC* part) {
+  dim3 grid(ceil_div(d.N, BN), ceil_div(d.M, BM), splits);
+  const int kchunk = chunk_of(d.K, splits, 32);
   bool ak = (d.sac == 1), bn = (d.sbc == 1);
   auto A = static_cast<const TA*>(d.A);
   auto B = static_cast<const TB*>(d.B);
   auto C = static_cast<TC*>(d.C);
 #define KS(a, b)                                                                              \
   hipLaunchKernelGGL((gemm_k32s<TA, TB, TC, a, b>), grid, dim3(NT), 0, s, d.M, d.N, d.K,      \
-                     d.alpha, d.beta, A, d.sar, d.sac, B, d.sbr, d.sbc, C, d.ldc, d.a_exp,    \
-                     d.b_colexp)
+                     kchunk, d.alpha, d.beta, A, d.sar, d.sac, B, d.sbr, d.sbc, C, d.ldc,    \
+                     part, d.a_exp, d.b_colexp)
   if (ak && bn) KS(true, true);
   else if (ak) KS(true, false);
   else if (bn) KS(false, true);
@@ -630,37 +655,63 @@ int launch_k32s(hipStream_t s, const GemmDesc& d) {
   return LYAP_OK;
 }
 
+// Split-K for products with fewer output tiles than four workgroups per CU and a long
+// k-loop: about 1024 workgroups, at least 256 k per split, at most 64 splits, within the
+// workspace (splits x M x N FP64 partial products).  With the 64 x 64 tile at M = n = 4096,
+// N <= 320, K = n (the factor products of the solvers) one block per tile left the matrix
+// cores idle most of the time: about 500 us per product, regardless of N.
+int split_count(const GemmDesc& d, size_t ws_elems) {
+  const long tiles = (long)ceil_div(d.M, BM) * ceil_div(d.N, BN);
+  if (ws_elems == 0 || tiles >= 256 || d.K < 512) return 1;
+  int splits = (int)std::min<long>((1024 + tiles - 1) / tiles, d.K / 256);
+  splits = std::min(splits, 64);
+  while (splits > 1 && (size_t)splits * d.M * d.N > ws_elems) --splits;
+  return std::max(splits, 1);
+}
+
+int reduce_splits(hipStream_t s, const GemmDesc& d, int splits, const double* part) {
+  const long total = (long)d.M * d.N;
+  hipLaunchKernelGGL(splitk_reduce, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, d.M,
+                     d.N, splits, part, d.beta, static_cast<double*>(d.C), d.ldc);
+  LYAP_HIP(hipGetLastError());
+  return LYAP_OK;
+}
+
 template <class TA, class TB, class TC>
-int dispatch_lp_op(hipStream_t s, Prec op, const GemmDesc& d) {
+int dispatch_lp_op(hipStream_t s, Prec op, const GemmDesc& d, int splits, TC* part) {
   switch (op) {
     case Prec::F32:
-      if (use_big(d)) return launch_big<TA, TB, float, TC>(s, d);
-      return launch_k4<TA, TB, float, TC>(s, d, 1, nullptr);
-    case Prec::F16: return launch_k32<TA, TB, _Float16, TC>(s, d);
-    case Prec::BF16: return launch_k32<TA, TB, __bf16, TC>(s, d);
+      if (splits <= 1 && use_big(d)) return launch_big<TA, TB, float, TC>(s, d);
+      return launch_k4<TA, TB, float, TC>(s, d, splits, part);
+    case Prec::F16: return launch_k32<TA, TB, _Float16, TC>(s, d, splits, part);
+    case Prec::BF16: return launch_k32<TA, TB, __bf16, TC>(s, d, splits, part);
     case Prec::F16X2:
       if constexpr ((std::is_same<TA, double>::value || std::is_same<TA, float>::value) &&
                     (std::is_same<TB, double>::value || std::is_same<TB, float>::value))
-        return launch_k32s<TA, TB, TC>(s, d);
+        return launch_k32s<TA, TB, TC>(s, d, splits, part);
       return LYAP_BADARG;
     default: return LYAP_BADARG;
   }
 }
 
 template <class TA, class TB>
-int dispatch_lp_c(hipStream_t s, Prec op, Store sc, const GemmDesc& d) {
-  if (sc == Store::F32) return dispatch_lp_op<TA, TB, float>(s, op, d);
-  if (sc == Store::F64) return dispatch_lp_op<TA, TB, double>(s, op, d);
-  return LYAP_BADARG;
+int dispatch_lp_c(hipStream_t s, Prec op, Store sc, const GemmDesc& d, double* ws,
+                  size_t ws_elems) {
+  if (sc == Store::F32) return dispatch_lp_op<TA, TB, float>(s, op, d, 1, nullptr);
+  if (sc != Store::F64) return LYAP_BADARG;
+  const int splits = split_count(d, ws ? ws_elems : 0);
+  LYAP_TRY((dispatch_lp_op<TA, TB, double>(s, op, d, splits, splits > 1 ? ws : nullptr)));
+  return splits > 1 ? reduce_splits(s, d, splits, ws) : LYAP_OK;
 }
 
 template <class TA>
-int dispatch_lp_b(hipStream_t s, Prec op, Store sb, Store sc, const GemmDesc& d) {
+int dispatch_lp_b(hipStream_t s, Prec op, Store sb, Store sc, const GemmDesc& d, double* ws,
+                  size_t ws_elems) {
   switch (sb) {
-    case Store::F64: return dispatch_lp_c<TA, double>(s, op, sc, d);
-    case Store::F32: return dispatch_lp_c<TA, float>(s, op, sc, d);
-    case Store::F16: return dispatch_lp_c<TA, _Float16>(s, op, sc, d);
-    case Store::BF16: return dispatch_lp_c<TA, __bf16>(s, op, sc, d);
+    case Store::F64: return dispatch_lp_c<TA, double>(s, op, sc, d, ws, ws_elems);
+    case Store::F32: return dispatch_lp_c<TA, float>(s, op, sc, d, ws, ws_elems);
+    case Store::F16: return dispatch_lp_c<TA, _Float16>(s, op, sc, d, ws, ws_elems);
+    case Store::BF16: return dispatch_lp_c<TA, __bf16>(s, op, sc, d, ws, ws_elems);
   }
   return LYAP_BADARG;
 }
@@ -670,32 +721,23 @@ int dispatch_lp_b(hipStream_t s, Prec op, Store sb, Store sc, const GemmDesc& d)
 int gemm_f64(hipStream_t s, const GemmDesc& d, double* ws, size_t ws_elems) {
   if (d.M <= 0 || d.N <= 0) return LYAP_OK;
   // K == 0 is handled by the kernel itself: the k-loop is empty and C = beta * C.
-  int tiles = ceil_div(d.M, BM) * ceil_div(d.N, BN);
-  int splits = 1;
-  if (ws && tiles < 128 && d.K >= 1024) {
-    splits = std::min(64, std::max(1, 256 / tiles));
-    splits = std::min(splits, d.K / 256);
-    while (splits > 1 && (size_t)splits * d.M * d.N > ws_elems) --splits;
-  }
+  const int splits = split_count(d, ws ? ws_elems : 0);
   if (splits <= 1) {
     if (use_big(d)) return launch_big<double, double, double, double>(s, d);
     return launch_k4<double, double, double, double>(s, d, 1, nullptr);
   }
   LYAP_TRY((launch_k4<double, double, double, double>(s, d, splits, ws)));
-  long total = (long)d.M * d.N;
-  hipLaunchKernelGGL(splitk_reduce, dim3((unsigned)ceil_div((int)total, 256)), dim3(256), 0, s,
-                     d.M, d.N, splits, ws, d.beta, static_cast<double*>(d.C), d.ldc);
-  LYAP_HIP(hipGetLastError());
-  return LYAP_OK;
+  return reduce_splits(s, d, splits, ws);
 }
 
-int gemm_lp(hipStream_t s, Prec op, Store sa, Store sb, Store sc, const GemmDesc& d) {
+int gemm_lp(hipStream_t s, Prec op, Store sa, Store sb, Store sc, const GemmDesc& d, double* ws,
+            size_t ws_elems) {
   if (d.M <= 0 || d.N <= 0) return LYAP_OK;
   switch (sa) {
-    case Store::F64: return dispatch_lp_b<double>(s, op, sb, sc, d);
-    case Store::F32: return dispatch_lp_b<float>(s, op, sb, sc, d);
-    case Store::F16: return dispatch_lp_b<_Float16>(s, op, sb, sc, d);
-    case Store::BF16: return dispatch_lp_b<__bf16>(s, op, sb, sc, d);
+    case Store::F64: return dispatch_lp_b<double>(s, op, sb, sc, d, ws, ws_elems);
+    case Store::F32: return dispatch_lp_b<float>(s, op, sb, sc, d, ws, ws_elems);
+    case Store::F16: return dispatch_lp_b<_Float16>(s, op, sb, sc, d, ws, ws_elems);
+    case Store::BF16: return dispatch_lp_b<__bf16>(s, op, sb, sc, d, ws, ws_elems);
   }
   return LYAP_BADARG;
 }

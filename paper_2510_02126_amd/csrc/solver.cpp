@@ -589,6 +589,17 @@ int Solver::rank_trunc(Ctx& c, double* Zb, long ldb, int& cols, std::vector<doub
   return LYAP_OK;
 }
 
+// Split-K workspace for a tall-skinny product (n x n times n x c): the arena, which holds
+// nothing between the steps that use it (every user resets it first; one stream orders the
+// reuse).
+static double* splitk_part(Arena& a, size_t& elems) {
+  a.reset();
+  elems = a.cap > 4096 ? (a.cap - 4096) / sizeof(double) : 0;
+  double* p = elems ? a.take<double>(elems) : nullptr;
+  if (!p) elems = 0;
+  return p;
+}
+
 // ------------------------------------------------------------------ factor iteration
 // eq (3.3): Z_k = [Z_{k-1}, A_{k-1}^{-1} Z_{k-1}], D_k = (mu D, D / mu) / 2, truncating
 // whenever the column count exceeds floor(rho n) (threshold max(u_s, trunc_thr) relative);
@@ -618,13 +629,15 @@ int Solver::factor_iteration(Ctx& c, const double* L0, long ld0, int m0, int ort
       else { g.sar = n; g.sac = 1; }
       g.B = Zs; g.sbr = cap; g.sbc = 1;
       g.C = Zs + cols; g.ldc = cap;
+      size_t pe = 0;
+      double* part = splitk_part(c.arena, pe);
       if (c.us == Prec::F64) {
-        LYAP_TRY(gemm_f64(s, g));
+        LYAP_TRY(gemm_f64(s, g, part, pe));
       } else {
         LYAP_TRY(col_exponents(s, n, cols, Zs, cap, c.colexp, c.flags + 1, c.bits));
         g.a_exp = c.cexp + k;
         g.b_colexp = c.colexp;
-        LYAP_TRY(gemm_lp(s, c.us, c.cstore, Store::F64, Store::F64, g));
+        LYAP_TRY(gemm_lp(s, c.us, c.cstore, Store::F64, Store::F64, g, part, pe));
       }
     }
     const double mu = c.mus[k];
@@ -707,13 +720,15 @@ int Solver::adi_iteration(Ctx& c, const double* L0, long ld0, int m0,
     else { g.sar = n; g.sac = 1; }
     g.B = W; g.sbr = m0; g.sbc = 1;
     g.C = Zs + cols; g.ldc = cap;
+    size_t pe = 0;
+    double* part = splitk_part(c.arena, pe);
     if (c.us == Prec::F64) {
-      LYAP_TRY(gemm_f64(s, g));
+      LYAP_TRY(gemm_f64(s, g, part, pe));
     } else {
       LYAP_TRY(col_exponents(s, n, m0, W, m0, c.colexp, c.flags + 1, c.bits));
       g.a_exp = c.cexp + j;
       g.b_colexp = c.colexp;
-      LYAP_TRY(gemm_lp(s, c.us, c.cstore, Store::F64, Store::F64, g));
+      LYAP_TRY(gemm_lp(s, c.us, c.cstore, Store::F64, Store::F64, g, part, pe));
     }
     LYAP_TRY(add_block(s, n, m0, -2.0 * p, Zs + cols, cap, W, m0));
     for (int k = 0; k < m0; ++k) d.push_back(-2.0 * p * d0[k]);
@@ -784,8 +799,10 @@ int Solver::res_fac(Ctx& c, const double* Zb, long ldb, int cols, const std::vec
     else { g.sar = c.lda; g.sac = 1; }
     g.B = Zb; g.sbr = ldb; g.sbc = 1;
     g.C = c.F + cols; g.ldc = cap;
-    if (c.ur == Prec::F64) LYAP_TRY(gemm_f64(s, g));
-    else LYAP_TRY(gemm_lp(s, c.ur, Store::F64, Store::F64, Store::F64, g));
+    size_t pe = 0;
+    double* part = splitk_part(c.arena, pe);
+    if (c.ur == Prec::F64) LYAP_TRY(gemm_f64(s, g, part, pe));
+    else LYAP_TRY(gemm_lp(s, c.ur, Store::F64, Store::F64, Store::F64, g, part, pe));
   }
   LYAP_TRY(copy_block(s, n, m, c.L, c.ldl, c.F + 2 * cols, cap));
   c.arena.reset();

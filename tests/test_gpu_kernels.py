@@ -38,6 +38,9 @@ def _cuda(x):
     (16, 16, 4, False, False), (67, 45, 33, False, False), (130, 70, 129, True, False),
     (64, 200, 90, False, True), (33, 17, 65, True, True), (512, 384, 300, False, False),
     (64, 32, 4096, True, False),   # split-K path
+    # split-K on the tall-skinny shapes of the solvers' products; K = 4100 leaves the last
+    # k-chunk empty
+    (2000, 50, 3000, False, True), (300, 20, 4100, True, False), (4096, 130, 4096, False, False),
 ])
 def test_gemm_f64(lyap, M, N, K, ta, tb):
     print(f"gemm_f64 M={M} N={N} K={K} ta={ta} tb={tb}", flush=True)
@@ -54,7 +57,9 @@ def test_gemm_f64(lyap, M, N, K, ta, tb):
 
 
 @pytest.mark.parametrize("M,N,K,ta,tb", [(67, 45, 33, False, False), (128, 96, 160, True, False),
-                                         (50, 130, 70, False, True), (300, 260, 1000, False, False)])
+                                         (50, 130, 70, False, True), (300, 260, 1000, False, False),
+                                         (2000, 50, 3000, False, False),
+                                         (300, 20, 4100, True, True)])
 def test_gemm_split_fp16(lyap, M, N, K, ta, tb):
     # split binary16 operands (hi + 2^-11 lo): each operand is carried to 2^-22, the three
     # products are summed in binary32
@@ -79,7 +84,13 @@ def test_gemm_split_fp16(lyap, M, N, K, ta, tb):
                                          (1000, 900, 200, False, False),
                                          (1000, 900, 200, True, False),
                                          (1000, 900, 200, False, True),
-                                         (1000, 900, 200, True, True)])
+                                         (1000, 900, 200, True, True),
+                                         # few tiles and a long k-loop: K split over
+                                         # workgroups (K = 4100 leaves the last chunk empty)
+                                         (1000, 40, 3000, False, False),
+                                         (1000, 40, 3000, True, True),
+                                         (300, 20, 4100, False, False),
+                                         (4096, 130, 4096, False, False)])
 def test_gemm_reduced(lyap, dtype, M, N, K, ta, tb):
     print(f"gemm_{dtype} M={M} N={N} K={K} ta={ta} tb={tb}", flush=True)
     rng = np.random.default_rng(K)
