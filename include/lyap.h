@@ -132,7 +132,8 @@ typedef struct {
                         without pivoting on U^T A_k V, checked by a residual probe
                         ||A_k (A_k^-1 x) - x|| <= 8 sqrt(n) u_s ||A_k||_F ||A_k^-1||_F ||x||
                         and redone with partial pivoting when the probe fails (needs
-                        n % 4 == 0, otherwise partial pivoting)                            */
+                        n % 4 == 0, otherwise partial pivoting).  The ADI solver's shifted
+                        inverses and its spectral-interval inverse are treated alike.      */
   double omega;      /* the factor omega of the adaptive update threshold; default 0.1:
                         directions that small are the ones the next correction fixes
                         anyway (measured at n = 4096: fp16 inner, omega 1e-3 / 0.1 / 0.3:

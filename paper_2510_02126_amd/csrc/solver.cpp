@@ -403,28 +403,26 @@ int Solver::a_iteration(Ctx& c) {
 }
 
 // ------------------------------------------------------------------- ADI sequence
-// (A + p I)^{-1} at u_s into slot j (A^T's with the same shifts is its transpose).  With
-// opt.pivoting = 1 the butterfly inversion is tried first and checked by its probe, as in the
-// A-iteration.
-int Solver::shifted_inverse(Ctx& c, int j, double p) {
+// Inverse of the n x n FP64 matrix M at ``op`` into ``out`` (n x n): with opt.pivoting = 1
+// the butterfly inversion first, checked by its residual probe and redone with partial
+// pivoting when the probe fails (as in the A-iteration); otherwise partial pivoting.
+int Solver::checked_inverse(Ctx& c, Prec op, const double* M, long ld, double* out,
+                            unsigned long long seed) {
   const int n = c.n;
   hipStream_t s = c.s;
   double* scal = c.scal;
-  double* out = (c.us == Prec::F64) ? static_cast<double*>(c.slot(j)) : c.Ainv;
-  LYAP_TRY(copy_block(s, n, n, c.A, c.lda, c.Ak, n));
-  LYAP_TRY(add_diag(s, n, c.Ak, n, p));
   bool rbt = c.opt.pivoting == 1 && n % 4 == 0;
   int fl[2];
   for (;;) {
     LYAP_TRY(fill_int(s, c.flags, 2, 0));
     c.arena.reset();
     if (rbt) {
-      LYAP_TRY(rbt_invert(s, c.us, n, c.Ak, n, out, n, c.arena, c.flags, c.kt, nullptr,
-                          0x4144495348ull + (unsigned)j, scal + 13));
-      LYAP_TRY(sumsq(s, n, n, c.Ak, n, scal + 18, c.part));
+      LYAP_TRY(rbt_invert(s, op, n, M, ld, out, n, c.arena, c.flags, c.kt, nullptr, seed,
+                          scal + 13));
+      LYAP_TRY(sumsq(s, n, n, M, ld, scal + 18, c.part));
       LYAP_TRY(sumsq(s, n, n, out, n, scal + 19, c.part));
     } else {
-      LYAP_TRY(invert(s, c.us, n, c.Ak, n, out, n, c.arena, c.flags, true, c.kt, nullptr));
+      LYAP_TRY(invert(s, op, n, M, ld, out, n, c.arena, c.flags, true, c.kt, nullptr));
     }
     double h[7];
     LYAP_HIP(hipMemcpyAsync(h, scal + 13, sizeof(h), hipMemcpyDeviceToHost, s));
@@ -432,7 +430,7 @@ int Solver::shifted_inverse(Ctx& c, int j, double p) {
     LYAP_HIP(hipStreamSynchronize(s));
     c.info->inversions += 1;
     if (!rbt) break;
-    const double bound = 8.0 * std::sqrt((double)n) * unit_roundoff(c.us) * std::sqrt(h[5]) *
+    const double bound = 8.0 * std::sqrt((double)n) * unit_roundoff(op) * std::sqrt(h[5]) *
                          std::sqrt(h[6]);
     if (!fl[0] && !fl[1] && std::isfinite(h[0]) && h[0] <= bound) {
       c.info->rbt_steps += 1;
@@ -443,6 +441,17 @@ int Solver::shifted_inverse(Ctx& c, int j, double p) {
   }
   if (fl[0]) return LYAP_SINGULAR;
   if (fl[1]) return LYAP_NONFINITE;
+  return LYAP_OK;
+}
+
+// (A + p I)^{-1} at u_s into slot j (A^T's with the same shifts is its transpose).
+int Solver::shifted_inverse(Ctx& c, int j, double p) {
+  const int n = c.n;
+  hipStream_t s = c.s;
+  double* out = (c.us == Prec::F64) ? static_cast<double*>(c.slot(j)) : c.Ainv;
+  LYAP_TRY(copy_block(s, n, n, c.A, c.lda, c.Ak, n));
+  LYAP_TRY(add_diag(s, n, c.Ak, n, p));
+  LYAP_TRY(checked_inverse(c, c.us, c.Ak, n, out, 0x4144495348ull + (unsigned)j));
   if (c.us != Prec::F64) {
     LYAP_TRY(absmax_exp(s, n, n, out, n, c.cexp + j, c.flags + 1, c.part));
     LYAP_TRY(cast_scaled(s, c.cstore, n, n, out, n, c.slot(j), c.cexp + j));
@@ -453,8 +462,8 @@ int Solver::shifted_inverse(Ctx& c, int j, double p) {
 }
 
 // Spectral interval [a, b] of -A by power iteration (b = rho(A), a = 1 / rho(A^{-1}) with
-// A^{-1} at u_s, or binary32 for the half-precision solvers), the Wachspress shifts for it
-// and the cached shifted inverses.
+// A^{-1} at u_s, or binary32 for the half-precision solvers; inverted like the shifted
+// matrices), the Wachspress shifts for it and the cached shifted inverses.
 int Solver::adi_sequence(Ctx& c) {
   const int n = c.n;
   hipStream_t s = c.s;
@@ -463,20 +472,13 @@ int Solver::adi_sequence(Ctx& c) {
   c.K = 0;
   LYAP_TRY(specrad_est(s, n, c.A, c.lda, RHO_ITERS, scal + 15, c.vecs));
   const Prec iop = (c.us == Prec::F64) ? Prec::F64 : Prec::F32;
-  LYAP_TRY(fill_int(s, c.flags, 2, 0));
-  c.arena.reset();
-  LYAP_TRY(invert(s, iop, n, c.A, c.lda, c.Ainv, n, c.arena, c.flags, true, c.kt, nullptr));
-  c.info->inversions += 1;
+  LYAP_TRY(checked_inverse(c, iop, c.A, c.lda, c.Ainv, 0x494e54ull));
   LYAP_TRY(specrad_est(s, n, c.Ainv, n, RHO_ITERS, scal + 16, c.vecs));
   double h[2];
-  int fl[2];
   LYAP_HIP(hipMemcpyAsync(h, scal + 15, sizeof(h), hipMemcpyDeviceToHost, s));
-  LYAP_HIP(hipMemcpyAsync(fl, c.flags, sizeof(fl), hipMemcpyDeviceToHost, s));
   LYAP_HIP(hipStreamSynchronize(s));
-  if (fl[0]) return LYAP_SINGULAR;
   const double b = h[0], a = 1.0 / h[1];
-  if (fl[1] || !std::isfinite(a) || !std::isfinite(b) || !(a > 0.0) || !(b > 0.0))
-    return LYAP_NONFINITE;
+  if (!std::isfinite(a) || !std::isfinite(b) || !(a > 0.0) || !(b > 0.0)) return LYAP_NONFINITE;
   std::vector<double> p = adi_shifts(std::min(a, b), b, c.opt.adi_shifts,
                                      std::sqrt(unit_roundoff(c.us)));
   if ((int)p.size() > c.lay.slots) p = adi_shifts(std::min(a, b), b, c.lay.slots, 0.0);

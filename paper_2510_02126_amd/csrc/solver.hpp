@@ -55,6 +55,8 @@ class Solver {
   int a_iteration(Ctx& c);
   int adi_sequence(Ctx& c);
   int shifted_inverse(Ctx& c, int j, double p);
+  int checked_inverse(Ctx& c, Prec op, const double* M, long ld, double* out,
+                      unsigned long long seed);
   int ensure_sequence(Ctx& c);
   int refine_loop(Ctx& c, int& cols, std::vector<double>& d, int steps, int& status);
   int factor_iteration(Ctx& c, const double* L0, long ld0, int m0, int orth0,

@@ -119,7 +119,8 @@ def test_adi_with_butterfly_inversions(lyap):
     print(f"  {info['status']} res={info['res']:.2e} rbt={info['rbt_steps']} "
           f"fallbacks={info['rbt_fallbacks']} J={len(info['mus'])}", flush=True)
     assert info["status"] == "OK" and info["res"] <= 1e-13
-    assert info["rbt_steps"] == len(info["mus"]) and info["rbt_fallbacks"] == 0
+    # the J shifted inverses and the spectral-interval inverse
+    assert info["rbt_steps"] == len(info["mus"]) + 1 and info["rbt_fallbacks"] == 0
     assert _rel((Z * D) @ Z.T, X) <= 1e-9
 
 
