@@ -115,6 +115,17 @@ def test_gemm_reduced(lyap, dtype, M, N, K, ta, tb):
     assert np.all(err <= (2.01 * u_op + 4 * K * u32) * absprod + 1e-300)
 
 
+@pytest.mark.parametrize("dtype", ["fp64", "fp32", "fp16", "bf16", "fp16x2"])
+def test_split_k_products_are_deterministic(lyap, dtype):
+    # the split-K partial products are summed in a fixed order: repeated calls agree bit for bit
+    print(f"gemm split-K determinism {dtype} 2000 x 50 x 3000", flush=True)
+    rng = np.random.default_rng(11)
+    A, B = _cuda(rng.standard_normal((2000, 3000))), _cuda(rng.standard_normal((3000, 50)))
+    first = lyap.gemm(A, B, dtype=dtype).cpu().numpy()
+    for _ in range(2):
+        assert np.array_equal(lyap.gemm(A, B, dtype=dtype).cpu().numpy(), first)
+
+
 @pytest.mark.parametrize("n", [1, 7, 37, 200, 1000])
 @pytest.mark.parametrize("dtype", ["fp64", "fp32", "fp16", "bf16", "fp16x2"])
 def test_inverse_accuracy(lyap, n, dtype):
