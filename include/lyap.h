@@ -393,13 +393,17 @@ int lyap_gemm(lyap_handle h, void* stream, int dtype, int transa, int transb, in
               double beta, double* C, int ldc);
 
 /*
- * lyap_qr_lead -- the same thin QR F = U T (n >= p) when the first c columns Z of F are
- * orthonormal to working precision, as the truncated and updated factors of the solver are
- * (RankTruncLdlt in Alg 3.2, Fragments 2.3 / 2.4): C = Z^T Y and Y <- Y - Z C twice (block
- * Gram-Schmidt with reorthogonalisation), then the Householder QR of lyap_qr of the projected
- * Y = Q2 R2, so U = [Z, Q2] and T = [[I, C], [0, R2]].  Same layouts and errors as lyap_qr;
- * 0 <= c <= p (c = 0 or c < 32 gives lyap_qr's factorisation).  F is not modified.  If Z is
- * not orthonormal the result is not a QR factorisation of F.
+ * lyap_qr_lead -- the same thin QR F = U T when the first c columns Z of F are orthonormal
+ * to working precision, as the truncated and updated factors of the solver are
+ * (RankTruncLdlt in Alg 3.2, Fragments 2.3 / 2.4).  For p <= n: C = Z^T Y and Y <- Y - Z C
+ * twice (block Gram-Schmidt with reorthogonalisation), then the Householder QR of lyap_qr of
+ * the projected Y = Q2 R2, so U = [Z, Q2] and T = [[I, C], [0, R2]].  For p > n the columns
+ * span the whole space: U = [Z, Q2] (n x n) with Q2 an orthonormal completion of Z (from a
+ * seeded random block projected off range(Z) and factored twice) and T = U^T F (n x p,
+ * [[I, Z^T Y], [0, Q2^T Y]], not triangular).  Same layouts and errors as lyap_qr (U is
+ * n x min(n, p), ldu >= min(n, p)); 0 <= c <= min(n, p) (c < 32 gives lyap_qr's
+ * factorisation).  F is not modified.  If Z is not orthonormal the result is not a
+ * factorisation of F.
  */
 int lyap_qr_lead(lyap_handle h, void* stream, int n, int p, int c, const double* F, int ldf,
                  double* U, int ldu, double* T, int ldt);

@@ -415,14 +415,15 @@ int lyap_qr(lyap_handle h, void* stream, int n, int p, const double* F, int ldf,
 
 int lyap_qr_lead(lyap_handle h, void* stream, int n, int p, int c, const double* F, int ldf,
                  double* U, int ldu, double* T, int ldt) {
-  if (!h || n < 0 || p < 0 || n > 4096 || p > n || c < 0 || c > p ||
-      (p > 0 && (!F || !U || !T || ldf < p || ldu < p || ldt < p)))
+  const int k = std::min(n, p);
+  if (!h || n < 0 || p < 0 || n > 4096 || c < 0 || c > p || c > n ||
+      (p > 0 && (!F || !U || !T || ldf < p || ldu < k || ldt < p)))
     return LYAP_BADARG;
   if (p == 0) return LYAP_OK;
   hipStream_t s = (hipStream_t)stream;
   const size_t q = (size_t)(p - c);
   LYAP_TRY(h->ws.reserve(qr_workspace_bytes(n, p) + (size_t)n * p * 8 + (size_t)c * q * 8 +
-                         ((size_t)4 << 23) + (2 << 20)));
+                         (size_t)2 * n * n * 8 + ((size_t)4 << 23) + (2 << 20)));
   h->ws.reset();
   double* W = h->ws.take<double>((size_t)n * p);
   if (!W) return LYAP_NO_MEMORY;

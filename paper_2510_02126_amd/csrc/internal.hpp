@@ -106,10 +106,12 @@ size_t qr_workspace_bytes(int n, int p);
 int qr(hipStream_t s, int n, int p, const double* F, long ldf, double* U, long ldu, double* T,
        long ldt, Arena& ws, KernTimer* kt = nullptr);
 // The same factorisation when the first c columns of F are orthonormal (block Gram-Schmidt
-// against them, Householder QR of the rest); overwrites columns c.. of F.  Falls back to
-// ``qr`` when c < 32, c >= p or p > n.
+// against them, Householder QR of the rest); overwrites columns c.. of F.  With p > n and
+// ``complete`` (32 <= c <= n, scratch permitting) U = [Z, Q2] is an orthonormal completion of
+// Z and T = U^T F (n x p, not triangular).  Falls back to ``qr`` otherwise when c < 32,
+// c >= p or p > n.
 int qr_lead(hipStream_t s, int n, int p, int c, double* F, long ldf, double* U, long ldu,
-            double* T, long ldt, Arena& ws, KernTimer* kt = nullptr);
+            double* T, long ldt, Arena& ws, KernTimer* kt = nullptr, bool complete = true);
 
 // ---- eig.hip
 size_t syev_workspace_bytes(int p);

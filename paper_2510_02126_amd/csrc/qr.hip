@@ -438,6 +438,20 @@ __global__ void add_block(int rows, int cols, const double* __restrict__ src, lo
 
 inline unsigned nb256(long total) { return (unsigned)((total + 255) / 256); }
 
+// X (rows x cols, leading dimension ldx) <- uniform values in [-1, 1) from a counter-based
+// generator (the SplitMix64 finaliser of seed + linear index), the same on every run.
+__global__ void fill_uniform(int rows, int cols, double* __restrict__ X, long ldx,
+                             unsigned long long seed) {
+  long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)rows * cols) return;
+  unsigned long long x = seed + (unsigned long long)idx + 0x9e3779b97f4a7c15ull;
+  x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ull;
+  x = (x ^ (x >> 27)) * 0x94d049bb133111ebull;
+  x ^= x >> 31;
+  const int i = (int)(idx / cols), j = (int)(idx % cols);
+  X[(long)i * ldx + j] = (double)(x >> 11) * 0x1.0p-52 - 1.0;
+}
+
 }  // namespace
 
 size_t qr_workspace_bytes(int n, int p) {
@@ -516,13 +530,93 @@ int qr(hipStream_t s, int n, int p, const double* F, long ldf, double* U, long l
   return LYAP_OK;
 }
 
+namespace {
+
+// G <- G - Z (Z^T G) for the n x c orthonormal Z and the n x g block G (leading dimension g),
+// with the c x g coefficients in CG (split-K partial products in part).
+int project_off(hipStream_t s, int n, int c, int g, const double* Z, long ldz, double* G,
+                double* CG, double* part, size_t kws) {
+  GemmDesc a;  // CG = Z^T G
+  a.M = c; a.N = g; a.K = n;
+  a.A = Z; a.sar = 1; a.sac = ldz;
+  a.B = G; a.sbr = g; a.sbc = 1;
+  a.C = CG; a.ldc = g;
+  GemmDesc b;  // G -= Z CG
+  b.M = n; b.N = g; b.K = c;
+  b.alpha = -1.0; b.beta = 1.0;
+  b.A = Z; b.sar = ldz; b.sac = 1;
+  b.B = CG; b.sbr = g; b.sbc = 1;
+  b.C = G; b.ldc = g;
+  LYAP_TRY(gemm_f64(s, a, part, kws));
+  return gemm_f64(s, b);
+}
+
+// F = [Z, Y] with more columns than rows (p > n) whose first c columns Z are orthonormal:
+// the columns span the whole space, so any orthonormal basis U of it gives F = U T with
+// T = U^T F.  U = [Z, Q2] completes Z with Q2, the orthonormal factor of a seeded random
+// n x (n - c) block projected off range(Z) (two Gram-Schmidt passes, a Householder QR, then
+// one more projection and QR so that Q2 is orthogonal to Z to working precision whatever the
+// conditioning of the random block), and T = [[I, Z^T Y], [0, Q2^T Y]].  Keeping Z as the
+// leading block keeps T's leading block the identity (the Jacobi iterations that follow start
+// from a nearly diagonal leading block), and the Householder work is that of n - c columns
+// instead of an n x p QR.  T is n x p (not triangular; the callers only form products with
+// it).
+int qr_complete(hipStream_t s, int n, int p, int c, const double* F, long ldf, double* U,
+                long ldu, double* T, long ldt, Arena& ws, KernTimer* kt) {
+  const int g = n - c, q = p - c;
+  if (g > 0) {
+    double* G = ws.take<double>((size_t)n * g);
+    double* CG = ws.take<double>((size_t)c * g);
+    const size_t kws = std::min((size_t)8 * c * g, (size_t)4 << 20);
+    double* part = ws.take<double>(kws);
+    if (!G || !CG || !part) return LYAP_NO_MEMORY;
+    // the R factors of the two QRs go to T's columns c .. c + g - 1 (g < q), which the last
+    // product overwrites; the second QR reuses the first one's scratch
+    double* Rg = T + c;
+    hipLaunchKernelGGL(fill_uniform, dim3(nb256((long)n * g)), dim3(256), 0, s, n, g, G,
+                       (long)g, 0x51a3c0d2e4f6b789ull + (unsigned long long)n);
+    LYAP_HIP(hipGetLastError());
+    LYAP_TRY(project_off(s, n, c, g, F, ldf, G, CG, part, kws));
+    LYAP_TRY(project_off(s, n, c, g, F, ldf, G, CG, part, kws));
+    const size_t mark = ws.top;
+    LYAP_TRY(qr(s, n, g, G, g, U + c, ldu, Rg, ldt, ws, kt));
+    ws.top = mark;
+    hipLaunchKernelGGL(copy_rows, dim3(nb256((long)n * g)), dim3(256), 0, s, n, g, U + c, ldu,
+                       G, (long)g);
+    LYAP_HIP(hipGetLastError());
+    LYAP_TRY(project_off(s, n, c, g, F, ldf, G, CG, part, kws));
+    LYAP_TRY(qr(s, n, g, G, g, U + c, ldu, Rg, ldt, ws, kt));
+  }
+  LYAP_TRY(copy_block(s, n, c, F, ldf, U, ldu));
+  GemmDesc t;  // T[:, c:p] = U^T Y
+  t.M = n; t.N = q; t.K = n;
+  t.A = U; t.sar = 1; t.sac = ldu;
+  t.B = F + c; t.sbr = ldf; t.sbc = 1;
+  t.C = T + c; t.ldc = ldt;
+  LYAP_TRY(gemm_f64(s, t));
+  hipLaunchKernelGGL(eye_block, dim3(nb256((long)n * c)), dim3(256), 0, s, n, c, T, ldt);
+  LYAP_HIP(hipGetLastError());
+  return LYAP_OK;
+}
+
+// Scratch qr_complete takes from the arena.
+size_t complete_bytes(int n, int c) {
+  const size_t g = (size_t)(n - c);
+  return (n * g + c * g + std::min((size_t)8 * c * g, (size_t)4 << 20)) * 8 + 3 * 256 +
+         qr_workspace_bytes(n, (int)g);
+}
+
+}  // namespace
+
 // Thin QR of F = [Z, Y] whose first c columns Z are orthonormal: U = [Z, Q2] and
 // T = [[I, C], [0, R2]] with C = Z^T Y from two block Gram-Schmidt passes (the second removes
 // what rounding left of range(Z) in Y) and Q2 R2 the Householder QR above of Y - Z C.  The
 // same factorisation F = U T as ``qr`` (U orthonormal, T upper triangular) with half the
 // Householder work when c = p / 2.  Y (columns c.. of F) is overwritten.
 int qr_lead(hipStream_t s, int n, int p, int c, double* F, long ldf, double* U, long ldu,
-            double* T, long ldt, Arena& ws, KernTimer* kt) {
+            double* T, long ldt, Arena& ws, KernTimer* kt, bool complete) {
+  if (complete && p > n && c >= PB && c <= n && complete_bytes(n, c) + ws.top <= ws.cap)
+    return qr_complete(s, n, p, c, F, ldf, U, ldu, T, ldt, ws, kt);
   if (c < PB || c >= p || p > n) return qr(s, n, p, F, ldf, U, ldu, T, ldt, ws, kt);
   const int q = p - c;
   double* Y = F + c;

@@ -808,7 +808,10 @@ int Solver::res_fac(Ctx& c, const double* Zb, long ldb, int cols, const std::vec
   }
   LYAP_TRY(copy_block(s, n, m, c.L, c.ldl, c.F + 2 * cols, cap));
   c.arena.reset();
-  LYAP_TRY(qr_lead(s, n, p, c.zc_orth ? cols : 0, c.F, cap, c.Uq, cap, c.Tq, cap, c.arena, c.kt));
+  // the plain QR when p > n: the completed basis (T = U^T F by one long product) gave a
+  // residual a few units of u less accurate, which the residual factorisation cannot afford
+  LYAP_TRY(qr_lead(s, n, p, c.zc_orth ? cols : 0, c.F, cap, c.Uq, cap, c.Tq, cap, c.arena, c.kt,
+                   false));
   LYAP_TRY(round_block(s, rs, n, k, c.Uq, cap));
   LYAP_TRY(round_block(s, rs, k, p, c.Tq, cap));
   // TN = T N = [T2 D, T1 D, T3 S]

@@ -60,6 +60,27 @@ def test_qr_orthonormal_lead(lyap, n, c, q):
     assert np.linalg.norm(T.T @ T - T0.T @ T0) <= 100 * u * np.sqrt(n * p) * np.linalg.norm(G)
 
 
+@pytest.mark.parametrize("n,c,q", [(512, 300, 400), (1000, 968, 500), (256, 256, 100),
+                                   (300, 40, 400), (4096, 3900, 3900)])
+def test_qr_orthonormal_lead_wide(lyap, n, c, q):
+    # more columns than rows (c + q > n): U = [Z, Q2] is Z completed to an orthonormal basis
+    # of the whole space and T = U^T F, whose first c columns are [I; 0]; U T = F and
+    # U^T U = I to working precision
+    print(f"qr with orthonormal lead, wide: n={n} c={c} q={q}", flush=True)
+    rng = np.random.default_rng(n + 3 * c + q)
+    Z, _ = np.linalg.qr(rng.standard_normal((n, c)))
+    Y = rng.standard_normal((n, q)) * np.logspace(0, -8, q)[None, :]
+    F = np.hstack([Z, Y])
+    U, T = (x.cpu().numpy() for x in lyap.qr(_cuda(F), lead=c))
+    u = 2.0 ** -53
+    p = c + q
+    assert U.shape == (n, n) and T.shape == (n, p)
+    assert np.array_equal(U[:, :c], Z)
+    assert np.array_equal(T[:, :c], np.eye(n, c))
+    assert np.linalg.norm(U @ T - F) <= 50 * u * np.sqrt(n * p) * np.linalg.norm(F)
+    assert np.linalg.norm(U.T @ U - np.eye(n)) <= 50 * u * n
+
+
 def test_qr_rank_deficient(lyap):
     # F = [Z, A Z, L]-like: the middle block is (nearly) in the span of the others
     print("qr rank-deficient n=2048 p=136", flush=True)
