@@ -316,6 +316,10 @@ __device__ void solve_pair(SolveLds<T>& L, int pp, int np, const T* __restrict__
         T (&R1)[SB][LDS_PAD] = h1 == 0 ? RA : RB;
         const int yi = t / 8, yc = 2 * (t % 8);
         T y0 = T(0), y1 = T(0);
+        // partial unrolling: fully unrolled, these two loops held their LDS operands in
+        // registers and took the round kernel to 124 VGPRs (four waves per SIMD); at 8 it
+        // needs 64, which leaves room for seven binary32 round workgroups per CU
+#pragma unroll 8
         for (int k = 0; k < SB; ++k) {
           const T x = X[yi][k];
           y0 += x * R2[k][HB * H[h2] + yc];
@@ -328,6 +332,7 @@ __device__ void solve_pair(SolveLds<T>& L, int pp, int np, const T* __restrict__
         // S block = R_P[h1][:, half H[h1]]^T Y  (16 x 16): thread (i = t / 16, c = t % 16)
         const int si = t / HB, sc = t % HB;
         T sum = T(0);
+#pragma unroll 8
         for (int k = 0; k < SB; ++k) sum += R1[k][HB * H[h1] + si] * X[k][sc];
         L.S[0][HB * h1 + si][HB * h2 + sc] = sum;
       }
@@ -703,9 +708,11 @@ int syev_t(hipStream_t s, int p, const double* H, long ldh, double* w, double* V
   const double total = host[1];
   int cur = 0, rc = 0;  // A in Aw[cur], rotations of the next round in Rb[rc]
   bool solved = false;
-  // update workers: about as many as fit on the chip next to the solves (4 per CU)
+  // update workers: about as many as fit on the chip next to the solves (4 round workgroups
+  // per CU in FP64, bound by LDS; 7 in binary32, bound by registers)
   const int nitems = np * (np + 1) / 2 + np * (pp / SB);
-  const int nw = std::min(nitems, std::max(256, 4 * 256 - np));
+  const int per_cu = sizeof(T) == 4 ? 7 : 4;
+  const int nw = std::min(nitems, std::max(256, per_cu * 256 - np));
   while (sweep < max_sweeps && np > 0) {
     if (host[0] <= tol_rel * tol_rel * total) break;
     if (sweep > 0 && host[2] == 0.0) break;
