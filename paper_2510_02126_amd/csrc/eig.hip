@@ -150,7 +150,10 @@ __device__ inline long sidx(int r, int c, int pp) {
 template <class T>
 struct SolveLds {
   T S[2][SB][LDS_PAD];  // subproblem, double-buffered by step parity
-  T R[2][SB][LDS_PAD];  // accumulated rotation
+  // accumulated rotation, updated in place (a sweep step rotates its columns only, and each
+  // entry belongs to one thread); binary32 subproblem formation stages a rotation in R[1].
+  // Three FP64 buffers (25 KB) let six round workgroups share a CU.
+  T R[sizeof(T) == 8 ? 1 : 2][SB][LDS_PAD];
   int any;
 };
 
@@ -173,12 +176,12 @@ __device__ inline void step_pair(bool full, int k, int r, int& p, int& q) {
   }
 }
 
-// One sweep on L.S[0] (R starts as I in L.R[0]); returns the buffer holding the result (the
-// parity of the step count).  Thread t owns the 2 x 2 blocks (pair a = t / 16 rows, pair
-// b = t % 16 columns) and computes the two rotations it applies itself (the same arithmetic
-// on the same entries as any other thread that needs them, so no lane exchange); every
-// thread reads the current buffer and writes its block of the other one, so a step needs a
-// single barrier.
+// One sweep on L.S[0] (R starts as I in L.R[0]); returns the buffer of S holding the result
+// (the parity of the step count; R ends in L.R[0]).  Thread t owns the 2 x 2 blocks (pair
+// a = t / 16 rows, pair b = t % 16 columns) and computes the two rotations it applies itself
+// (the same arithmetic on the same entries as any other thread that needs them, so no lane
+// exchange); every thread reads the current S buffer and writes its block of the other one,
+// and rotates its block of R in place, so a step needs a single barrier.
 template <class T>
 __device__ int subproblem_sweep(SolveLds<T>& L, T thr, T eps, bool full) {
   const int t = threadIdx.x;
@@ -196,8 +199,8 @@ __device__ int subproblem_sweep(SolveLds<T>& L, T thr, T eps, bool full) {
     rot_params(L.S[cur][p1][p1], L.S[cur][q1][q1], L.S[cur][p1][q1], thr, eps, cb, sb);
     const T m00 = L.S[cur][p0][p1], m01 = L.S[cur][p0][q1];
     const T m10 = L.S[cur][q0][p1], m11 = L.S[cur][q0][q1];
-    const T r00 = L.R[cur][p0][p1], r01 = L.R[cur][p0][q1];
-    const T r10 = L.R[cur][q0][p1], r11 = L.R[cur][q0][q1];
+    const T r00 = L.R[0][p0][p1], r01 = L.R[0][p0][q1];
+    const T r10 = L.R[0][q0][p1], r11 = L.R[0][q0][q1];
     // G_a^T M G_b and R G_b
     const T x00 = ca * m00 - sa * m10, x01 = ca * m01 - sa * m11;
     const T x10 = sa * m00 + ca * m10, x11 = sa * m01 + ca * m11;
@@ -205,10 +208,10 @@ __device__ int subproblem_sweep(SolveLds<T>& L, T thr, T eps, bool full) {
     L.S[nxt][p0][q1] = x00 * sb + x01 * cb;
     L.S[nxt][q0][p1] = x10 * cb - x11 * sb;
     L.S[nxt][q0][q1] = x10 * sb + x11 * cb;
-    L.R[nxt][p0][p1] = r00 * cb - r01 * sb;
-    L.R[nxt][p0][q1] = r00 * sb + r01 * cb;
-    L.R[nxt][q0][p1] = r10 * cb - r11 * sb;
-    L.R[nxt][q0][q1] = r10 * sb + r11 * cb;
+    L.R[0][p0][p1] = r00 * cb - r01 * sb;
+    L.R[0][p0][q1] = r00 * sb + r01 * cb;
+    L.R[0][q0][p1] = r10 * cb - r11 * sb;
+    L.R[0][q0][q1] = r10 * sb + r11 * cb;
     __syncthreads();
   }
   return steps & 1;
@@ -232,9 +235,6 @@ __device__ void solve_pair(SolveLds<T>& L, int pp, int np, const T* __restrict__
     return;
   }
   const int nI = pn[2 * j], nJ = pn[2 * j + 1];
-  T (&X)[SB][LDS_PAD] = L.S[1];
-  T (&RA)[SB][LDS_PAD] = L.R[1];
-  T (&RB)[SB][LDS_PAD] = L.R[0];
   if (t == 0) L.any = 0;
   if (!Rc) {
     for (int e = t; e < SB * SB; e += NTJ) {
@@ -281,6 +281,9 @@ __device__ void solve_pair(SolveLds<T>& L, int pp, int np, const T* __restrict__
 #pragma unroll
       for (int i = 0; i < 4; ++i) L.S[0][HB * h1 + 4 * i + lk][HB * h2 + lr] = sb[i];
     } else {
+      T (&X)[SB][LDS_PAD] = L.S[1];
+      T (&RA)[SB][LDS_PAD] = L.R[1];
+      T (&RB)[SB][LDS_PAD] = L.R[0];
       // all four blocks of the current matrix and both rotations, loaded at once (thread t
       // owns elements t + 256 q)
       T xr[4][4], ra[4], rb[4];
@@ -318,7 +321,7 @@ __device__ void solve_pair(SolveLds<T>& L, int pp, int np, const T* __restrict__
         T y0 = T(0), y1 = T(0);
         // partial unrolling: fully unrolled, these two loops held their LDS operands in
         // registers and took the round kernel to 124 VGPRs (four waves per SIMD); at 8 it
-        // needs 64, which leaves room for seven binary32 round workgroups per CU
+        // needs under 64, which leaves room for eight binary32 round workgroups per CU
 #pragma unroll 8
         for (int k = 0; k < SB; ++k) {
           const T x = X[yi][k];
@@ -344,9 +347,9 @@ __device__ void solve_pair(SolveLds<T>& L, int pp, int np, const T* __restrict__
     L.R[0][i][k] = (i == k) ? T(1) : T(0);
   }
   __syncthreads();
-  const int res = subproblem_sweep(L, thr, eps, full);
+  subproblem_sweep(L, thr, eps, full);
   T* Ro = Rn + (long)j * SB * SB;
-  for (int e = t; e < SB * SB; e += NTJ) Ro[e] = L.R[res][e / SB][e % SB];
+  for (int e = t; e < SB * SB; e += NTJ) Ro[e] = L.R[0][e / SB][e % SB];
   if (t == 0 && L.any) atomicAdd(applied, 1);
 }
 
@@ -422,7 +425,7 @@ __device__ inline void load_item(const Item& it, int pp, const int* __restrict__
 }
 
 template <class T>
-__global__ __launch_bounds__(NTJ) void jac_round(int pp, int np, const T* __restrict__ Ain,
+__global__ __launch_bounds__(NTJ, sizeof(T) == 8 ? 5 : 1) void jac_round(int pp, int np, const T* __restrict__ Ain,
                                                  T* __restrict__ Aout, T* __restrict__ V,
                                                  const int* __restrict__ pc,
                                                  const int* __restrict__ mc,
@@ -445,8 +448,8 @@ __global__ __launch_bounds__(NTJ) void jac_round(int pp, int np, const T* __rest
   if (item >= nitems) return;
   T (&M)[SB][LDS_PAD] = L.S[1];
   T (&RQ)[SB][LDS_PAD] = L.S[0];
-  T (&RP)[SB][LDS_PAD] = L.R[1];
-  T (&T1)[SB][LDS_PAD] = L.R[0];
+  T (&RP)[SB][LDS_PAD] = L.R[0];
+  T (&T1)[SB][LDS_PAD] = L.S[0];  // the first product's result replaces RQ
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
   const int ti = wave >> 1, tj = wave & 1;
@@ -483,6 +486,7 @@ __global__ __launch_bounds__(NTJ) void jac_round(int pp, int np, const T* __rest
       }
     } else {
       const int pI = pc[2 * cur.P], pJ = pc[2 * cur.P + 1];
+      __syncthreads();  // every wave has read RQ
 #pragma unroll
       for (int i = 0; i < 4; ++i) T1[16 * ti + M4::row(i, lk)][16 * tj + lr] = acc[i];
       __syncthreads();
@@ -708,10 +712,10 @@ int syev_t(hipStream_t s, int p, const double* H, long ldh, double* w, double* V
   const double total = host[1];
   int cur = 0, rc = 0;  // A in Aw[cur], rotations of the next round in Rb[rc]
   bool solved = false;
-  // update workers: about as many as fit on the chip next to the solves (4 round workgroups
-  // per CU in FP64, bound by LDS; 7 in binary32, bound by registers)
+  // update workers: about as many as fit on the chip next to the solves (6 round workgroups
+  // per CU in FP64, bound by LDS; 8 in binary32, bound by registers)
   const int nitems = np * (np + 1) / 2 + np * (pp / SB);
-  const int per_cu = sizeof(T) == 4 ? 7 : 4;
+  const int per_cu = sizeof(T) == 4 ? 8 : 6;
   const int nw = std::min(nitems, std::max(256, per_cu * 256 - np));
   while (sweep < max_sweeps && np > 0) {
     if (host[0] <= tol_rel * tol_rel * total) break;
