@@ -144,9 +144,10 @@ __device__ inline long sidx(int r, int c, int pp) {
   return (r / HB <= c / HB) ? (long)r * pp + c : (long)c * pp + r;
 }
 
-// LDS of a round workgroup (four 32 x 32 buffers, so four workgroups fit on a CU).  A solve
-// uses S[0..1] and R[0..1] for the sweep and, while it forms its subproblem, S[1] / R[1] /
-// R[0] as staging (X / RA / RB); an update workgroup uses all four for its operands.
+// LDS of a round workgroup: 32 x 32 buffers, three in FP64 (six workgroups fit on a CU) and
+// four in binary32.  A solve uses S[0..1] and R[0] for the sweep and, while it forms a binary32
+// subproblem, S[1] / R[1] / R[0] as staging (X / RA / RB); an update workgroup uses S[1],
+// S[0] and R[0] for its operands (M, RQ, RP).
 template <class T>
 struct SolveLds {
   T S[2][SB][LDS_PAD];  // subproblem, double-buffered by step parity
